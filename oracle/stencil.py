@@ -1,0 +1,66 @@
+"""In-place diffusion loop and its reverse pass, in FP64.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Forward (a `State` loop, Sec. 2.3.1): `for t:(Fin T). u := step (get u)` with the
+periodic five-point update
+
+    step(u)[y, x] = u[y, x] + c * (u[y+1, x] + u[y-1, x] + u[y, x+1] + u[y, x-1]
+                                   - 4 u[y, x]),       c = 0.2,
+
+indices taken modulo the grid. `get` returns an immutable value (Sec. 5.3.2), so
+every read in a step is of the previous field (a Jacobi update).
+Loss: L = 1/2 * || u_T - target ||^2.
+
+Reverse: the transposed loop. ForTranspose runs the time loop backwards; the
+cotangent of u_T is u_T - target; GetTranspose / PutTranspose carry the
+cotangent of the state reference through each step, and the transpose of one
+step turns each of its five reads into an accumulation into the cotangent of
+the cell that was read (LetIndexingTranspose). The step is linear, so nothing
+of the primal needs to be saved (only non-linear operations keep their inputs,
+Sec. 5.3.2).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+C = 0.2
+
+
+def step(u: np.ndarray, c: float = C) -> np.ndarray:
+    u = np.asarray(u, dtype=np.float64)
+    nb = (np.roll(u, -1, 0) + np.roll(u, 1, 0) + np.roll(u, -1, 1) + np.roll(u, 1, 1))
+    return u + c * (nb - 4.0 * u)
+
+
+def step_transpose(ct_next: np.ndarray, c: float = C) -> np.ndarray:
+    """Cotangent of u_t from the cotangent of u_{t+1}, written as accumulation:
+    the forward cell (y, x) read u[y, x] with weight (1 - 4c) and its four
+    neighbours with weight c, so it adds those weights times ct_next[y, x]
+    into the corresponding cells of the result."""
+    g = np.asarray(ct_next, dtype=np.float64)
+    acc = np.zeros_like(g)
+    acc += (1.0 - 4.0 * c) * g            # read of u[y, x]
+    acc += c * np.roll(g, 1, 0)           # read of u[y+1, x] by cell (y, x): lands at y+1
+    acc += c * np.roll(g, -1, 0)          # read of u[y-1, x]
+    acc += c * np.roll(g, 1, 1)           # read of u[y, x+1]
+    acc += c * np.roll(g, -1, 1)          # read of u[y, x-1]
+    return acc
+
+
+def forward(u0: np.ndarray, steps: int, c: float = C) -> np.ndarray:
+    u = np.asarray(u0, dtype=np.float64)
+    for _ in range(steps):
+        u = step(u, c)
+    return u
+
+
+def loss_and_grad(u0: np.ndarray, target: np.ndarray, steps: int, c: float = C):
+    """Returns (L, u_T, dL/du0)."""
+    uT = forward(u0, steps, c)
+    r = uT - np.asarray(target, dtype=np.float64)
+    L = 0.5 * float(np.sum(r * r))
+    lam = r
+    for _ in range(steps):                 # ForTranspose: t = T-1 ... 0
+        lam = step_transpose(lam, c)
+    return L, uT, lam
