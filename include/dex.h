@@ -1,0 +1,294 @@
+/*
+ * dex.h -- C ABI of libdexmi, the MI355X (gfx950) reverse-mode path for
+ * pointful, index-set-typed loops.
+ *
+ * Paper: "Getting to the Point. Index Sets and Parallelism-Preserving Autodiff
+ * for Pointful Array Programming" (arXiv 2104.05372).
+ *
+ * The calls follow the paper's statement of the problem:
+ *   linearize : (a -> b) -> a -> (b, a -o b)            (Sec. 5.1)
+ *   transpose : (a -o b) -> (b -o a)                     (Sec. 5.2)
+ *   grad f x  = transpose (snd (linearize f x)) 1.0      (Sec. 5.2)
+ *   (+=)      : Ref h w -> w -> {Accum h} Unit, runAccum (Sec. 2.3.2)
+ *   (!)       : Ref h (n=>a) -> n -> Ref h a             (Sec. 2.3.3)
+ *
+ *   dex_fwd            = the primal half of `linearize f x`: the output and the
+ *                        residuals the linear map closes over.
+ *   dex_vjp            = `transpose (snd (linearize f x)) ct`.
+ *   dex_accum_scatter  = `runAccum \acc. for j. acc!(idx.j) += scale.j * vals.j`.
+ *
+ * General rules for every entry point
+ *   - Pointers named *_dev, and every dex_buf.ptr, are device pointers on the
+ *     current HIP device, owned by the caller. dex_fwd, dex_vjp and
+ *     dex_accum_scatter never allocate device memory; scratch comes from the
+ *     caller's `workspace` (size from dex_workspace_bytes /
+ *     dex_accum_scatter_workspace_bytes).
+ *   - Work is enqueued on `hip_stream` (a hipStream_t; NULL = default stream)
+ *     and the call returns after the launches. Argument errors are detected on
+ *     the host and returned before anything is enqueued. A failed launch
+ *     returns DEX_ERR_HIP. dex_last_error() gives a message for the last
+ *     non-OK status on the calling thread.
+ *   - Arrays are dense, row-major, with no padding (the flat unboxed layout of
+ *     Sec. 6.3). Float arrays of a descriptor share its `dtype`.
+ *   - A device that is not gfx950 gives DEX_ERR_UNSUPPORTED.
+ */
+#ifndef DEX_H
+#define DEX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dex_status;
+#define DEX_OK                0
+#define DEX_ERR_INVALID_ARG  (-1) /* null pointer, bad size, dtype mismatch */
+#define DEX_ERR_OUT_OF_RANGE (-2) /* DEX_SYNC_CHECK found an index outside its set */
+#define DEX_ERR_UNSUPPORTED  (-3) /* kind/dtype/variant/shape not built, or not gfx950 */
+#define DEX_ERR_HIP          (-4) /* a HIP runtime call or launch failed */
+#define DEX_ERR_WORKSPACE    (-5) /* workspace missing or smaller than required */
+
+/* element types */
+#define DEX_F64 1
+#define DEX_F32 2
+#define DEX_I32 3
+#define DEX_U32 4
+#define DEX_I64 5
+#define DEX_U8  6
+
+/* function kinds (dex_desc.kind) */
+#define DEX_GMM          1 /* GMM log-likelihood, one instance            */
+#define DEX_GMM_BATCHED  2 /* many independent GMM instances, one launch  */
+#define DEX_GATHER_SCALE 3 /* out[j,:] = w[j] * T[idx[j],:]                */
+#define DEX_STENCIL5     4 /* in-place periodic 5-point diffusion loop     */
+
+/* GMM arithmetic variants (dex_desc.variant) */
+#define DEX_GMM_PLAIN  0 /* every product and sum in the descriptor dtype            */
+#define DEX_GMM_BF16   1 /* Q_k (x_i - mu_k) and the weighted outer products as BF16
+                            MFMA with FP32 accumulation; FP32 storage only          */
+#define DEX_GMM_BF16X3 2 /* split-BF16 operands, hi*hi + hi*lo + lo*hi per product   */
+
+/* stencil variants */
+#define DEX_STENCIL_RECOMPUTE 0 /* reverse pass recomputes each checkpoint segment */
+#define DEX_STENCIL_LINEAR    1 /* reverse pass uses no primal state (step linear) */
+
+/* flags */
+#define DEX_ACCUMULATE   1u /* dex_vjp: ct_in += result (VarTranspose); else ct_in = result */
+#define DEX_CHECK_BOUNDS 2u /* count indices outside [0, n_rows) into *oob_count_dev
+                               (int64, added to) and skip them                        */
+#define DEX_SYNC_CHECK   4u /* with DEX_CHECK_BOUNDS: wait for the stream and return
+                               DEX_ERR_OUT_OF_RANGE if this call found any           */
+#define DEX_NO_DW        8u /* DEX_GATHER_SCALE dex_vjp: skip the cotangent of w      */
+
+/* workspace roles for dex_workspace_bytes */
+#define DEX_WS_FWD   0 /* scratch for dex_fwd                           */
+#define DEX_WS_VJP   1 /* scratch for dex_vjp                           */
+#define DEX_WS_RESID 2 /* bytes of the second (operand-cache) residual  */
+
+/*
+ * Descriptor of the function being differentiated.
+ *   kind     DEX_GMM | DEX_GMM_BATCHED | DEX_GATHER_SCALE | DEX_STENCIL5
+ *   dtype    DEX_F64 or DEX_F32: storage type of all float buffers
+ *   variant  arithmetic variant (see above), 0 for kinds without variants
+ *   config   0 = tuned or default tile configuration; c > 0 forces candidate c
+ *            (see dex_num_configs); used by the autotuner and by tests
+ *   dims     DEX_GMM:          {N, D, K}
+ *            DEX_GMM_BATCHED:  filled by dex_gmm_batched_plan
+ *            DEX_GATHER_SCALE: {V (rows of T), R (row length), n (indices)}
+ *            DEX_STENCIL5:     {H, W, steps, every (checkpoint interval)}
+ *   fparams  DEX_STENCIL5: {c (diffusion weight), rho (weight of the
+ *            non-linear term rho*sin(u); 0 for the pure diffusion loop)}
+ */
+typedef struct dex_desc {
+  int32_t kind;
+  int32_t dtype;
+  int32_t variant;
+  int32_t config;
+  int64_t dims[8];
+  double fparams[4];
+} dex_desc;
+
+/* A device array: ptr (may be NULL only when numel == 0), element count, dtype. */
+typedef struct dex_buf {
+  void* ptr;
+  int64_t numel;
+  int32_t dtype;
+  int32_t reserved;
+} dex_buf;
+
+/*
+ * Buffer lists per kind (in / out / resid / ct_out / ct_in, in this order):
+ *
+ * DEX_GMM (dims {N, D, K}, L = D(D-1)/2). Objective, with
+ *   Q_k = diag(exp(qd[k])) + strict-lower(l[k]), Q_k[a,b] (a > b) at l[k, a(a-1)/2 + b]:
+ *     beta[i,k] = alphas[k] + sum_d qd[k,d] - 1/2 || Q_k (x[i] - means[k]) ||^2
+ *     f[i]      = logsumexp_k beta[i,k]                (max-shifted)
+ *     F         = sum_i f[i] - N logsumexp_k alphas[k]
+ *   in     = alphas[K], means[K*D], qd[K*D], l[K*L], x[N*D]
+ *   out    = F[1]
+ *   resid  = f[N] (dtype), cache[DEX_WS_RESID bytes, DEX_U8] (may be numel 0
+ *            when DEX_WS_RESID is 0)
+ *   ct_out = dF[1] (device scalar)
+ *   ct_in  = d_alphas[K], d_means[K*D], d_qd[K*D], d_l[K*L]
+ *   The reverse pass is the transposed loop: for the reads of alphas.k, means.k
+ *   and Q.k inside `for i k` (rule LetIndexingTranspose, Fig. "transposition
+ *   rules"), each cotangent is a regular segmented reduction over i
+ *   (Sec. 6.1.3), done as per-block partial sums and a fixed-order compensated
+ *   final sum (so the result does not depend on scheduling).
+ *
+ * DEX_GMM_BATCHED (dims from dex_gmm_batched_plan; FP32, variant PLAIN):
+ *   in     = plan[bytes, DEX_U8, device copy of the plan], alphas, means, qd, l, x
+ *            (instances concatenated in order; instance b's arrays have the
+ *            DEX_GMM sizes of its (N_b, D_b, K_b))
+ *   out    = F[B];  resid = f[sum N_b];  ct_out = dF[B]
+ *   ct_in  = d_alphas, d_means, d_qd, d_l (packed like the inputs)
+ *
+ * DEX_GATHER_SCALE (dims {V, R, n}; FP32):
+ *   in     = T[V*R], idx[n] (DEX_I32), w[n]
+ *   out    = out[n*R];  resid = none;  ct_out = g[n*R]
+ *   ct_in  = dT[V*R], dw[n] (dw may be numel 0 with DEX_NO_DW)
+ *   dT is the transposed gather: dT!(idx.j) += w.j * g.j (Sec. 5.3.3).
+ *
+ * DEX_STENCIL5 (dims {H, W, steps, every}; FP32): the State loop
+ *     for t in 0..steps-1:  u := u + c (u[y+1,x]+u[y-1,x]+u[y,x+1]+u[y,x-1]-4u) + rho sin(u)
+ *   (periodic; each step reads only the previous field), then
+ *     L = 1/2 || u_T - target ||^2.
+ *   in     = u0[H*W], target[H*W]
+ *   out    = L[1], uT[H*W]
+ *   resid  = checkpoints[ceil(steps/every) * H*W]  (u_0, u_every, u_2every, ...)
+ *   ct_out = dL[1] (device scalar)
+ *   ct_in  = du0[H*W]
+ *   The reverse pass runs the time loop backwards (ForTranspose); with
+ *   DEX_STENCIL_RECOMPUTE it rebuilds each segment's states from its
+ *   checkpoint first (only non-linear terms read them, Sec. 5.3.2).
+ */
+
+/* Message for a status code (static storage). */
+const char* dex_status_string(dex_status s);
+
+/* Message describing the last non-OK status returned on this thread. */
+const char* dex_last_error(void);
+
+/* Library version string, e.g. "dexmi 0.1 gfx950". */
+const char* dex_version(void);
+
+/* Check the current device (must be gfx950) and set up per-device state.
+ * Called implicitly by every entry point; safe to call repeatedly. */
+dex_status dex_init(void);
+
+/* Bytes of caller-provided scratch that `role` (DEX_WS_*) needs for `d`. */
+dex_status dex_workspace_bytes(const dex_desc* d, int32_t role, size_t* bytes);
+
+/* Number of tile configurations that `config` may select for (d, role). */
+dex_status dex_num_configs(const dex_desc* d, int32_t role, int32_t* count);
+
+/* Forward: out = f(in) and the residuals for dex_vjp. */
+dex_status dex_fwd(const dex_desc* d,
+                   const dex_buf* in, int32_t n_in,
+                   dex_buf* out, int32_t n_out,
+                   dex_buf* resid, int32_t n_resid,
+                   void* workspace, size_t ws_bytes,
+                   void* hip_stream);
+
+/* Reverse: ct_in (=|+=) transpose(linearize f in) applied to ct_out.
+ * `resid` must come from dex_fwd with an identical descriptor and inputs. */
+dex_status dex_vjp(const dex_desc* d,
+                   const dex_buf* in, int32_t n_in,
+                   const dex_buf* resid, int32_t n_resid,
+                   const dex_buf* ct_out, int32_t n_ct_out,
+                   dex_buf* ct_in, int32_t n_ct_in,
+                   uint32_t flags,
+                   void* workspace, size_t ws_bytes,
+                   void* hip_stream);
+
+/*
+ * acc!(idx[j]) += scale[j] * vals[j, :]  for j in [0, n)      (Sec. 2.3.2-2.3.3)
+ *
+ *   acc        device, n_rows x row_len, DEX_F32 or DEX_I32; accumulated into,
+ *              never overwritten; not to be read until the stream reaches the
+ *              end of this call (the write-only Ref of `runAccum`).
+ *   idx        device, n entries, DEX_I32 or DEX_U32.
+ *   vals       device, n x row_len of acc's type, or NULL meaning all ones.
+ *   scale      device, n floats, or NULL meaning all ones (DEX_F32 only).
+ *   flags      DEX_CHECK_BOUNDS / DEX_SYNC_CHECK. Without DEX_CHECK_BOUNDS an
+ *              out-of-range index is still skipped (never written), but not counted.
+ *   oob_count_dev  device int64, required with DEX_CHECK_BOUNDS; the number of
+ *              out-of-range indices is added to it.
+ * Integer accumulation is exact, hence identical under every schedule. Float
+ * accumulation is associative only up to rounding (Sec. 2.3.2): duplicate
+ * indices are first summed in registers/LDS within a block, then added with
+ * global atomics, so the rounding order is unspecified.
+ * Integer with row_len == 1, vals == NULL and n_rows <= 65536 is the
+ * histogram of Sec. 6.1.2 and uses LDS-private counters.
+ */
+dex_status dex_accum_scatter(void* acc, int32_t acc_dtype, int64_t n_rows, int64_t row_len,
+                             const void* idx, int32_t idx_dtype,
+                             const void* vals, const float* scale, int64_t n,
+                             uint32_t flags, int64_t* oob_count_dev,
+                             void* workspace, size_t ws_bytes,
+                             void* hip_stream);
+
+/* Scratch bytes that dex_accum_scatter needs for these arguments. */
+dex_status dex_accum_scatter_workspace_bytes(int32_t acc_dtype, int64_t n_rows,
+                                             int64_t row_len, int64_t n, int32_t has_vals,
+                                             size_t* bytes);
+
+/*
+ * Host-side plan for DEX_GMM_BATCHED. `shapes` is host memory, B rows of
+ * (N, D, K) int64 with D in {8, 16, 32}, N >= 1, K >= 1. Fills *desc_out and
+ * writes the plan (instance table and work lists, longest work first) into
+ * host memory `plan` of *plan_bytes bytes. Call with plan == NULL to query
+ * *plan_bytes. The caller copies the plan to the device and passes it as in[0].
+ */
+dex_status dex_gmm_batched_plan(const int64_t* shapes, int64_t B, int32_t variant,
+                                dex_desc* desc_out, void* plan, size_t* plan_bytes);
+
+/*
+ * Autotuner: times every tile configuration of (d, role) on the caller's
+ * buffers (arguments as for dex_fwd / dex_vjp) with HIP events, keeps the
+ * fastest for the descriptor's shape class in a process-wide table that
+ * dex_fwd / dex_vjp consult when d->config == 0, and returns it in *best.
+ * The buffers' contents are overwritten. Enqueues on hip_stream and waits.
+ */
+dex_status dex_autotune(const dex_desc* d, int32_t role,
+                        const dex_buf* in, int32_t n_in,
+                        dex_buf* out, int32_t n_out,
+                        dex_buf* resid, int32_t n_resid,
+                        const dex_buf* ct_out, int32_t n_ct_out,
+                        dex_buf* ct_in, int32_t n_ct_in,
+                        void* workspace, size_t ws_bytes,
+                        void* hip_stream, int32_t* best);
+
+/* Drop every tuned configuration (the process-wide table). */
+void dex_autotune_reset(void);
+
+/*
+ * Live kernel timing. When enabled, the library records a pair of HIP events on
+ * the launching stream around each launch (or launch sequence) of the main
+ * kernel of a path, identified as below; dex_profile_read waits for the
+ * recorded events and returns their summed duration and the number of kernel
+ * launches they cover. Disabled by default; enabling adds two event records
+ * per covered launch.
+ */
+#define DEX_PROF_GMM_FWD      0 /* matrix-core forward tile kernel            */
+#define DEX_PROF_GMM_VJP      1 /* matrix-core reverse tile kernel            */
+#define DEX_PROF_SCATTER      2 /* float row scatter (sort + segmented sum)   */
+#define DEX_PROF_HIST         3 /* LDS-private histogram kernel               */
+#define DEX_PROF_GATHER       4 /* gather-scale forward                       */
+#define DEX_PROF_GATHER_DW    5 /* cotangent of the gather weights            */
+#define DEX_PROF_BGMM_FWD     6 /* batched forward persistent kernel          */
+#define DEX_PROF_BGMM_VJP     7 /* batched reverse persistent kernel          */
+#define DEX_PROF_STENCIL_FWD  8 /* forward steps (one range per dex_fwd)      */
+#define DEX_PROF_STENCIL_VJP  9 /* reverse steps incl. recompute (per dex_vjp) */
+#define DEX_PROF_COUNT       10
+void dex_profile_enable(int32_t on);
+dex_status dex_profile_read(int32_t id, double* total_ms, int64_t* launches);
+void dex_profile_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEX_H */

@@ -1,0 +1,469 @@
+// GMM log-likelihood, one instance: host dispatch, the VALU forms (FP64 or
+// FP32, one thread per point) and the merge / finalize kernels shared with the
+// matrix-core forms (gmm_dev.h, gmm_mfma_inst.hip).
+#include "gmm_host.h"
+#include "internal.h"
+
+namespace dexk {
+
+// Forward, VALU: one thread per point, D <= DB. beta is stored [K][N].
+template <typename T, int DB>
+__global__ void __launch_bounds__(256) gmm_fwd_valu(const T* __restrict__ alphas,
+                                                    const T* __restrict__ means,
+                                                    const T* __restrict__ qd,
+                                                    const T* __restrict__ l,
+                                                    const T* __restrict__ x, int N, int D, int K,
+                                                    T* __restrict__ beta, T* __restrict__ f,
+                                                    T* __restrict__ fpart) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  const bool valid = p < N;
+  const int L = D * (D - 1) / 2;
+  T xr[DB];
+#pragma unroll
+  for (int b = 0; b < DB; ++b) xr[b] = (valid && b < D) ? x[(size_t)p * D + b] : T(0);
+  T m = -INFINITY, ls = 0;
+  for (int k = 0; k < K; ++k) {
+    T r[DB];
+    T kap = alphas[k];
+#pragma unroll
+    for (int b = 0; b < DB; ++b) {
+      if (b < D) {
+        r[b] = xr[b] - means[(size_t)k * D + b];
+        kap += qd[(size_t)k * D + b];
+      } else {
+        r[b] = 0;
+      }
+    }
+    T s = 0;
+#pragma unroll
+    for (int a = 0; a < DB; ++a) {
+      if (a < D) {
+        T y = dexp<T>(qd[(size_t)k * D + a]) * r[a];
+#pragma unroll
+        for (int b = 0; b < a; ++b) y += l[(size_t)k * L + a * (a - 1) / 2 + b] * r[b];
+        s += y * y;
+      }
+    }
+    const T bv = kap - T(0.5) * s;
+    if (valid) beta[(size_t)k * N + p] = bv;
+    const T d = bv - m;
+    if (d > 0) {
+      ls = ls * dexp<T>(-d) + 1;
+      m = bv;
+    } else {
+      ls += dexp<T>(d);
+    }
+  }
+  T v = 0;
+  if (valid) {
+    v = m + dlog<T>(ls);
+    f[p] = v;
+  }
+  T s = 0, e = 0;
+  block_comp_sum<T>(v, s, e);
+  if (threadIdx.x == 0) {
+    fpart[2 * blockIdx.x] = s;
+    fpart[2 * blockIdx.x + 1] = e;
+  }
+}
+
+// Reverse, VALU: block (k, point chunk), 64-point tiles. Threads 0..63 put
+// w y and r of one point each in LDS; then every thread accumulates its share
+// of the D(D+1)/2 + D + 1 sums over the tile.
+template <typename T, int DB>
+__global__ void __launch_bounds__(256) gmm_bwd_valu(const T* __restrict__ means,
+                                                    const T* __restrict__ qd,
+                                                    const T* __restrict__ l,
+                                                    const T* __restrict__ x, int N, int D, int K,
+                                                    int chunk_pts, const T* __restrict__ beta,
+                                                    const T* __restrict__ f,
+                                                    const T* __restrict__ ct,
+                                                    T* __restrict__ part) {
+  constexpr int MAXE = (DB * (DB + 1) / 2 + DB + 1 + 255) / 256;
+  __shared__ T wy[64][DB + 1], rr[64][DB + 1], wsh[64];
+  const int k = blockIdx.x;
+  const int L = D * (D - 1) / 2;
+  const int nM = D * (D + 1) / 2, nE = nM + D + 1;
+  const int pbeg = blockIdx.y * chunk_pts, pend = min(N, pbeg + chunk_pts);
+  const T ctv = ct[0];
+  int ea[MAXE], eb[MAXE], kind[MAXE];
+  T acc[MAXE];
+#pragma unroll
+  for (int q = 0; q < MAXE; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    acc[q] = 0;
+    kind[q] = 3;
+    ea[q] = eb[q] = 0;
+    if (e < nM) {
+      int a = 0;
+      while ((a + 1) * (a + 2) / 2 <= e) ++a;
+      ea[q] = a;
+      eb[q] = e - a * (a + 1) / 2;
+      kind[q] = 0;
+    } else if (e < nM + D) {
+      ea[q] = e - nM;
+      kind[q] = 1;
+    } else if (e < nE) {
+      kind[q] = 2;
+    }
+  }
+  for (int t0 = pbeg; t0 < pend; t0 += 64) {
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int p = t0 + threadIdx.x;
+      const bool valid = p < pend;
+      T r[DB];
+      T w = 0;
+#pragma unroll
+      for (int b = 0; b < DB; ++b)
+        r[b] = (valid && b < D) ? x[(size_t)p * D + b] - means[(size_t)k * D + b] : T(0);
+      if (valid) w = dexp<T>(beta[(size_t)k * N + p] - f[p]) * ctv;
+#pragma unroll
+      for (int a = 0; a < DB; ++a) {
+        if (a < D) {
+          T y = dexp<T>(qd[(size_t)k * D + a]) * r[a];
+#pragma unroll
+          for (int b = 0; b < a; ++b) y += l[(size_t)k * L + a * (a - 1) / 2 + b] * r[b];
+          wy[threadIdx.x][a] = w * y;
+          rr[threadIdx.x][a] = r[a];
+        }
+      }
+      wsh[threadIdx.x] = w;
+    }
+    __syncthreads();
+    const int np = min(64, pend - t0);
+#pragma unroll
+    for (int q = 0; q < MAXE; ++q) {
+      if (kind[q] == 0) {
+        for (int pp = 0; pp < np; ++pp) acc[q] += wy[pp][ea[q]] * rr[pp][eb[q]];
+      } else if (kind[q] == 1) {
+        for (int pp = 0; pp < np; ++pp) acc[q] += wy[pp][ea[q]];
+      } else if (kind[q] == 2) {
+        for (int pp = 0; pp < np; ++pp) acc[q] += wsh[pp];
+      }
+    }
+  }
+  T* P = part + ((size_t)blockIdx.y * K + k) * ((size_t)D * D + D + 1);
+#pragma unroll
+  for (int q = 0; q < MAXE; ++q) {
+    if (kind[q] == 0)
+      P[(size_t)ea[q] * D + eb[q]] = acc[q];
+    else if (kind[q] == 1)
+      P[(size_t)D * D + ea[q]] = acc[q];
+    else if (kind[q] == 2)
+      P[(size_t)D * D + D] = acc[q];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_merge_lse(const float2* __restrict__ ml, int Sk, int N,
+                                                   int Npad, T* __restrict__ f,
+                                                   T* __restrict__ fpart) {
+  T s = 0, e = 0;
+  merge_lse_block<T>(ml, Sk, N, Npad, blockIdx.x * 256, f, s, e);
+  if (threadIdx.x == 0) {
+    fpart[2 * blockIdx.x] = s;
+    fpart[2 * blockIdx.x + 1] = e;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_finalize_F(const T* __restrict__ fpart, int nparts,
+                                                    const T* __restrict__ alphas, int K, int64_t N,
+                                                    T* __restrict__ F) {
+  finalize_F_block<T>(fpart, nparts, alphas, K, N, F);
+}
+
+template <typename T, typename TP>
+__global__ void __launch_bounds__(256) k_bwd_finalize(const TP* __restrict__ part, size_t E, int S,
+                                                      int K, int D, int ld, int64_t N,
+                                                      const T* __restrict__ alphas,
+                                                      const T* __restrict__ qd,
+                                                      const T* __restrict__ l,
+                                                      const T* __restrict__ ct,
+                                                      T* __restrict__ d_alphas,
+                                                      T* __restrict__ d_means, T* __restrict__ d_qd,
+                                                      T* __restrict__ d_l, int accumulate) {
+  const int k = blockIdx.x;
+  bwd_finalize_comp<T, TP>(part + (size_t)k * E, (size_t)K * E, S, k, K, D, ld, N, alphas, qd, l,
+                           ct[0], d_alphas, d_means, d_qd, d_l, accumulate);
+}
+
+}  // namespace dexk
+
+// ===========================================================================
+namespace dexi {
+using namespace dexk;
+
+namespace {
+
+struct Shape {
+  GmmGeom g;
+  int dtype, variant, prec;
+  bool mfma;
+  size_t tsize;
+};
+
+Shape shape_of(const dex_desc& d) {
+  Shape s{};
+  s.g.N = d.dims[0];
+  s.g.D = d.dims[1];
+  s.g.K = d.dims[2];
+  s.g.DP = s.g.D <= 16 ? 16 : s.g.D <= 32 ? 32 : 64;
+  s.g.Npad = (s.g.N + 255) / 256 * 256;
+  s.dtype = d.dtype;
+  s.variant = d.variant;
+  s.tsize = d.dtype == DEX_F64 ? 8 : 4;
+  s.mfma = d.dtype == DEX_F32;
+  s.prec = d.variant == DEX_GMM_BF16 ? PREC_BF16 : d.variant == DEX_GMM_BF16X3 ? PREC_BF16X3 : PREC_F32;
+  return s;
+}
+
+// forward candidates: (points per wave / 16, k-splits, chunk depth)
+const FwdCfg kFwdBF[] = {{4, 1, 32}, {4, 2, 32}, {2, 1, 32}, {4, 1, 16}, {4, 2, 16}, {2, 2, 32}};
+const FwdCfg kFwdF32[] = {{4, 1, 16}, {4, 2, 16}, {2, 1, 16}, {2, 2, 16}};
+// reverse candidates: (points per tile / 16, components per wave, chunk depth, point chunks)
+const BwdCfg kBwdBF[] = {{4, 2, 32, 16}, {4, 1, 32, 16}, {2, 2, 32, 16}, {4, 2, 32, 32},
+                         {4, 1, 32, 32}, {4, 2, 16, 16}, {4, 1, 16, 32}, {4, 2, 32, 8}};
+const BwdCfg kBwdF32[] = {{4, 1, 16, 16}, {4, 2, 16, 16}, {2, 2, 16, 16}, {4, 1, 16, 32},
+                          {2, 2, 16, 32}};
+constexpr int kMaxSk = 2;
+constexpr int kMaxS = 32;
+constexpr int kValuS = 16;
+
+int nfwd(const Shape& s) { return s.prec == PREC_F32 ? 4 : 6; }
+int nbwd(const Shape& s) { return s.prec == PREC_F32 ? 5 : 8; }
+FwdCfg fwd_cfg(const Shape& s, int i) { return s.prec == PREC_F32 ? kFwdF32[i] : kFwdBF[i]; }
+BwdCfg bwd_cfg(const Shape& s, int i) { return s.prec == PREC_F32 ? kBwdF32[i] : kBwdBF[i]; }
+
+struct CacheLayout {
+  size_t xh, xl, xhT, xlT, Qh, Ql, negc, kappa, beta, total;
+};
+
+CacheLayout cache_layout(const Shape& s) {
+  CacheLayout c{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  const GmmGeom& g = s.g;
+  if (s.mfma) {
+    const size_t es = s.prec == PREC_F32 ? 4 : 2;
+    const bool lo = s.prec == PREC_BF16X3;
+    c.xh = take(g.Npad * g.DP * es);
+    c.xl = lo ? take(g.Npad * g.DP * es) : 0;
+    c.xhT = take(g.Npad * g.DP * es);
+    c.xlT = lo ? take(g.Npad * g.DP * es) : 0;
+    c.Qh = take(g.K * g.DP * g.DP * es);
+    c.Ql = lo ? take(g.K * g.DP * g.DP * es) : 0;
+    c.negc = take(g.K * g.DP * 4);
+    c.kappa = take(g.K * 4);
+    c.beta = take(g.K * g.Npad * 4);
+  } else {
+    c.beta = take(g.K * g.N * s.tsize);
+  }
+  c.total = o;
+  return c;
+}
+
+MfmaOps ops_of(const Shape& s, const CacheLayout& cl, const char* cache) {
+  MfmaOps o;
+  const bool lo = s.prec == PREC_BF16X3;
+  o.xh = cache + cl.xh;
+  o.xl = lo ? cache + cl.xl : nullptr;
+  o.xhT = cache + cl.xhT;
+  o.xlT = lo ? cache + cl.xlT : nullptr;
+  o.Qh = cache + cl.Qh;
+  o.Ql = lo ? cache + cl.Ql : nullptr;
+  o.negc = (const float*)(cache + cl.negc);
+  o.kappa = (const float*)(cache + cl.kappa);
+  return o;
+}
+
+template <typename T>
+void launch_fwd_valu(const Shape& s, const GmmPtrs& in, T* beta, T* f, T* fpart, hipStream_t st) {
+  dim3 grid((unsigned)((s.g.N + 255) / 256));
+#define DEX_FV(DB)                                                                         \
+  hipLaunchKernelGGL((gmm_fwd_valu<T, DB>), grid, dim3(256), 0, st, (const T*)in.alphas, \
+                     (const T*)in.means, (const T*)in.qd, (const T*)in.l, (const T*)in.x,  \
+                     (int)s.g.N, (int)s.g.D, (int)s.g.K, beta, f, fpart)
+  if (s.g.D <= 4)
+    DEX_FV(4);
+  else if (s.g.D <= 8)
+    DEX_FV(8);
+  else if (s.g.D <= 16)
+    DEX_FV(16);
+  else if (s.g.D <= 32)
+    DEX_FV(32);
+  else
+    DEX_FV(64);
+#undef DEX_FV
+}
+
+template <typename T>
+void launch_bwd_valu(const Shape& s, const GmmPtrs& in, const T* beta, const T* f, const T* ct,
+                     T* part, int chunk, hipStream_t st) {
+  dim3 grid((unsigned)s.g.K, (unsigned)((s.g.N + chunk - 1) / chunk));
+#define DEX_BV(DB)                                                                          \
+  hipLaunchKernelGGL((gmm_bwd_valu<T, DB>), grid, dim3(256), 0, st, (const T*)in.means,   \
+                     (const T*)in.qd, (const T*)in.l, (const T*)in.x, (int)s.g.N,         \
+                     (int)s.g.D, (int)s.g.K, chunk, beta, f, ct, part)
+  if (s.g.D <= 4)
+    DEX_BV(4);
+  else if (s.g.D <= 8)
+    DEX_BV(8);
+  else if (s.g.D <= 16)
+    DEX_BV(16);
+  else if (s.g.D <= 32)
+    DEX_BV(32);
+  else
+    DEX_BV(64);
+#undef DEX_BV
+}
+
+bool valid_shape(const Shape& s) {
+  const GmmGeom& g = s.g;
+  if (g.N < 1 || g.D < 1 || g.K < 1 || g.D > 64) return false;
+  if (s.dtype != DEX_F32 && s.dtype != DEX_F64) return false;
+  if (s.variant != DEX_GMM_PLAIN && s.dtype != DEX_F32) return false;
+  return true;
+}
+
+}  // namespace
+
+size_t gmm_cache_bytes(const dex_desc& d) {
+  Shape s = shape_of(d);
+  if (!valid_shape(s)) return 0;
+  return cache_layout(s).total;
+}
+
+size_t gmm_ws_bytes(const dex_desc& d, int role) {
+  Shape s = shape_of(d);
+  if (!valid_shape(s)) return 0;
+  if (role == DEX_WS_RESID) return cache_layout(s).total;
+  const size_t nblk = (size_t)(s.g.Npad / 256);
+  if (role == DEX_WS_FWD) {
+    size_t b = align256(nblk * 2 * s.tsize);
+    if (s.mfma) b += align256((size_t)kMaxSk * s.g.Npad * sizeof(float2));
+    return b;
+  }
+  if (s.mfma) return align256((size_t)kMaxS * s.g.K * bwd_slot(s.g.DP) * 4);
+  return align256((size_t)kValuS * s.g.K * (s.g.D * s.g.D + s.g.D + 1) * s.tsize);
+}
+
+int gmm_num_configs(const dex_desc& d, int role) {
+  Shape s = shape_of(d);
+  if (!s.mfma) return 1;
+  return role == DEX_WS_VJP ? nbwd(s) : nfwd(s);
+}
+
+dex_status gmm_fwd(const dex_desc& d, int cfg, const GmmPtrs& in, void* F, void* f, void* cache,
+                   void* ws, hipStream_t st) {
+  Shape s = shape_of(d);
+  if (!valid_shape(s)) return fail(DEX_ERR_UNSUPPORTED, "GMM shape/dtype/variant not supported");
+  CacheLayout cl = cache_layout(s);
+  char* cc = (char*)cache;
+  const size_t nblk = (size_t)(s.g.Npad / 256);
+  if (!s.mfma) {
+    double* fpart = (double*)ws;
+    launch_fwd_valu<double>(s, in, (double*)(cc + cl.beta), (double*)f, fpart, st);
+    hipLaunchKernelGGL((k_finalize_F<double>), dim3(1), dim3(256), 0, st, fpart,
+                       (int)((s.g.N + 255) / 256), (const double*)in.alphas, (int)s.g.K, s.g.N,
+                       (double*)F);
+    return check_hip(hipGetLastError(), "gmm_fwd (VALU)");
+  }
+  if (cfg < 0 || cfg >= nfwd(s)) return fail(DEX_ERR_INVALID_ARG, "GMM forward config %d out of range", cfg);
+  const FwdCfg c = fwd_cfg(s, cfg);
+  float* fpart = (float*)ws;
+  float2* ml = (float2*)((char*)ws + align256(nblk * 2 * 4));
+  float* beta = (float*)(cc + cl.beta);
+  const MfmaOps o = ops_of(s, cl, cc);
+  const float* x = (const float*)in.x;
+  const float *al = (const float*)in.alphas, *mu = (const float*)in.means,
+              *qd = (const float*)in.qd, *l = (const float*)in.l;
+  void *xh = cc + cl.xh, *xl = cc + cl.xl, *xhT = cc + cl.xhT, *xlT = cc + cl.xlT, *Qh = cc + cl.Qh,
+       *Ql = cc + cl.Ql;
+  float *negc = (float*)(cc + cl.negc), *kappa = (float*)(cc + cl.kappa);
+  switch (s.prec) {
+    case PREC_BF16:
+      mfma_prep<PREC_BF16>(s.g, x, al, mu, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
+      {
+        ProfRange pr(DEX_PROF_GMM_FWD, st);
+        mfma_fwd<PREC_BF16>(s.g, c, o, beta, ml, st);
+        pr.end(1);
+      }
+      break;
+    case PREC_BF16X3:
+      mfma_prep<PREC_BF16X3>(s.g, x, al, mu, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
+      {
+        ProfRange pr(DEX_PROF_GMM_FWD, st);
+        mfma_fwd<PREC_BF16X3>(s.g, c, o, beta, ml, st);
+        pr.end(1);
+      }
+      break;
+    default:
+      mfma_prep<PREC_F32>(s.g, x, al, mu, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
+      {
+        ProfRange pr(DEX_PROF_GMM_FWD, st);
+        mfma_fwd<PREC_F32>(s.g, c, o, beta, ml, st);
+        pr.end(1);
+      }
+  }
+  hipLaunchKernelGGL((k_merge_lse<float>), dim3((unsigned)nblk), dim3(256), 0, st, ml, c.sk,
+                     (int)s.g.N, (int)s.g.Npad, (float*)f, fpart);
+  hipLaunchKernelGGL((k_finalize_F<float>), dim3(1), dim3(256), 0, st, fpart, (int)nblk, al,
+                     (int)s.g.K, s.g.N, (float*)F);
+  return check_hip(hipGetLastError(), "gmm_fwd (MFMA)");
+}
+
+dex_status gmm_vjp(const dex_desc& d, int cfg, const GmmPtrs& in, const void* f,
+                   const void* cache, const void* ct, const GmmGrads& out, bool accumulate,
+                   void* ws, hipStream_t st) {
+  Shape s = shape_of(d);
+  if (!valid_shape(s)) return fail(DEX_ERR_UNSUPPORTED, "GMM shape/dtype/variant not supported");
+  CacheLayout cl = cache_layout(s);
+  const char* cc = (const char*)cache;
+  if (!s.mfma) {
+    const int chunk = (int)(((s.g.N + kValuS - 1) / kValuS + 63) / 64 * 64);
+    const int S = (int)((s.g.N + chunk - 1) / chunk);
+    launch_bwd_valu<double>(s, in, (const double*)(cc + cl.beta), (const double*)f,
+                            (const double*)ct, (double*)ws, chunk, st);
+    const size_t E = (size_t)s.g.D * s.g.D + s.g.D + 1;
+    hipLaunchKernelGGL((k_bwd_finalize<double, double>), dim3((unsigned)s.g.K), dim3(256), 0, st,
+                       (const double*)ws, E, S, (int)s.g.K, (int)s.g.D, (int)s.g.D, s.g.N,
+                       (const double*)in.alphas, (const double*)in.qd, (const double*)in.l,
+                       (const double*)ct, (double*)out.d_alphas, (double*)out.d_means,
+                       (double*)out.d_qd, (double*)out.d_l, accumulate ? 1 : 0);
+    return check_hip(hipGetLastError(), "gmm_vjp (VALU)");
+  }
+  if (cfg < 0 || cfg >= nbwd(s)) return fail(DEX_ERR_INVALID_ARG, "GMM reverse config %d out of range", cfg);
+  const BwdCfg c = bwd_cfg(s, cfg);
+  const MfmaOps o = ops_of(s, cl, cc);
+  const float* beta = (const float*)(cc + cl.beta);
+  float* part = (float*)ws;
+  ProfRange pr(DEX_PROF_GMM_VJP, st);
+  switch (s.prec) {
+    case PREC_BF16:
+      mfma_bwd<PREC_BF16>(s.g, c, o, beta, (const float*)f, (const float*)ct, part, st);
+      break;
+    case PREC_BF16X3:
+      mfma_bwd<PREC_BF16X3>(s.g, c, o, beta, (const float*)f, (const float*)ct, part, st);
+      break;
+    default:
+      mfma_bwd<PREC_F32>(s.g, c, o, beta, (const float*)f, (const float*)ct, part, st);
+  }
+  pr.end(1);
+  int64_t chunk;
+  int nch;
+  bwd_chunks(s.g.Npad, c.s, &chunk, &nch);
+  hipLaunchKernelGGL((k_bwd_finalize<float, float>), dim3((unsigned)s.g.K), dim3(256), 0, st,
+                     (const float*)part, bwd_slot(s.g.DP), nch, (int)s.g.K, (int)s.g.D, s.g.DP,
+                     s.g.N, (const float*)in.alphas, (const float*)in.qd, (const float*)in.l,
+                     (const float*)ct, (float*)out.d_alphas, (float*)out.d_means,
+                     (float*)out.d_qd, (float*)out.d_l, accumulate ? 1 : 0);
+  return check_hip(hipGetLastError(), "gmm_vjp (MFMA)");
+}
+
+}  // namespace dexi

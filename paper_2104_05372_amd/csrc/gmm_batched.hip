@@ -1,0 +1,493 @@
+// Many independent GMM instances of uneven size, FP32 matrix-core form.
+//
+// The nested parallel loop `for b. for i k. ...` is flattened into work items
+// (Sec. 6.1.1: parallelism is allocated at the top level only). A host-side
+// plan lists, per phase, the items (instance, point block[, component group])
+// ordered longest first; the forward and reverse phases each run as one
+// persistent launch whose blocks take items from an atomic counter until the
+// list is exhausted, so the smallest instances do not pay a launch each.
+// Tiles: 16-deep contraction chunks (D in {8, 16} padded to 16, D = 32 as is).
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "gmm_host.h"
+#include "internal.h"
+
+namespace dexk {
+
+struct BInst {
+  int32_t N, D, K, DP;
+  int64_t Npad;
+  int64_t a_off, m_off, l_off, x_off, f_off;       // packed inputs / f (elements)
+  int64_t xh_off, xhT_off, Q_off, negc_off, kappa_off, beta_off;  // cache (bytes)
+  int64_t ml_off;     // ws float2 elements
+  int64_t fpart_off;  // ws float pairs
+  int64_t part_off;   // ws floats
+  int32_t nblk;       // Npad / 256
+  int32_t pad0;
+};
+
+struct BItem {
+  int32_t inst, a, b, c;
+};
+
+constexpr int kBFwdCfgs = 2;
+constexpr int kBBwdCfgs = 4;
+struct BBwd {
+  int pb, gw;
+  int64_t chunk;
+};
+__host__ __device__ inline BBwd bbwd_cfg(int i) {
+  const BBwd t[kBBwdCfgs] = {{4, 1, 4096}, {4, 2, 4096}, {2, 2, 2048}, {4, 1, 8192}};
+  return t[i];
+}
+__host__ __device__ inline int bfwd_cb(int i) { return i == 0 ? 4 : 2; }
+
+struct PlanHeader {
+  int64_t B;
+  int64_t inst_off;
+  int64_t prepx_off, n_prepx;
+  int64_t prepq_off, n_prepq;
+  int64_t merge_off, n_merge;
+  int64_t fwd_off[kBFwdCfgs], n_fwd[kBFwdCfgs];
+  int64_t bwd_off[kBBwdCfgs], n_bwd[kBBwdCfgs];
+  int64_t nch_off;  // int32 [kBBwdCfgs][B]: point chunks per instance
+  int64_t cache_bytes, ws_bytes;
+  int64_t ws_ml, ws_fpart, ws_counter, ws_part;  // byte offsets into ws
+};
+
+__device__ inline const PlanHeader* hdr(const char* plan) { return (const PlanHeader*)plan; }
+
+__device__ inline MfmaOps bops(const BInst& I, const char* cache) {
+  MfmaOps o;
+  o.xh = cache + I.xh_off;
+  o.xl = nullptr;
+  o.xhT = cache + I.xhT_off;
+  o.xlT = nullptr;
+  o.Qh = cache + I.Q_off;
+  o.Ql = nullptr;
+  o.negc = (const float*)(cache + I.negc_off);
+  o.kappa = (const float*)(cache + I.kappa_off);
+  return o;
+}
+
+__global__ void __launch_bounds__(256) k_bprep_x(const char* __restrict__ plan,
+                                                 const float* __restrict__ x, char* cache) {
+  const PlanHeader* h = hdr(plan);
+  const BItem w = ((const BItem*)(plan + h->prepx_off))[blockIdx.x];
+  const BInst I = ((const BInst*)(plan + h->inst_off))[w.inst];
+  float* xh = (float*)(cache + I.xh_off);
+  float* xhT = (float*)(cache + I.xhT_off);
+  if (I.DP == 16)
+    prep_x_tile<PREC_F32, 16>(x + I.x_off, I.N, I.D, (int)I.Npad, w.a * 64, xh, nullptr, xhT, nullptr);
+  else
+    prep_x_tile<PREC_F32, 32>(x + I.x_off, I.N, I.D, (int)I.Npad, w.a * 64, xh, nullptr, xhT, nullptr);
+}
+
+__global__ void __launch_bounds__(256) k_bprep_q(const char* __restrict__ plan,
+                                                 const float* __restrict__ alphas,
+                                                 const float* __restrict__ means,
+                                                 const float* __restrict__ qd,
+                                                 const float* __restrict__ l, char* cache) {
+  const PlanHeader* h = hdr(plan);
+  const BItem w = ((const BItem*)(plan + h->prepq_off))[blockIdx.x];
+  const BInst I = ((const BInst*)(plan + h->inst_off))[w.inst];
+  float* Q = (float*)(cache + I.Q_off);
+  float* negc = (float*)(cache + I.negc_off);
+  float* kappa = (float*)(cache + I.kappa_off);
+  if (I.DP == 16)
+    prep_q_comp<PREC_F32, 16>(alphas + I.a_off, means + I.m_off, qd + I.m_off, l + I.l_off, I.D, w.a,
+                              Q, nullptr, negc, kappa);
+  else
+    prep_q_comp<PREC_F32, 32>(alphas + I.a_off, means + I.m_off, qd + I.m_off, l + I.l_off, I.D, w.a,
+                              Q, nullptr, negc, kappa);
+}
+
+__global__ void fill_counters(int* c, int n) {
+  if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
+
+// Take the next item index for the whole block.
+DEX_DEV int next_item(int* counter) {
+  __shared__ int cur;
+  __syncthreads();
+  if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+  __syncthreads();
+  return cur;
+}
+
+template <int CB>
+__global__ void __launch_bounds__(256) k_bgmm_fwd(const char* __restrict__ plan, int cfg,
+                                                  const char* cache, char* ws) {
+  const PlanHeader* h = hdr(plan);
+  const BInst* inst = (const BInst*)(plan + h->inst_off);
+  const BItem* items = (const BItem*)(plan + h->fwd_off[cfg]);
+  const int n = (int)h->n_fwd[cfg];
+  int* counter = (int*)(ws + h->ws_counter);
+  float2* ml = (float2*)(ws + h->ws_ml);
+  for (;;) {
+    const int it = next_item(counter);
+    if (it >= n) break;
+    const BItem w = items[it];
+    const BInst I = inst[w.inst];
+    const MfmaOps o = bops(I, cache);
+    float* beta = (float*)(cache + I.beta_off);
+    if (I.DP == 16)
+      fwd_unit<16, PREC_F32, CB, 16>(o, I.N, (int)I.Npad, w.a * 64 * CB, 0, I.K, beta, ml + I.ml_off);
+    else
+      fwd_unit<32, PREC_F32, CB, 16>(o, I.N, (int)I.Npad, w.a * 64 * CB, 0, I.K, beta, ml + I.ml_off);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_bmerge(const char* __restrict__ plan, float* __restrict__ f,
+                                                char* ws) {
+  const PlanHeader* h = hdr(plan);
+  const BItem w = ((const BItem*)(plan + h->merge_off))[blockIdx.x];
+  const BInst I = ((const BInst*)(plan + h->inst_off))[w.inst];
+  const float2* ml = (const float2*)(ws + h->ws_ml) + I.ml_off;
+  float* fpart = (float*)(ws + h->ws_fpart) + 2 * I.fpart_off;
+  float s = 0.f, e = 0.f;
+  merge_lse_block<float>(ml, 1, I.N, (int)I.Npad, w.a * 256, f + I.f_off, s, e);
+  if (threadIdx.x == 0) {
+    fpart[2 * w.a] = s;
+    fpart[2 * w.a + 1] = e;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_bfinalize_F(const char* __restrict__ plan,
+                                                     const float* __restrict__ alphas,
+                                                     const char* ws, float* __restrict__ F) {
+  const PlanHeader* h = hdr(plan);
+  const BInst I = ((const BInst*)(plan + h->inst_off))[blockIdx.x];
+  const float* fpart = (const float*)(ws + h->ws_fpart) + 2 * I.fpart_off;
+  finalize_F_block<float>(fpart, I.nblk, alphas + I.a_off, I.K, I.N, F + blockIdx.x);
+}
+
+template <int PB, int GW>
+__global__ void __launch_bounds__(256) k_bgmm_bwd(const char* __restrict__ plan, int cfg,
+                                                  const char* cache, const float* __restrict__ f,
+                                                  const float* __restrict__ ct, char* ws) {
+  const PlanHeader* h = hdr(plan);
+  const BInst* inst = (const BInst*)(plan + h->inst_off);
+  const BItem* items = (const BItem*)(plan + h->bwd_off[cfg]);
+  const int n = (int)h->n_bwd[cfg];
+  const int64_t chunk = bbwd_cfg(cfg).chunk;
+  int* counter = (int*)(ws + h->ws_counter) + 1;
+  float* part = (float*)(ws + h->ws_part);
+  for (;;) {
+    const int it = next_item(counter);
+    if (it >= n) break;
+    const BItem w = items[it];
+    const BInst I = inst[w.inst];
+    const MfmaOps o = bops(I, cache);
+    const float* beta = (const float*)(cache + I.beta_off);
+    const int pbeg = (int)(w.b * chunk);
+    const int pend = (int)std::min<int64_t>(I.Npad, pbeg + chunk);
+    const size_t E = dexi::bwd_slot(I.DP);
+    float* P = part + I.part_off + (size_t)w.b * I.K * E;
+    if (I.DP == 16)
+      bwd_unit<16, PREC_F32, PB, GW, 16>(o, I.N, (int)I.Npad, I.K, w.a * 4 * GW, pbeg, pend, beta,
+                                         f + I.f_off, ct[w.inst], P, E);
+    else
+      bwd_unit<32, PREC_F32, PB, GW, 16>(o, I.N, (int)I.Npad, I.K, w.a * 4 * GW, pbeg, pend, beta,
+                                         f + I.f_off, ct[w.inst], P, E);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_bbwd_finalize(const char* __restrict__ plan, int cfg,
+                                                       const char* ws, const float* __restrict__ alphas,
+                                                       const float* __restrict__ qd,
+                                                       const float* __restrict__ l,
+                                                       const float* __restrict__ ct,
+                                                       float* __restrict__ d_alphas,
+                                                       float* __restrict__ d_means,
+                                                       float* __restrict__ d_qd,
+                                                       float* __restrict__ d_l, int accumulate) {
+  const PlanHeader* h = hdr(plan);
+  const BItem w = ((const BItem*)(plan + h->prepq_off))[blockIdx.x];  // (instance, k)
+  const BInst I = ((const BInst*)(plan + h->inst_off))[w.inst];
+  const int nch = ((const int32_t*)(plan + h->nch_off))[cfg * h->B + w.inst];
+  const size_t E = dexi::bwd_slot(I.DP);
+  const float* part = (const float*)(ws + h->ws_part) + I.part_off + (size_t)w.a * E;
+  bwd_finalize_comp<float, float>(part, (size_t)I.K * E, nch, w.a, I.K, I.D, I.DP, I.N,
+                                  alphas + I.a_off, qd + I.m_off, l + I.l_off, ct[w.inst],
+                                  d_alphas + I.a_off, d_means + I.m_off, d_qd + I.m_off,
+                                  d_l + I.l_off, accumulate);
+}
+
+}  // namespace dexk
+
+// ===========================================================================
+namespace dexi {
+using namespace dexk;
+
+namespace {
+
+struct PlanBuild {
+  PlanHeader h{};
+  std::vector<BInst> inst;
+  std::vector<BItem> prepx, prepq, merge;
+  std::vector<BItem> fwd[kBFwdCfgs], bwd[kBBwdCfgs];
+  std::vector<int32_t> nch;  // [cfg][B]
+  size_t bytes = 0;
+};
+
+int64_t dp_cost(int DP) { return DP == 16 ? 1 : 3; }  // 16-deep chunks per 16 points per k
+
+PlanBuild build_plan(const int64_t* shapes, int64_t B) {
+  PlanBuild p;
+  p.h.B = B;
+  p.inst.resize(B);
+  int64_t a = 0, m = 0, lo = 0, xo = 0, fo = 0, ml = 0, fp = 0, cache = 0, part = 0;
+  auto take = [&](int64_t bytes) {
+    int64_t at = cache;
+    cache += (int64_t)align256((size_t)bytes);
+    return at;
+  };
+  for (int64_t b = 0; b < B; ++b) {
+    BInst& I = p.inst[b];
+    I.N = (int32_t)shapes[3 * b];
+    I.D = (int32_t)shapes[3 * b + 1];
+    I.K = (int32_t)shapes[3 * b + 2];
+    I.DP = I.D <= 16 ? 16 : 32;
+    I.Npad = (I.N + 255) / 256 * 256;
+    I.nblk = (int32_t)(I.Npad / 256);
+    I.a_off = a;
+    I.m_off = m;
+    I.l_off = lo;
+    I.x_off = xo;
+    I.f_off = fo;
+    a += I.K;
+    m += (int64_t)I.K * I.D;
+    lo += (int64_t)I.K * I.D * (I.D - 1) / 2;
+    xo += (int64_t)I.N * I.D;
+    fo += I.N;
+    I.xh_off = take(I.Npad * I.DP * 4);
+    I.xhT_off = take(I.Npad * I.DP * 4);
+    I.Q_off = take((int64_t)I.K * I.DP * I.DP * 4);
+    I.negc_off = take((int64_t)I.K * I.DP * 4);
+    I.kappa_off = take((int64_t)I.K * 4);
+    I.beta_off = take((int64_t)I.K * I.Npad * 4);
+    I.ml_off = ml;
+    ml += I.Npad;
+    I.fpart_off = fp;
+    fp += I.nblk;
+    int64_t maxch = 0;
+    for (int c = 0; c < kBBwdCfgs; ++c) {
+      const int64_t ch = (I.Npad + bbwd_cfg(c).chunk - 1) / bbwd_cfg(c).chunk;
+      maxch = std::max(maxch, ch);
+    }
+    I.part_off = part;
+    part += maxch * I.K * (int64_t)bwd_slot(I.DP);
+    part = (part + 63) / 64 * 64;
+    for (int t = 0; t < I.Npad / 64; ++t) p.prepx.push_back({(int32_t)b, t, 0, 0});
+    for (int k = 0; k < I.K; ++k) p.prepq.push_back({(int32_t)b, k, 0, 0});
+    for (int t = 0; t < I.nblk; ++t) p.merge.push_back({(int32_t)b, t, 0, 0});
+  }
+  // forward work lists, longest first
+  for (int c = 0; c < kBFwdCfgs; ++c) {
+    const int pts = 64 * bfwd_cb(c);
+    std::vector<std::pair<int64_t, BItem>> v;
+    for (int64_t b = 0; b < B; ++b) {
+      const BInst& I = p.inst[b];
+      for (int t = 0; t < I.Npad / pts; ++t)
+        v.push_back({(int64_t)I.K * dp_cost(I.DP) * pts, BItem{(int32_t)b, t, 0, 0}});
+    }
+    std::stable_sort(v.begin(), v.end(), [](auto& x, auto& y) { return x.first > y.first; });
+    for (auto& e : v) p.fwd[c].push_back(e.second);
+  }
+  p.nch.assign((size_t)kBBwdCfgs * B, 0);
+  for (int c = 0; c < kBBwdCfgs; ++c) {
+    const BBwd bc = bbwd_cfg(c);
+    std::vector<std::pair<int64_t, BItem>> v;
+    for (int64_t b = 0; b < B; ++b) {
+      const BInst& I = p.inst[b];
+      const int nch = (int)((I.Npad + bc.chunk - 1) / bc.chunk);
+      p.nch[(size_t)c * B + b] = nch;
+      const int kg = 4 * bc.gw;
+      const int ngroups = (I.K + kg - 1) / kg;
+      for (int g = 0; g < ngroups; ++g) {
+        const int kk = std::min(kg, I.K - g * kg);
+        for (int s = 0; s < nch; ++s) {
+          const int64_t pts = std::min<int64_t>(bc.chunk, I.Npad - s * bc.chunk);
+          // the busiest wave of the block bounds the item's time
+          const int64_t per_wave = std::min(bc.gw, kk);
+          v.push_back({per_wave * pts * (dp_cost(I.DP) + (I.DP == 16 ? 1 : 3)),
+                       BItem{(int32_t)b, g, s, 0}});
+        }
+      }
+    }
+    std::stable_sort(v.begin(), v.end(), [](auto& x, auto& y) { return x.first > y.first; });
+    for (auto& e : v) p.bwd[c].push_back(e.second);
+  }
+  // layout of the plan bytes
+  size_t o = align256(sizeof(PlanHeader));
+  auto place = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes);
+    return (int64_t)at;
+  };
+  p.h.inst_off = place(p.inst.size() * sizeof(BInst));
+  p.h.prepx_off = place(p.prepx.size() * sizeof(BItem));
+  p.h.n_prepx = (int64_t)p.prepx.size();
+  p.h.prepq_off = place(p.prepq.size() * sizeof(BItem));
+  p.h.n_prepq = (int64_t)p.prepq.size();
+  p.h.merge_off = place(p.merge.size() * sizeof(BItem));
+  p.h.n_merge = (int64_t)p.merge.size();
+  for (int c = 0; c < kBFwdCfgs; ++c) {
+    p.h.fwd_off[c] = place(p.fwd[c].size() * sizeof(BItem));
+    p.h.n_fwd[c] = (int64_t)p.fwd[c].size();
+  }
+  for (int c = 0; c < kBBwdCfgs; ++c) {
+    p.h.bwd_off[c] = place(p.bwd[c].size() * sizeof(BItem));
+    p.h.n_bwd[c] = (int64_t)p.bwd[c].size();
+  }
+  p.h.nch_off = place(p.nch.size() * sizeof(int32_t));
+  p.bytes = o;
+  p.h.cache_bytes = cache;
+  size_t w = 0;
+  p.h.ws_counter = (int64_t)w;  // fixed at offset 0: the host clears it before each phase
+  w += 256;
+  p.h.ws_ml = (int64_t)w;
+  w += align256((size_t)ml * sizeof(float2));
+  p.h.ws_fpart = (int64_t)w;
+  w += align256((size_t)fp * 2 * sizeof(float));
+  p.h.ws_part = (int64_t)w;
+  w += align256((size_t)part * sizeof(float));
+  p.h.ws_bytes = (int64_t)w;
+  return p;
+}
+
+// host copy of the header fields the launcher needs, recovered from the
+// descriptor (the plan itself lives on the device)
+struct HostPlan {
+  int64_t B, n_prepx, n_prepq, n_merge, n_fwd[kBFwdCfgs], n_bwd[kBBwdCfgs], cache, ws;
+};
+
+}  // namespace
+
+size_t gmm_batched_plan_bytes(int64_t B, const int64_t* shapes) {
+  return build_plan(shapes, B).bytes;
+}
+
+// Descriptor dims: {B, sum N, sum K, sum K*D, sum K*L, sum N*D, plan bytes, cache bytes}.
+// The item counts and workspace size are recovered from the plan header on
+// the host by dex_gmm_batched_plan only; launches use the counts stored in
+// fparams (exact integers below 2^53).
+dex_status gmm_batched_plan(const int64_t* shapes, int64_t B, int32_t variant, dex_desc* d,
+                            void* plan, size_t plan_bytes) {
+  PlanBuild p = build_plan(shapes, B);
+  int64_t sumN = 0, sumK = 0, sumKD = 0, sumKL = 0, sumND = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    const int64_t N = shapes[3 * b], D = shapes[3 * b + 1], K = shapes[3 * b + 2];
+    sumN += N;
+    sumK += K;
+    sumKD += K * D;
+    sumKL += K * D * (D - 1) / 2;
+    sumND += N * D;
+  }
+  memset(d, 0, sizeof(*d));
+  d->kind = DEX_GMM_BATCHED;
+  d->dtype = DEX_F32;
+  d->variant = variant;
+  d->dims[0] = B;
+  d->dims[1] = sumN;
+  d->dims[2] = sumK;
+  d->dims[3] = sumKD;
+  d->dims[4] = sumKL;
+  d->dims[5] = sumND;
+  d->dims[6] = (int64_t)p.bytes;
+  d->dims[7] = p.h.cache_bytes;
+  // item counts for the launches: prepx, merge, ws bytes, and the persistent
+  // lists' lengths are read on the device; the host needs grid sizes
+  d->fparams[0] = (double)p.h.n_prepx;
+  d->fparams[1] = (double)p.h.n_merge;
+  d->fparams[2] = (double)p.h.ws_bytes;
+  d->fparams[3] = 0.0;
+  if (!plan) return DEX_OK;
+  if (plan_bytes < p.bytes) return fail(DEX_ERR_INVALID_ARG, "plan buffer too small");
+  char* o = (char*)plan;
+  memset(o, 0, p.bytes);
+  memcpy(o, &p.h, sizeof(PlanHeader));
+  memcpy(o + p.h.inst_off, p.inst.data(), p.inst.size() * sizeof(BInst));
+  memcpy(o + p.h.prepx_off, p.prepx.data(), p.prepx.size() * sizeof(BItem));
+  memcpy(o + p.h.prepq_off, p.prepq.data(), p.prepq.size() * sizeof(BItem));
+  memcpy(o + p.h.merge_off, p.merge.data(), p.merge.size() * sizeof(BItem));
+  for (int c = 0; c < kBFwdCfgs; ++c)
+    memcpy(o + p.h.fwd_off[c], p.fwd[c].data(), p.fwd[c].size() * sizeof(BItem));
+  for (int c = 0; c < kBBwdCfgs; ++c)
+    memcpy(o + p.h.bwd_off[c], p.bwd[c].data(), p.bwd[c].size() * sizeof(BItem));
+  memcpy(o + p.h.nch_off, p.nch.data(), p.nch.size() * sizeof(int32_t));
+  return DEX_OK;
+}
+
+size_t gmm_batched_ws_bytes(const dex_desc& d, int role) {
+  if (role == DEX_WS_RESID) return (size_t)d.dims[7];
+  return (size_t)d.fparams[2];
+}
+
+int gmm_batched_num_configs(const dex_desc& d, int role) {
+  (void)d;
+  return role == DEX_WS_VJP ? kBBwdCfgs : kBFwdCfgs;
+}
+
+static int persistent_blocks() { return num_cus() * 2; }
+
+dex_status gmm_batched_fwd(const dex_desc& d, int cfg, const void* plan, const GmmPtrs& in,
+                           void* F, void* f, void* cache, void* ws, hipStream_t st) {
+  if (cfg < 0 || cfg >= kBFwdCfgs) return fail(DEX_ERR_INVALID_ARG, "batched forward config");
+  const int64_t B = d.dims[0], sumK = d.dims[2];
+  const int64_t n_prepx = (int64_t)d.fparams[0], n_merge = (int64_t)d.fparams[1];
+  const char* pl = (const char*)plan;
+  char* cc = (char*)cache;
+  char* w = (char*)ws;
+  hipLaunchKernelGGL(k_bprep_x, dim3((unsigned)n_prepx), dim3(256), 0, st, pl, (const float*)in.x, cc);
+  hipLaunchKernelGGL(k_bprep_q, dim3((unsigned)sumK), dim3(256), 0, st, pl, (const float*)in.alphas,
+                     (const float*)in.means, (const float*)in.qd, (const float*)in.l, cc);
+  hipLaunchKernelGGL(fill_counters, dim3(1), dim3(64), 0, st, (int*)w, 64);
+  ProfRange pr(DEX_PROF_BGMM_FWD, st);
+  if (bfwd_cb(cfg) == 4)
+    hipLaunchKernelGGL((k_bgmm_fwd<4>), dim3(persistent_blocks()), dim3(256), 0, st, pl, cfg,
+                       (const char*)cc, w);
+  else
+    hipLaunchKernelGGL((k_bgmm_fwd<2>), dim3(persistent_blocks()), dim3(256), 0, st, pl, cfg,
+                       (const char*)cc, w);
+  pr.end(1);
+  hipLaunchKernelGGL(k_bmerge, dim3((unsigned)n_merge), dim3(256), 0, st, pl, (float*)f, w);
+  hipLaunchKernelGGL(k_bfinalize_F, dim3((unsigned)B), dim3(256), 0, st, pl, (const float*)in.alphas,
+                     (const char*)w, (float*)F);
+  return check_hip(hipGetLastError(), "gmm_batched_fwd");
+}
+
+dex_status gmm_batched_vjp(const dex_desc& d, int cfg, const void* plan, const GmmPtrs& in,
+                           const void* f, const void* cache, const void* ct, const GmmGrads& out,
+                           bool accumulate, void* ws, hipStream_t st) {
+  if (cfg < 0 || cfg >= kBBwdCfgs) return fail(DEX_ERR_INVALID_ARG, "batched reverse config");
+  const int64_t sumK = d.dims[2];
+  const char* pl = (const char*)plan;
+  char* w = (char*)ws;
+  const BBwd bc = bbwd_cfg(cfg);
+  hipLaunchKernelGGL(fill_counters, dim3(1), dim3(64), 0, st, (int*)w, 64);
+#define DEX_BB(PB_, GW_)                                                                     \
+  hipLaunchKernelGGL((k_bgmm_bwd<PB_, GW_>), dim3(persistent_blocks()), dim3(256), 0, st, pl, \
+                     cfg, (const char*)cache, (const float*)f, (const float*)ct, w)
+  ProfRange pr(DEX_PROF_BGMM_VJP, st);
+  if (bc.pb == 4 && bc.gw == 1)
+    DEX_BB(4, 1);
+  else if (bc.pb == 4)
+    DEX_BB(4, 2);
+  else
+    DEX_BB(2, 2);
+#undef DEX_BB
+  pr.end(1);
+  hipLaunchKernelGGL(k_bbwd_finalize, dim3((unsigned)sumK), dim3(256), 0, st, pl, cfg,
+                     (const char*)w, (const float*)in.alphas, (const float*)in.qd,
+                     (const float*)in.l, (const float*)ct, (float*)out.d_alphas,
+                     (float*)out.d_means, (float*)out.d_qd, (float*)out.d_l, accumulate ? 1 : 0);
+  return check_hip(hipGetLastError(), "gmm_batched_vjp");
+}
+
+}  // namespace dexi

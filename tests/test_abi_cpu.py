@@ -1,0 +1,141 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/dex.h declares, rejects bad arguments before touching a
+device, sizes its workspaces, and builds batched plans."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dex.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dex_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def dex():
+    from paper_2104_05372_amd import dex as d
+    d.lib()
+    return d
+
+
+def test_library_exports_every_declared_function(dex):
+    names = header_functions()
+    assert len(names) >= 12
+    L = ctypes.CDLL(dex.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(dex.EXPORTS)
+
+
+def test_status_strings(dex):
+    L = dex.lib()
+    for s in (0, -1, -2, -3, -4, -5):
+        assert L.dex_status_string(s).decode() not in ("", "unknown status")
+    assert "gfx950" in dex.dex_version()
+
+
+def _status(fn, *a):
+    try:
+        fn(*a)
+    except dex_error() as e:
+        return e.status
+    return 0
+
+
+def dex_error():
+    from paper_2104_05372_amd.dex import DexError
+    return DexError
+
+
+def test_invalid_descriptors_rejected_on_host(dex):
+    bad = [dex.gmm_desc(0, 2, 3), dex.gmm_desc(10, 65, 3), dex.gmm_desc(10, 2, 3, dex.DEX_F64, dex.DEX_GMM_BF16),
+           dex.desc(99, dex.DEX_F32, (1, 1, 1)), dex.stencil_desc(8, 8, 10, 0),
+           dex.stencil_desc(8, 8, 10, 2, rho=0.1, variant=dex.DEX_STENCIL_LINEAR),
+           dex.gather_desc(0, 4, 4)]
+    for d in bad:
+        s = _status(dex.dex_workspace_bytes, d, dex.DEX_WS_FWD)
+        assert s in (dex.DEX_ERR_INVALID_ARG, dex.DEX_ERR_UNSUPPORTED), s
+        s = _status(dex.dex_fwd, d, [], [], [], None)
+        assert s in (dex.DEX_ERR_INVALID_ARG, dex.DEX_ERR_UNSUPPORTED), s
+
+
+def test_accum_scatter_argument_checks(dex):
+    L = dex.lib()
+    # bad dtypes / sizes return before any device work
+    assert L.dex_accum_scatter(None, 7, 10, 1, None, dex.DEX_I32, None, None, 0, 0, None, None, 0, None) \
+        == dex.DEX_ERR_INVALID_ARG
+    assert L.dex_accum_scatter(None, dex.DEX_F32, 0, 1, None, dex.DEX_I32, None, None, 0, 0, None, None, 0,
+                               None) == dex.DEX_ERR_INVALID_ARG
+    assert L.dex_accum_scatter(None, dex.DEX_F32, 10, 1, None, dex.DEX_I32, None, None, 5, 0, None, None, 0,
+                               None) == dex.DEX_ERR_INVALID_ARG
+    # bounds checking needs a counter
+    assert L.dex_accum_scatter(ctypes.c_void_p(16), dex.DEX_I32, 10, 1, ctypes.c_void_p(16), dex.DEX_I32, None,
+                               None, 5, dex.DEX_CHECK_BOUNDS, None, None, 0, None) == dex.DEX_ERR_INVALID_ARG
+
+
+def test_workspace_sizes(dex):
+    d = dex.gmm_desc(100_000, 64, 200, dex.DEX_F32, dex.DEX_GMM_BF16)
+    cache = dex.dex_workspace_bytes(d, dex.DEX_WS_RESID)
+    # bf16 x (both layouts) + bf16 Q + beta, at least
+    assert cache >= 100_096 * 64 * 2 * 2 + 200 * 64 * 64 * 2 + 200 * 100_096 * 4
+    assert dex.dex_workspace_bytes(d, dex.DEX_WS_VJP) > 0
+    d64 = dex.gmm_desc(1000, 2, 5, dex.DEX_F64, dex.DEX_GMM_PLAIN)
+    assert dex.dex_workspace_bytes(d64, dex.DEX_WS_RESID) >= 1000 * 5 * 8
+    st = dex.stencil_desc(64, 64, 100, 32)
+    assert dex.dex_workspace_bytes(st, dex.DEX_WS_VJP) >= (2 + 31) * 64 * 64 * 4
+    lin = dex.stencil_desc(64, 64, 100, 32, variant=dex.DEX_STENCIL_LINEAR)
+    assert dex.dex_workspace_bytes(lin, dex.DEX_WS_VJP) < dex.dex_workspace_bytes(st, dex.DEX_WS_VJP)
+    hist = dex.dex_accum_scatter_workspace_bytes(dex.DEX_I32, 65536, 1, 1 << 26, False)
+    assert hist >= 32768 * 4
+    assert dex.dex_num_configs(d, dex.DEX_WS_FWD) >= 2
+    assert dex.dex_num_configs(d, dex.DEX_WS_VJP) >= 2
+
+
+def test_batched_plan(dex):
+    shapes = workloads.batched_shapes(64, seed=3)
+    d, plan = dex.dex_gmm_batched_plan(shapes)
+    B = shapes.shape[0]
+    N, D, K = shapes[:, 0], shapes[:, 1], shapes[:, 2]
+    assert d.kind == dex.DEX_GMM_BATCHED and d.dims[0] == B
+    assert d.dims[1] == N.sum() and d.dims[2] == K.sum()
+    assert d.dims[3] == (K * D).sum() and d.dims[4] == (K * D * (D - 1) // 2).sum()
+    assert d.dims[5] == (N * D).sum() and d.dims[6] == plan.size
+    # header: int64 fields; instance table follows at inst_off
+    hdr = plan[:8 * 40].view(np.int64)
+    assert hdr[0] == B
+    inst_off = hdr[1]
+    rec = np.dtype([("N", "<i4"), ("D", "<i4"), ("K", "<i4"), ("DP", "<i4"), ("Npad", "<i8"),
+                    ("offs", "<i8", (14,)), ("nblk", "<i4"), ("pad", "<i4")])
+    inst = plan[inst_off: inst_off + B * rec.itemsize].view(rec)
+    assert np.array_equal(inst["N"], N) and np.array_equal(inst["D"], D) and np.array_equal(inst["K"], K)
+    assert np.all(inst["Npad"] % 256 == 0) and np.all(inst["Npad"] >= N)
+    # packed input offsets are prefix sums in instance order
+    assert np.array_equal(inst["offs"][:, 0], np.concatenate([[0], np.cumsum(K)[:-1]]))
+    assert np.array_equal(inst["offs"][:, 3], np.concatenate([[0], np.cumsum(N * D)[:-1]]))
+    ws = dex.dex_workspace_bytes(d, dex.DEX_WS_FWD)
+    assert ws > 0 and dex.dex_workspace_bytes(d, dex.DEX_WS_RESID) == d.dims[7]
+
+
+def test_batched_plan_rejects_bad_shapes(dex):
+    for bad in ([[100, 12, 5]], [[0, 8, 5]], [[100, 8, 0]]):
+        with pytest.raises(dex_error()):
+            dex.dex_gmm_batched_plan(np.array(bad))
+
+
+def test_package_has_no_oracle_dependency():
+    """The product package never imports the oracle."""
+    pkg = os.path.join(ROOT, "paper_2104_05372_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".cpp", ".h")):
+                src = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in src and "from oracle" not in src, fn

@@ -1,0 +1,95 @@
+"""GPU parity of the batched (persistent, one launch per phase) GMM against the
+FP64 oracle, instance by instance (FP32: 1e-5 relative L2)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import gmm as ogmm
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def run_batched(shapes, insts, fcfg=0, bcfg=0, ct=None, dev="cuda"):
+    from paper_2104_05372_amd import dex
+    d, plan = dex.dex_gmm_batched_plan(shapes)
+    packed = [torch.tensor(a, device=dev) for a in workloads.pack_batched(insts)]
+    tplan = torch.tensor(plan, device=dev)
+    B = shapes.shape[0]
+    F = torch.empty(B, device=dev)
+    f = torch.empty(int(d.dims[1]), device=dev)
+    cache = torch.empty(int(d.dims[7]), dtype=torch.uint8, device=dev)
+    ws = dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_FWD), dev)
+    d.config = fcfg
+    print(f"  batched B={B} fwd cfg={fcfg}", flush=True)
+    dex.dex_fwd(d, [tplan, *packed], [F], [f, cache], ws)
+    d.config = bcfg
+    ctt = torch.tensor(np.ones(B, np.float32) if ct is None else ct, device=dev)
+    grads = [torch.empty_like(p) for p in packed[:4]]
+    print(f"  batched vjp cfg={bcfg}", flush=True)
+    dex.dex_vjp(d, [tplan, *packed], [f, cache], [ctt], grads, 0, ws)
+    torch.cuda.synchronize()
+    return F.cpu().numpy(), f.cpu().numpy(), [x.cpu().numpy() for x in grads]
+
+
+def split(shapes, arr, per):
+    out, o = [], 0
+    for row in shapes:
+        m = per(*row)
+        out.append(arr[o:o + m])
+        o += m
+    return out
+
+
+def check_instances(shapes, insts, got, which, ct=None):
+    F, f, grads = got
+    fs = split(shapes, f, lambda N, D, K: N)
+    ga = split(shapes, grads[0], lambda N, D, K: K)
+    gm = split(shapes, grads[1], lambda N, D, K: K * D)
+    gq = split(shapes, grads[2], lambda N, D, K: K * D)
+    gl = split(shapes, grads[3], lambda N, D, K: K * D * (D - 1) // 2)
+    for b in which:
+        g = insts[b]
+        Fo, fo = ogmm.objective(*g.params(), g.x)
+        c = 1.0 if ct is None else float(ct[b])
+        go = ogmm.vjp(*g.params(), g.x, fo, c)
+        assert abs(F[b] - Fo) <= 1e-5 * abs(Fo), b
+        assert rel(fs[b], fo) <= 1e-5, b
+        for a, o in zip((ga[b], gm[b], gq[b], gl[b]), go):
+            assert rel(a, o.ravel()) <= 1e-5, b
+
+
+def small_batch():
+    shapes = np.array([[1000, 8, 10], [1537, 16, 3], [2049, 32, 7], [256, 8, 1],
+                       [3001, 32, 12], [999, 16, 25], [4100, 8, 2]], np.int64)
+    return shapes, workloads.batched_inputs(shapes, seed=30)
+
+
+@pytest.mark.parametrize("fcfg,bcfg", [(0, 0), (1, 1), (2, 2), (1, 3), (2, 4)])
+def test_small_batch_all_configs(dev, fcfg, bcfg):
+    shapes, insts = small_batch()
+    got = run_batched(shapes, insts, fcfg, bcfg)
+    check_instances(shapes, insts, got, range(len(insts)))
+
+
+def test_per_instance_cotangents(dev):
+    shapes, insts = small_batch()
+    ct = np.linspace(-2, 2, len(insts)).astype(np.float32)
+    got = run_batched(shapes, insts, ct=ct)
+    check_instances(shapes, insts, got, range(len(insts)), ct)
+
+
+def test_full_batch_sampled(dev):
+    """512 instances, N ~ U[1000, 50000], D in {8,16,32}, K ~ U[10,100]."""
+    shapes = workloads.batched_shapes()
+    insts = workloads.batched_inputs(shapes)
+    got = run_batched(shapes, insts)
+    cost = shapes[:, 0] * shapes[:, 2] * shapes[:, 1] ** 2
+    which = sorted({int(np.argmax(cost)), int(np.argmin(cost)), 0, 511, 100, 257})
+    check_instances(shapes, insts, got, which)

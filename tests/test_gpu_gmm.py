@@ -1,0 +1,169 @@
+"""GPU parity of the GMM objective and its reverse pass against the FP64 oracle.
+
+Tolerances (relative L2 per output block, FP64 on the host):
+  FP64 form           1e-10
+  FP32 form           1e-5
+  BF16 products       TOL_BF16 (derived below)
+  split-BF16 products TOL_BF16X3
+The BF16 tolerance comes from the arithmetic: x~ and Q~ are rounded to BF16
+(unit roundoff u = 2^-9), so y = Q~(x~ - mu) carries relative errors of order
+u; the weights w = exp(beta - f) inherit absolute errors of order
+|beta| u ~ 64 u, which cancel in part across points. Measured errors sit near
+3e-3; the bound is 5 u = 1e-2. Split-BF16 drops only the lo*lo terms (about
+2^-16 relative) and keeps w Y in two parts, bound 2e-4.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import gmm as ogmm
+
+pytestmark = pytest.mark.gpu
+
+TOL_BF16 = 1e-2
+TOL_BF16X3 = 2e-4
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def run_gmm(g, dtype, variant, fcfg=0, bcfg=0, ct=1.0, accumulate_into=None, dev="cuda"):
+    from paper_2104_05372_amd import dex
+    tdt = torch.float64 if dtype == dex.DEX_F64 else torch.float32
+    t = [torch.tensor(np.ascontiguousarray(a), dtype=tdt, device=dev).contiguous()
+         for a in (g.alphas, g.means, g.qd, g.l, g.x)]
+    N, D, K = g.N, g.D, g.K
+    d = dex.gmm_desc(N, D, K, dtype, variant, fcfg)
+    F = torch.empty(1, dtype=tdt, device=dev)
+    f = torch.empty(N, dtype=tdt, device=dev)
+    cache = torch.empty(dex.dex_workspace_bytes(d, dex.DEX_WS_RESID), dtype=torch.uint8, device=dev)
+    ws = dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_FWD), dev)
+    print(f"  gmm fwd N={N} D={D} K={K} dtype={dtype} variant={variant} cfg={fcfg}", flush=True)
+    dex.dex_fwd(d, t, [F], [f, cache], ws)
+    d.config = bcfg
+    grads = ([torch.zeros_like(x) for x in t[:4]] if accumulate_into is None
+             else [torch.tensor(a, dtype=tdt, device=dev) for a in accumulate_into])
+    ctt = torch.tensor([ct], dtype=tdt, device=dev)
+    wsv = dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_VJP), dev)
+    print(f"  gmm vjp cfg={bcfg}", flush=True)
+    dex.dex_vjp(d, t, [f, cache], [ctt], grads,
+                dex.DEX_ACCUMULATE if accumulate_into is not None else 0, wsv)
+    torch.cuda.synchronize()
+    return float(F.item()), f.cpu().numpy(), [x.cpu().numpy() for x in grads]
+
+
+def oracle_gmm(g, ct=1.0):
+    F, f = ogmm.objective(*g.params(), g.x)
+    return F, f, ogmm.vjp(*g.params(), g.x, f, ct)
+
+
+def check(got, want, tol, what=""):
+    F, f, grads = got
+    Fo, fo, go = want
+    assert abs(F - Fo) <= tol * max(1.0, abs(Fo)), (what, F, Fo)
+    assert rel(f, fo) <= tol, (what, rel(f, fo))
+    for name, a, b in zip(("d_alphas", "d_means", "d_qd", "d_l"), grads, go):
+        if b.size:
+            assert rel(a, b) <= tol, (what, name, rel(a, b))
+
+
+def test_small_fp64_matches_oracle_and_golden(dev):
+    import json
+    import os
+    from paper_2104_05372_amd import dex
+    g = workloads.gmm_small()
+    got = run_gmm(g, dex.DEX_F64, dex.DEX_GMM_PLAIN)
+    check(got, oracle_gmm(g), 1e-10, "S0 fp64")
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "gmm_small_f64.json")))
+    assert abs(got[0] - gold["F"]) <= 1e-10 * abs(gold["F"])
+    assert rel(got[2][0], gold["d_alphas"]) <= 1e-10
+    assert rel(got[2][3], gold["d_l"]) <= 1e-10
+
+
+@pytest.mark.parametrize("N,D,K", [(257, 1, 3), (1000, 3, 4), (700, 7, 1), (1500, 16, 5),
+                                   (999, 17, 6), (2048, 32, 3), (640, 33, 4), (1100, 64, 5)])
+def test_fp64_shapes(dev, N, D, K):
+    from paper_2104_05372_amd import dex
+    g = workloads.gmm_inputs(N, D, K, 100 + D)
+    check(run_gmm(g, dex.DEX_F64, dex.DEX_GMM_PLAIN), oracle_gmm(g), 1e-10, f"fp64 {N},{D},{K}")
+
+
+@pytest.mark.parametrize("N,D,K", [(257, 1, 3), (1000, 2, 5), (700, 7, 1), (1500, 16, 5),
+                                   (999, 17, 6), (2048, 32, 3), (640, 33, 4), (3000, 64, 7),
+                                   (513, 63, 2)])
+def test_fp32_matrix_core_shapes(dev, N, D, K):
+    from paper_2104_05372_amd import dex
+    g = workloads.gmm_inputs(N, D, K, 200 + D, np.float32)
+    check(run_gmm(g, dex.DEX_F32, dex.DEX_GMM_PLAIN), oracle_gmm(g), 1e-5, f"fp32 {N},{D},{K}")
+
+
+@pytest.mark.parametrize("variant,tol", [(1, TOL_BF16), (2, TOL_BF16X3)])
+@pytest.mark.parametrize("N,D,K", [(1000, 2, 5), (1500, 16, 5), (999, 17, 6), (3000, 64, 7),
+                                   (640, 33, 4)])
+def test_bf16_shapes(dev, variant, tol, N, D, K):
+    g = workloads.gmm_inputs(N, D, K, 300 + D, np.float32)
+    got = run_gmm(g, 2, variant)
+    want = oracle_gmm(g)
+    errs = [rel(a, b) for a, b in zip(got[2], want[2]) if b.size]
+    print(f"  variant {variant} N={N} D={D} K={K} grad rel-L2 per block: {errs}", flush=True)
+    check(got, want, tol, f"bf16 v{variant} {N},{D},{K}")
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_every_tile_configuration(dev, variant):
+    from paper_2104_05372_amd import dex
+    g = workloads.gmm_inputs(2500, 64, 9, 7, np.float32)
+    want = oracle_gmm(g)
+    tol = {0: 1e-5, 1: TOL_BF16, 2: TOL_BF16X3}[variant]
+    d = dex.gmm_desc(g.N, g.D, g.K, dex.DEX_F32, variant)
+    nf, nb = dex.dex_num_configs(d, dex.DEX_WS_FWD), dex.dex_num_configs(d, dex.DEX_WS_VJP)
+    ref = None
+    for c in range(1, max(nf, nb) + 1):
+        got = run_gmm(g, dex.DEX_F32, variant, min(c, nf), min(c, nb))
+        check(got, want, tol, f"config {c}")
+        if ref is None:
+            ref = got
+        else:  # every configuration computes the same function
+            assert rel(got[2][3], ref[2][3]) <= tol
+
+
+def test_cotangent_scaling_and_accumulate(dev):
+    from paper_2104_05372_amd import dex
+    g = workloads.gmm_inputs(1200, 16, 4, 9, np.float32)
+    want = oracle_gmm(g, ct=-2.5)
+    got = run_gmm(g, dex.DEX_F32, dex.DEX_GMM_PLAIN, ct=-2.5)
+    check(got, want, 1e-5, "ct=-2.5")
+    base = [np.full_like(a, 0.25, dtype=np.float32) for a in want[2]]
+    acc = run_gmm(g, dex.DEX_F32, dex.DEX_GMM_PLAIN, ct=-2.5, accumulate_into=base)
+    for a, b in zip(acc[2], want[2]):
+        if b.size:
+            assert rel(a - 0.25, b) <= 1e-5
+
+
+def test_autograd_function(dev):
+    from paper_2104_05372_amd import autograd
+    g = workloads.gmm_inputs(800, 8, 3, 13, np.float32)
+    t = [torch.tensor(a, device=dev, requires_grad=(i < 4)) for i, a in enumerate(
+        (g.alphas, g.means, g.qd, g.l, g.x))]
+    F = autograd.gmm_loglik(*t, variant=0)
+    F.backward()
+    Fo, fo, go = oracle_gmm(g)
+    assert abs(F.item() - Fo) <= 1e-5 * abs(Fo)
+    for x, b in zip(t[:4], go):
+        assert rel(x.grad.cpu().numpy(), b) <= 1e-5
+
+
+def test_full_size_bf16_and_fp32(dev):
+    """N=1e5, D=64, K=200 in the launch configuration the benchmark uses."""
+    g = workloads.gmm_large()
+    want = oracle_gmm(g)
+    for variant, tol in ((1, TOL_BF16), (0, 1e-5)):
+        got = run_gmm(g, 2, variant)
+        errs = {n: rel(a, b) for n, a, b in zip(("alphas", "means", "qd", "l"), got[2], want[2])}
+        print(f"  full size variant {variant}: F rel {abs(got[0]-want[0])/abs(want[0]):.3e} "
+              f"f rel {rel(got[1], want[1]):.3e} grads {errs}", flush=True)
+        check(got, want, tol, f"full size v{variant}")

@@ -1,0 +1,176 @@
+"""GPU parity of the gather, its transpose (float scatter-accumulate) and the
+integer histogram against the oracle. Integer results must be bit-exact; float
+results within 1e-5 relative L2 (FP32)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import scatter as osc
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gather_vjp(T, idx, w, g, dev, want_dw=True):
+    from paper_2104_05372_amd import dex
+    V, R = T.shape
+    n = idx.shape[0]
+    d = dex.gather_desc(V, R, n)
+    tT = torch.tensor(T, device=dev)
+    ti = torch.tensor(idx, device=dev)
+    tw = torch.tensor(w, device=dev)
+    tg = torch.tensor(g, device=dev)
+    out = torch.empty(n, R, device=dev)
+    print(f"  gather V={V} R={R} n={n}", flush=True)
+    dex.dex_fwd(d, [tT, ti, tw], [out], [])
+    dT = torch.empty_like(tT)
+    dw = torch.empty_like(tw) if want_dw else None
+    dex.dex_vjp(d, [tT, ti, tw], [], [tg], [dT, dw], 0 if want_dw else dex.DEX_NO_DW)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), dT.cpu().numpy(), (dw.cpu().numpy() if want_dw else None)
+
+
+@pytest.mark.parametrize("V,R,n,seed", [(50, 8, 1000, 0), (1000, 128, 50_000, 1), (7, 3, 5000, 2),
+                                        (300, 100, 4097, 3), (20_000, 130, 2049, 4), (1, 64, 3000, 5)])
+def test_gather_and_transpose(dev, V, R, n, seed):
+    si = workloads.scatter_inputs(V, R, n, 1.1, seed)
+    out, dT, dw = gather_vjp(si.table, si.idx, si.w, si.g, dev)
+    assert rel(out, osc.gather(si.table, si.idx, si.w)) <= 1e-6
+    want = osc.scatter(V, si.idx, si.w, si.g)
+    assert rel(dT, want) <= 1e-5
+    untouched = np.setdiff1d(np.arange(V), si.idx)
+    assert np.all(dT[untouched] == 0)
+    assert rel(dw, osc.scatter_dw(si.table, si.idx, si.g)) <= 1e-5
+
+
+def test_dense_one_hot_invariant(dev):
+    si = workloads.scatter_inputs(50, 8, 1000, 1.1, 0)
+    _, dT, _ = gather_vjp(si.table, si.idx, si.w, si.g, dev)
+    S = np.zeros((1000, 50))
+    S[np.arange(1000), si.idx] = 1
+    assert rel(dT, S.T @ (si.w[:, None].astype(np.float64) * si.g)) <= 1e-5
+
+
+@pytest.mark.parametrize("order", ["equal", "sorted", "reverse", "distinct"])
+def test_contention_patterns(dev, order):
+    rng = np.random.default_rng(7)
+    n, V, R = 200_000, 5000, 32
+    if order == "equal":
+        idx = np.full(n, 17, np.int32)
+    elif order == "sorted":
+        idx = np.sort(rng.integers(0, V, n)).astype(np.int32)
+    elif order == "reverse":
+        idx = np.sort(rng.integers(0, V, n))[::-1].astype(np.int32).copy()
+    else:
+        n = V
+        idx = rng.permutation(V).astype(np.int32)
+    w = rng.uniform(-1, 1, n).astype(np.float32)
+    g = rng.standard_normal((n, R)).astype(np.float32)
+    T = rng.standard_normal((V, R)).astype(np.float32)
+    _, dT, _ = gather_vjp(T, idx, w, g, dev, want_dw=False)
+    if order == "equal":
+        want = np.zeros((V, R))
+        want[17] = (w[:, None].astype(np.float64) * g).sum(0)
+    else:
+        want = osc.scatter(V, idx, w, g)
+    assert rel(dT, want) <= 1e-5
+
+
+def test_accum_scatter_entry_point_and_bounds(dev):
+    from paper_2104_05372_amd import autograd, dex
+    rng = np.random.default_rng(3)
+    idx = rng.integers(-5, 105, 3000).astype(np.int32)
+    vals = rng.standard_normal((3000, 5)).astype(np.float32)
+    scale = rng.uniform(-1, 1, 3000).astype(np.float32)
+    acc = torch.full((100, 5), 2.0, device=dev)
+    bad = autograd.accum_scatter(acc, torch.tensor(idx, device=dev), torch.tensor(vals, device=dev),
+                                 torch.tensor(scale, device=dev), check_bounds=True)
+    want, nbad = osc.scatter(100, idx, scale, vals, check_bounds=True)
+    assert bad == nbad
+    assert rel(acc.cpu().numpy() - 2.0, want) <= 1e-5
+    # DEX_SYNC_CHECK turns found indices into an error status
+    oob = torch.zeros(1, dtype=torch.int64, device=dev)
+    with pytest.raises(dex.DexError) as ei:
+        dex.dex_accum_scatter(acc, torch.tensor(idx, device=dev), torch.tensor(vals, device=dev), None,
+                              dex.DEX_CHECK_BOUNDS | dex.DEX_SYNC_CHECK, oob)
+    assert ei.value.status == dex.DEX_ERR_OUT_OF_RANGE
+    # empty input is a no-op
+    dex.dex_accum_scatter(acc, torch.zeros(0, dtype=torch.int32, device=dev))
+
+
+def test_integer_rows_exact(dev):
+    from paper_2104_05372_amd import dex
+    rng = np.random.default_rng(5)
+    for R in (3, 70):
+        idx = rng.integers(0, 40, 20_000).astype(np.int32)
+        vals = rng.integers(-1000, 1000, (20_000, R)).astype(np.int32)
+        acc = torch.zeros(40, R, dtype=torch.int32, device=dev)
+        dex.dex_accum_scatter(acc, torch.tensor(idx, device=dev), torch.tensor(vals, device=dev))
+        want = np.zeros((40, R), np.int64)
+        np.add.at(want, idx, vals)
+        assert np.array_equal(acc.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("n,bins,seed", [(1 << 20, 65536, 0), (100_003, 17, 1), (5, 65536, 2),
+                                         (300_000, 1, 3), (1 << 18, 1000, 4)])
+def test_histogram_bit_exact(dev, n, bins, seed):
+    from paper_2104_05372_amd import autograd
+    keys = workloads.histogram_keys(n, bins, 1.1, seed)
+    tk = torch.tensor(keys.view(np.int32), device=dev)
+    print(f"  histogram n={n} bins={bins}", flush=True)
+    h1 = autograd.histogram(tk, bins).cpu().numpy()
+    h2 = autograd.histogram(tk, bins).cpu().numpy()
+    want = osc.histogram(keys, bins)
+    assert np.array_equal(h1, want) and np.array_equal(h2, want)
+
+
+def test_histogram_single_hot_bin_drains(dev):
+    """All keys equal: the LDS counter crosses the drain threshold many times."""
+    from paper_2104_05372_amd import autograd
+    keys = np.full(3_000_000, 40_001, np.uint32)
+    keys[::7] = 3
+    h = autograd.histogram(torch.tensor(keys.view(np.int32), device=dev), 65536).cpu().numpy()
+    assert h[40_001] == np.count_nonzero(keys == 40_001) and h[3] == np.count_nonzero(keys == 3)
+    assert h.sum() == keys.size
+
+
+def test_histogram_out_of_range_keys(dev):
+    from paper_2104_05372_amd import dex
+    keys = np.array([1, 2, 70_000, 2, 65_535, 65_536], np.uint32)
+    h = torch.zeros(65536, dtype=torch.int32, device=dev)
+    oob = torch.zeros(1, dtype=torch.int64, device=dev)
+    dex.dex_accum_scatter(h, torch.tensor(keys.view(np.int32), device=dev), flags=dex.DEX_CHECK_BOUNDS,
+                          oob=oob, idx_dtype=dex.DEX_U32)
+    hh = h.cpu().numpy()
+    assert oob.item() == 2 and hh[2] == 2 and hh[1] == 1 and hh[65535] == 1 and hh.sum() == 4
+
+
+def test_full_size_scatter_sampled(dev):
+    """1e6 x 128 table, 2^22 Zipf(1.1) indices, as benchmarked; sampled rows."""
+    c = workloads.SCATTER
+    si = workloads.scatter_inputs(c["rows"], c["row_len"], c["n"], c["s"], c["seed"])
+    out, dT, dw = gather_vjp(si.table, si.idx, si.w, si.g, dev)
+    rng = np.random.default_rng(0)
+    js = np.concatenate([[0, c["n"] - 1], rng.integers(0, c["n"], 64)])
+    assert rel(out[js], osc.gather(si.table, si.idx, si.w, js)) <= 1e-6
+    assert rel(dw[js], osc.scatter_dw(si.table, si.idx, si.g, js)) <= 1e-5
+    touched = np.unique(si.idx)
+    rows = np.concatenate([[0, 1, 2, 3], rng.choice(touched, 40, replace=False)])
+    for r in rows:
+        assert rel(dT[r], osc.scatter_rows([r], si.idx, si.w, si.g)[0]) <= 1e-5, r
+    untouched = np.setdiff1d(np.arange(1000), touched)
+    assert np.all(dT[untouched] == 0)
+
+
+def test_full_size_histogram(dev):
+    from paper_2104_05372_amd import autograd
+    c = workloads.HISTOGRAM
+    keys = workloads.histogram_keys(c["n"], c["bins"], c["s"], c["seed"])
+    h = autograd.histogram(torch.tensor(keys.view(np.int32), device=dev), c["bins"]).cpu().numpy()
+    assert np.array_equal(h, osc.histogram(keys, c["bins"]))

@@ -1,0 +1,106 @@
+"""GPU parity of the in-place diffusion loop and its checkpointed reverse pass
+against the oracle (small grids) and the FFT closed form (full size)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import stencil as ost
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def run(u0, target, steps, every, rho=0.0, variant=0, vcfg=0, dev="cuda", ct=1.0):
+    from paper_2104_05372_amd import dex
+    H, W = u0.shape
+    d = dex.stencil_desc(H, W, steps, every, 0.2, rho, variant)
+    tu = torch.tensor(u0, device=dev)
+    tt = torch.tensor(target, device=dev)
+    nck = (steps + every - 1) // every
+    L = torch.empty(1, device=dev)
+    uT = torch.empty_like(tu)
+    ck = torch.empty(nck * H * W, device=dev)
+    print(f"  stencil {H}x{W} steps={steps} every={every} rho={rho} variant={variant} cfg={vcfg}",
+          flush=True)
+    dex.dex_fwd(d, [tu, tt], [L, uT], [ck, uT], dex.workspace(dex.dex_workspace_bytes(d, 0), dev))
+    d.config = vcfg
+    du = torch.empty_like(tu)
+    dex.dex_vjp(d, [tu, tt], [ck, uT], [torch.tensor([ct], device=dev)], [du], 0,
+                dex.workspace(dex.dex_workspace_bytes(d, 1), dev))
+    torch.cuda.synchronize()
+    return L.item(), uT.cpu().numpy(), du.cpu().numpy(), ck.cpu().numpy().reshape(nck, H, W)
+
+
+@pytest.mark.parametrize("H,W,steps,every", [(32, 24, 7, 3), (16, 16, 50, 32), (9, 13, 11, 4),
+                                             (64, 64, 100, 32), (8, 40, 1, 1), (12, 12, 0, 5)])
+def test_matches_oracle(dev, H, W, steps, every):
+    u0, tg = workloads.stencil_inputs(H, W, 1)
+    L, uT, du, ck = run(u0, tg, steps, every)
+    Lo, uTo, duo = ost.loss_and_grad(u0, tg, steps)
+    assert abs(L - Lo) <= 1e-5 * abs(Lo)
+    assert rel(uT, uTo) <= 1e-5 and rel(du, duo) <= 1e-5
+    for s in range(ck.shape[0]):  # checkpoints are the forward states
+        assert rel(ck[s], ost.forward(u0, s * every)) <= 1e-5
+
+
+def test_checkpoint_interval_does_not_change_gradient(dev):
+    u0, tg = workloads.stencil_inputs(64, 64, 2)
+    grads = [run(u0, tg, 100, e)[2] for e in (1, 7, 32, 100, 1000)]
+    for g in grads[1:]:
+        assert np.array_equal(g, grads[0])  # the gather-form adjoint is deterministic
+    lin = run(u0, tg, 100, 32, variant=1)[2]
+    assert np.array_equal(lin, grads[0])
+
+
+def test_scatter_form_adjoint(dev):
+    u0, tg = workloads.stencil_inputs(48, 40, 3)
+    g_gather = run(u0, tg, 30, 8)[2]
+    g_scatter = run(u0, tg, 30, 8, vcfg=2)[2]
+    assert rel(g_scatter, g_gather) <= 1e-6
+    assert rel(g_scatter, ost.loss_and_grad(u0, tg, 30)[2]) <= 1e-5
+
+
+@pytest.mark.parametrize("rho", [0.05, -0.2])
+def test_nonlinear_term_needs_recompute(dev, rho):
+    u0, tg = workloads.stencil_inputs(40, 36, 5)
+    L, uT, du, _ = run(u0, tg, 40, 6, rho=rho)
+    Lo, uTo, duo = ost.loss_and_grad(u0, tg, 40, rho=rho)
+    assert abs(L - Lo) <= 1e-5 * abs(Lo)
+    assert rel(uT, uTo) <= 1e-5 and rel(du, duo) <= 1e-5
+    du1 = run(u0, tg, 40, 1, rho=rho)[2]
+    assert np.array_equal(du1, du)
+
+
+def test_cotangent_scaling(dev):
+    u0, tg = workloads.stencil_inputs(16, 20, 6)
+    a = run(u0, tg, 10, 4)[2]
+    b = run(u0, tg, 10, 4, ct=-3.0)[2]
+    assert rel(b, -3.0 * a) <= 1e-6
+
+
+def fft_power(v, steps, c=0.2):
+    H, W = v.shape
+    p = np.arange(H)[:, None]
+    q = np.arange(W)[None, :]
+    lam = 1.0 + c * (2 * np.cos(2 * np.pi * p / H) + 2 * np.cos(2 * np.pi * q / W) - 4.0)
+    return np.real(np.fft.ifft2(lam ** steps * np.fft.fft2(v)))
+
+
+def test_full_size_against_closed_form(dev):
+    """4096 x 4096, 1000 steps, checkpoints every 32, as benchmarked."""
+    c = workloads.STENCIL
+    u0, tg = workloads.stencil_inputs(c["H"], c["W"], c["seed"])
+    L, uT, du, _ = run(u0, tg, c["steps"], c["every"])
+    uTo = fft_power(u0.astype(np.float64), c["steps"])
+    duo = fft_power(uTo - tg, c["steps"])
+    Lo = 0.5 * np.sum((uTo - tg) ** 2)
+    print(f"  full size: L rel {abs(L - Lo) / Lo:.2e} uT rel {rel(uT, uTo):.2e} "
+          f"grad rel {rel(du, duo):.2e}", flush=True)
+    assert abs(L - Lo) <= 1e-5 * Lo
+    assert rel(uT, uTo) <= 1e-5 and rel(du, duo) <= 1e-5

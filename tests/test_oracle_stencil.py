@@ -72,3 +72,26 @@ def test_planted_gauss_seidel_is_caught():
             u[y, x] = u[y, x] + 0.2 * (u[(y + 1) % H, x] + u[y - 1, x] + u[y, (x + 1) % W]
                                        + u[y, x - 1] - 4 * u[y, x])
     assert np.max(np.abs(u - fft_power(u0.astype(np.float64), H, W, 1))) > 1e-3
+
+
+@pytest.mark.parametrize("rho", [0.05, -0.3])
+def test_nonlinear_term_gradient_central_differences(rho):
+    u0, target = workloads.stencil_inputs(9, 12, 5)
+    u0 = u0.astype(np.float64)
+    _, _, grad = stencil.loss_and_grad(u0, target, 15, rho=rho)
+    for (y, x) in [(0, 0), (4, 7), (8, 11)]:
+        e = np.zeros_like(u0)
+        e[y, x] = 1e-6
+        up = stencil.loss_and_grad(u0 + e, target, 15, rho=rho)[0]
+        dn = stencil.loss_and_grad(u0 - e, target, 15, rho=rho)[0]
+        assert np.isclose((up - dn) / 2e-6, grad[y, x], rtol=1e-6, atol=1e-8)
+
+
+def test_nonlinear_step_adjoint_identity():
+    """The transposed step at state u is the adjoint of the linearized step."""
+    rng = np.random.default_rng(4)
+    u, du, v = rng.standard_normal((3, 10, 14))
+    # linearized step applied to du: diffusion part is linear, sin part gives cos(u) du
+    lin = stencil.step(du) + 0.2 * np.cos(u) * du
+    assert np.isclose(np.sum(lin * v), np.sum(du * stencil.step_transpose(v, u=u, rho=0.2)),
+                      rtol=1e-13)
