@@ -12,6 +12,6 @@ __all__ = ["dex", "autograd"]
 
 def __getattr__(name):
     if name == "autograd":
-        from . import autograd
-        return autograd
+        import importlib
+        return importlib.import_module(__name__ + ".autograd")
     raise AttributeError(name)

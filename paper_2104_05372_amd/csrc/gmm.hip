@@ -180,13 +180,14 @@ __global__ void __launch_bounds__(256) k_bwd_finalize(const TP* __restrict__ par
                                                       const T* __restrict__ alphas,
                                                       const T* __restrict__ qd,
                                                       const T* __restrict__ l,
+                                                      const T* __restrict__ means,
                                                       const T* __restrict__ ct,
                                                       T* __restrict__ d_alphas,
                                                       T* __restrict__ d_means, T* __restrict__ d_qd,
                                                       T* __restrict__ d_l, int accumulate) {
   const int k = blockIdx.x;
   bwd_finalize_comp<T, TP>(part + (size_t)k * E, (size_t)K * E, S, k, K, D, ld, N, alphas, qd, l,
-                           ct[0], d_alphas, d_means, d_qd, d_l, accumulate);
+                           means, ct[0], d_alphas, d_means, d_qd, d_l, accumulate);
 }
 
 }  // namespace dexk
@@ -434,7 +435,7 @@ dex_status gmm_vjp(const dex_desc& d, int cfg, const GmmPtrs& in, const void* f,
     hipLaunchKernelGGL((k_bwd_finalize<double, double>), dim3((unsigned)s.g.K), dim3(256), 0, st,
                        (const double*)ws, E, S, (int)s.g.K, (int)s.g.D, (int)s.g.D, s.g.N,
                        (const double*)in.alphas, (const double*)in.qd, (const double*)in.l,
-                       (const double*)ct, (double*)out.d_alphas, (double*)out.d_means,
+                       (const double*)nullptr, (const double*)ct, (double*)out.d_alphas, (double*)out.d_means,
                        (double*)out.d_qd, (double*)out.d_l, accumulate ? 1 : 0);
     return check_hip(hipGetLastError(), "gmm_vjp (VALU)");
   }
@@ -461,7 +462,7 @@ dex_status gmm_vjp(const dex_desc& d, int cfg, const GmmPtrs& in, const void* f,
   hipLaunchKernelGGL((k_bwd_finalize<float, float>), dim3((unsigned)s.g.K), dim3(256), 0, st,
                      (const float*)part, bwd_slot(s.g.DP), nch, (int)s.g.K, (int)s.g.D, s.g.DP,
                      s.g.N, (const float*)in.alphas, (const float*)in.qd, (const float*)in.l,
-                     (const float*)ct, (float*)out.d_alphas, (float*)out.d_means,
+                     (const float*)in.means, (const float*)ct, (float*)out.d_alphas, (float*)out.d_means,
                      (float*)out.d_qd, (float*)out.d_l, accumulate ? 1 : 0);
   return check_hip(hipGetLastError(), "gmm_vjp (MFMA)");
 }

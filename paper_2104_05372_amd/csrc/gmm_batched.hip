@@ -201,6 +201,7 @@ __global__ void __launch_bounds__(256) k_bbwd_finalize(const char* __restrict__ 
                                                        const char* ws, const float* __restrict__ alphas,
                                                        const float* __restrict__ qd,
                                                        const float* __restrict__ l,
+                                                       const float* __restrict__ means,
                                                        const float* __restrict__ ct,
                                                        float* __restrict__ d_alphas,
                                                        float* __restrict__ d_means,
@@ -213,7 +214,8 @@ __global__ void __launch_bounds__(256) k_bbwd_finalize(const char* __restrict__ 
   const size_t E = dexi::bwd_slot(I.DP);
   const float* part = (const float*)(ws + h->ws_part) + I.part_off + (size_t)w.a * E;
   bwd_finalize_comp<float, float>(part, (size_t)I.K * E, nch, w.a, I.K, I.D, I.DP, I.N,
-                                  alphas + I.a_off, qd + I.m_off, l + I.l_off, ct[w.inst],
+                                  alphas + I.a_off, qd + I.m_off, l + I.l_off, means + I.m_off,
+                                  ct[w.inst],
                                   d_alphas + I.a_off, d_means + I.m_off, d_qd + I.m_off,
                                   d_l + I.l_off, accumulate);
 }
@@ -485,7 +487,8 @@ dex_status gmm_batched_vjp(const dex_desc& d, int cfg, const void* plan, const G
   pr.end(1);
   hipLaunchKernelGGL(k_bbwd_finalize, dim3((unsigned)sumK), dim3(256), 0, st, pl, cfg,
                      (const char*)w, (const float*)in.alphas, (const float*)in.qd,
-                     (const float*)in.l, (const float*)ct, (float*)out.d_alphas,
+                     (const float*)in.l, (const float*)in.means, (const float*)ct,
+                     (float*)out.d_alphas,
                      (float*)out.d_means, (float*)out.d_qd, (float*)out.d_l, accumulate ? 1 : 0);
   return check_hip(hipGetLastError(), "gmm_batched_vjp");
 }

@@ -594,32 +594,20 @@ DEX_DEV void finalize_F_block(const T* __restrict__ fpart, int nparts, const T* 
 // Reverse, final step for component k: fixed-order compensated sum over the
 // S partial slots (stride `sstride` elements), then the gradient assembly.
 // Slot layout: M[a*ld + b] (a >= b), b[ld*ld + a], A at ld*ld + ld.
+// With `means` non-null the slots hold sum_i w y x~^T instead of M, and
+// M = that - b mu^T is formed here (the matrix-core reverse pass contracts
+// against x~, which does not depend on the component).
 template <typename T, typename TP>
 DEX_DEV void bwd_finalize_comp(const TP* __restrict__ part, size_t sstride, int S, int k, int K,
                                int D, int ld, int64_t N, const T* __restrict__ alphas,
-                               const T* __restrict__ qd, const T* __restrict__ l, T ctv,
-                               T* __restrict__ d_alphas, T* __restrict__ d_means,
-                               T* __restrict__ d_qd, T* __restrict__ d_l, int accumulate) {
+                               const T* __restrict__ qd, const T* __restrict__ l,
+                               const T* __restrict__ means, T ctv, T* __restrict__ d_alphas,
+                               T* __restrict__ d_means, T* __restrict__ d_qd, T* __restrict__ d_l,
+                               int accumulate) {
   __shared__ T bsh[64], mdiag[64], Ash;
   const int L = D * (D - 1) / 2;
   const int nM = D * (D + 1) / 2;
-  const int nE = nM + D + 1;
-  __syncthreads();
-  for (int e = threadIdx.x; e < nE; e += blockDim.x) {
-    size_t off;
-    int a = 0, b = 0;
-    if (e < nM) {
-      a = (int)((sqrtf(8.f * e + 1.f) - 1.f) * 0.5f);
-      while (a * (a + 1) / 2 > e) --a;
-      while ((a + 1) * (a + 2) / 2 <= e) ++a;
-      b = e - a * (a + 1) / 2;
-      off = (size_t)a * ld + b;
-    } else if (e < nM + D) {
-      a = e - nM;
-      off = (size_t)ld * ld + a;
-    } else {
-      off = (size_t)ld * ld + ld;
-    }
+  auto comp_sum = [&](size_t off) {
     T s = 0, err = 0;
     for (int sp = 0; sp < S; ++sp) {
       T ns, ne;
@@ -627,18 +615,28 @@ DEX_DEV void bwd_finalize_comp(const TP* __restrict__ part, size_t sstride, int 
       s = ns;
       err += ne;
     }
-    const T val = s + err;
-    if (e < nM) {
-      if (a > b) {
-        T* o = d_l + (size_t)k * L + a * (a - 1) / 2 + b;
-        *o = accumulate ? *o - val : -val;
-      } else {
-        mdiag[a] = val;
-      }
-    } else if (e < nM + D) {
-      bsh[a] = val;
+    return s + err;
+  };
+  __syncthreads();
+  for (int e = threadIdx.x; e <= D; e += blockDim.x) {
+    if (e < D)
+      bsh[e] = comp_sum((size_t)ld * ld + e);
+    else
+      Ash = comp_sum((size_t)ld * ld + ld);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nM; e += blockDim.x) {
+    int a = (int)((sqrtf(8.f * e + 1.f) - 1.f) * 0.5f);
+    while (a * (a + 1) / 2 > e) --a;
+    while ((a + 1) * (a + 2) / 2 <= e) ++a;
+    const int b = e - a * (a + 1) / 2;
+    T val = comp_sum((size_t)a * ld + b);
+    if (means) val -= bsh[a] * means[(size_t)k * D + b];
+    if (a > b) {
+      T* o = d_l + (size_t)k * L + a * (a - 1) / 2 + b;
+      *o = accumulate ? *o - val : -val;
     } else {
-      Ash = val;
+      mdiag[a] = val;
     }
   }
   __syncthreads();
