@@ -70,7 +70,7 @@ def timed(fn, steps, sync):
 
 
 # ---------------------------------------------------------------------------
-def gmm_setup(torch, dex, g, variant, dev):
+def gmm_setup(torch, dex, g, variant, dev, configs=None):
     t = [torch.tensor(a, device=dev) for a in (g.alphas, g.means, g.qd, g.l, g.x)]
     d = dex.gmm_desc(g.N, g.D, g.K, dex.DEX_F32, variant)
     F = torch.empty(1, device=dev)
@@ -80,15 +80,20 @@ def gmm_setup(torch, dex, g, variant, dev):
     wsb = dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_VJP), dev)
     ct = torch.ones(1, device=dev)
     grads = [torch.empty_like(x) for x in t[:4]]
-    bf = dex.dex_autotune(d, dex.DEX_WS_FWD, t, [F], [f, cache], [], [], wsf)
-    dex.dex_fwd(d, t, [F], [f, cache], wsf)
-    bb = dex.dex_autotune(d, dex.DEX_WS_VJP, t, [], [f, cache], [ct], grads, wsb)
+    if configs:
+        bf, bb = configs
+    else:
+        bf = dex.dex_autotune(d, dex.DEX_WS_FWD, t, [F], [f, cache], [], [], wsf)
+        dex.dex_fwd(d, t, [F], [f, cache], wsf)
+        bb = dex.dex_autotune(d, dex.DEX_WS_VJP, t, [], [f, cache], [ct], grads, wsb)
+    dfw = dex.gmm_desc(g.N, g.D, g.K, dex.DEX_F32, variant, bf)
+    dbw = dex.gmm_desc(g.N, g.D, g.K, dex.DEX_F32, variant, bb)
 
     def fwd():
-        dex.dex_fwd(d, t, [F], [f, cache], wsf)
+        dex.dex_fwd(dfw, t, [F], [f, cache], wsf)
 
     def vjp():
-        dex.dex_vjp(d, t, [f, cache], [ct], grads, 0, wsb)
+        dex.dex_vjp(dbw, t, [f, cache], [ct], grads, 0, wsb)
 
     return dict(t=t, d=d, F=F, grads=grads, fwd=fwd, vjp=vjp, cfg=(bf, bb))
 
@@ -97,7 +102,8 @@ def run_headline(torch, dex, workloads, args, dev):
     g = workloads.gmm_large()
     N, D, K = g.N, g.D, g.K
     variant = {"bf16": dex.DEX_GMM_BF16, "bf16x3": dex.DEX_GMM_BF16X3, "fp32": dex.DEX_GMM_PLAIN}[args.variant]
-    S = gmm_setup(torch, dex, g, variant, dev)
+    cfgs = tuple(int(v) for v in args.configs.split(",")) if args.configs else None
+    S = gmm_setup(torch, dex, g, variant, dev, cfgs)
     sync = torch.cuda.synchronize
 
     def step():
@@ -369,6 +375,8 @@ def main(argv=None):
     ap.add_argument("--variant", choices=["bf16", "bf16x3", "fp32"], default="bf16")
     ap.add_argument("--no-rows", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--configs", default=None,
+                    help="forward,reverse tile configuration (1-based); skips the autotuner")
     ap.add_argument("--rows-only", default=None, help="comma list of rows to run (scatter,hist,batched,stencil)")
     args = ap.parse_args(argv)
     if args.gpus != 1:

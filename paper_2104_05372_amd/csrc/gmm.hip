@@ -190,6 +190,16 @@ __global__ void __launch_bounds__(256) k_bwd_finalize(const TP* __restrict__ par
                            means, ct[0], d_alphas, d_means, d_qd, d_l, accumulate);
 }
 
+__global__ void __launch_bounds__(256) k_bwd_finalize_mom(
+    const float* __restrict__ part, size_t E, int S, int K, int D, int DP, int64_t N,
+    const float* __restrict__ alphas, const float* __restrict__ means, const float* __restrict__ qd,
+    const float* __restrict__ l, const float* __restrict__ ct, float* __restrict__ d_alphas,
+    float* __restrict__ d_means, float* __restrict__ d_qd, float* __restrict__ d_l, int accumulate) {
+  const int k = blockIdx.x;
+  bwd_finalize_mom(part + (size_t)k * E, (size_t)K * E, S, k, K, D, DP, N, alphas, means, qd, l,
+                   ct[0], d_alphas, d_means, d_qd, d_l, accumulate);
+}
+
 }  // namespace dexk
 
 // ===========================================================================
@@ -224,16 +234,16 @@ Shape shape_of(const dex_desc& d) {
 const FwdCfg kFwdBF[] = {{4, 1, 32}, {4, 2, 32}, {2, 1, 32}, {4, 1, 16}, {4, 2, 16}, {2, 2, 32}};
 const FwdCfg kFwdF32[] = {{4, 1, 16}, {4, 2, 16}, {2, 1, 16}, {2, 2, 16}};
 // reverse candidates: (points per tile / 16, components per wave, chunk depth, point chunks)
-const BwdCfg kBwdBF[] = {{4, 2, 32, 16}, {4, 1, 32, 16}, {2, 2, 32, 16}, {4, 2, 32, 32},
-                         {4, 1, 32, 32}, {4, 2, 16, 16}, {4, 1, 16, 32}, {4, 2, 32, 8}};
-const BwdCfg kBwdF32[] = {{4, 1, 16, 16}, {4, 2, 16, 16}, {2, 2, 16, 16}, {4, 1, 16, 32},
-                          {2, 2, 16, 32}};
+// reverse candidates: (components per wave, point chunks)
+const BwdCfg kBwdBF[] = {{2, 16}, {2, 32}, {4, 16}, {4, 32}, {1, 16}, {1, 32}, {2, 8}, {4, 8}};
+const BwdCfg kBwdF32[] = {{2, 16}, {1, 16}, {4, 16}, {2, 32}, {1, 32}};
 constexpr int kMaxSk = 2;
 constexpr int kMaxS = 32;
 constexpr int kValuS = 16;
 
 int nfwd(const Shape& s) { return s.prec == PREC_F32 ? 4 : 6; }
 int nbwd(const Shape& s) { return s.prec == PREC_F32 ? 5 : 8; }
+size_t mom_es(const Shape& s) { return s.prec == PREC_F32 ? 4 : 2; }
 FwdCfg fwd_cfg(const Shape& s, int i) { return s.prec == PREC_F32 ? kFwdF32[i] : kFwdBF[i]; }
 BwdCfg bwd_cfg(const Shape& s, int i) { return s.prec == PREC_F32 ? kBwdF32[i] : kBwdBF[i]; }
 
@@ -255,8 +265,8 @@ CacheLayout cache_layout(const Shape& s) {
     const bool lo = s.prec == PREC_BF16X3;
     c.xh = take(g.Npad * g.DP * es);
     c.xl = lo ? take(g.Npad * g.DP * es) : 0;
-    c.xhT = take(g.Npad * g.DP * es);
-    c.xlT = lo ? take(g.Npad * g.DP * es) : 0;
+    c.xhT = take(g.Npad * g.DP * mom_es(s));
+    c.xlT = lo ? take(g.Npad * g.DP * mom_es(s)) : 0;
     c.Qh = take(g.K * g.DP * g.DP * es);
     c.Ql = lo ? take(g.K * g.DP * g.DP * es) : 0;
     c.negc = take(g.K * g.DP * 4);
@@ -350,7 +360,7 @@ size_t gmm_ws_bytes(const dex_desc& d, int role) {
     if (s.mfma) b += align256((size_t)kMaxSk * s.g.Npad * sizeof(float2));
     return b;
   }
-  if (s.mfma) return align256((size_t)kMaxS * s.g.K * bwd_slot(s.g.DP) * 4);
+  if (s.mfma) return align256((size_t)kMaxS * s.g.K * mom_slot(s.g.DP) * 4);
   return align256((size_t)kValuS * s.g.K * (s.g.D * s.g.D + s.g.D + 1) * s.tsize);
 }
 
@@ -459,11 +469,11 @@ dex_status gmm_vjp(const dex_desc& d, int cfg, const GmmPtrs& in, const void* f,
   int64_t chunk;
   int nch;
   bwd_chunks(s.g.Npad, c.s, &chunk, &nch);
-  hipLaunchKernelGGL((k_bwd_finalize<float, float>), dim3((unsigned)s.g.K), dim3(256), 0, st,
-                     (const float*)part, bwd_slot(s.g.DP), nch, (int)s.g.K, (int)s.g.D, s.g.DP,
-                     s.g.N, (const float*)in.alphas, (const float*)in.qd, (const float*)in.l,
-                     (const float*)in.means, (const float*)ct, (float*)out.d_alphas, (float*)out.d_means,
-                     (float*)out.d_qd, (float*)out.d_l, accumulate ? 1 : 0);
+  hipLaunchKernelGGL(k_bwd_finalize_mom, dim3((unsigned)s.g.K), dim3(256), 0, st, (const float*)part,
+                     mom_slot(s.g.DP), nch, (int)s.g.K, (int)s.g.D, s.g.DP, s.g.N,
+                     (const float*)in.alphas, (const float*)in.means, (const float*)in.qd,
+                     (const float*)in.l, (const float*)ct, (float*)out.d_alphas,
+                     (float*)out.d_means, (float*)out.d_qd, (float*)out.d_l, accumulate ? 1 : 0);
   return check_hip(hipGetLastError(), "gmm_vjp (MFMA)");
 }
 

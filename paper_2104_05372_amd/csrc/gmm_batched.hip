@@ -37,11 +37,11 @@ struct BItem {
 constexpr int kBFwdCfgs = 2;
 constexpr int kBBwdCfgs = 4;
 struct BBwd {
-  int pb, gw;
+  int gw;
   int64_t chunk;
 };
 __host__ __device__ inline BBwd bbwd_cfg(int i) {
-  const BBwd t[kBBwdCfgs] = {{4, 1, 4096}, {4, 2, 4096}, {2, 2, 2048}, {4, 1, 8192}};
+  const BBwd t[kBBwdCfgs] = {{2, 4096}, {1, 4096}, {2, 2048}, {4, 8192}};
   return t[i];
 }
 __host__ __device__ inline int bfwd_cb(int i) { return i == 0 ? 4 : 2; }
@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(256) k_bfinalize_F(const char* __restrict__ pl
   finalize_F_block<float>(fpart, I.nblk, alphas + I.a_off, I.K, I.N, F + blockIdx.x);
 }
 
-template <int PB, int GW>
+template <int GW>
 __global__ void __launch_bounds__(256) k_bgmm_bwd(const char* __restrict__ plan, int cfg,
                                                   const char* cache, const float* __restrict__ f,
                                                   const float* __restrict__ ct, char* ws) {
@@ -182,18 +182,17 @@ __global__ void __launch_bounds__(256) k_bgmm_bwd(const char* __restrict__ plan,
     if (it >= n) break;
     const BItem w = items[it];
     const BInst I = inst[w.inst];
-    const MfmaOps o = bops(I, cache);
     const float* beta = (const float*)(cache + I.beta_off);
     const int pbeg = (int)(w.b * chunk);
     const int pend = (int)std::min<int64_t>(I.Npad, pbeg + chunk);
-    const size_t E = dexi::bwd_slot(I.DP);
+    const size_t E = mom_slot(I.DP);
     float* P = part + I.part_off + (size_t)w.b * I.K * E;
     if (I.DP == 16)
-      bwd_unit<16, PREC_F32, PB, GW, 16>(o, I.N, (int)I.Npad, I.K, w.a * 4 * GW, pbeg, pend, beta,
-                                         f + I.f_off, ct[w.inst], P, E);
+      bwd_mom_unit<16, MP_F32, GW>(cache + I.xhT_off, nullptr, I.N, (int)I.Npad, I.K, w.a * 4 * GW,
+                                   pbeg, pend, beta, f + I.f_off, ct[w.inst], P, E);
     else
-      bwd_unit<32, PREC_F32, PB, GW, 16>(o, I.N, (int)I.Npad, I.K, w.a * 4 * GW, pbeg, pend, beta,
-                                         f + I.f_off, ct[w.inst], P, E);
+      bwd_mom_unit<32, MP_F32, GW>(cache + I.xhT_off, nullptr, I.N, (int)I.Npad, I.K, w.a * 4 * GW,
+                                   pbeg, pend, beta, f + I.f_off, ct[w.inst], P, E);
   }
 }
 
@@ -211,13 +210,11 @@ __global__ void __launch_bounds__(256) k_bbwd_finalize(const char* __restrict__ 
   const BItem w = ((const BItem*)(plan + h->prepq_off))[blockIdx.x];  // (instance, k)
   const BInst I = ((const BInst*)(plan + h->inst_off))[w.inst];
   const int nch = ((const int32_t*)(plan + h->nch_off))[cfg * h->B + w.inst];
-  const size_t E = dexi::bwd_slot(I.DP);
+  const size_t E = mom_slot(I.DP);
   const float* part = (const float*)(ws + h->ws_part) + I.part_off + (size_t)w.a * E;
-  bwd_finalize_comp<float, float>(part, (size_t)I.K * E, nch, w.a, I.K, I.D, I.DP, I.N,
-                                  alphas + I.a_off, qd + I.m_off, l + I.l_off, means + I.m_off,
-                                  ct[w.inst],
-                                  d_alphas + I.a_off, d_means + I.m_off, d_qd + I.m_off,
-                                  d_l + I.l_off, accumulate);
+  bwd_finalize_mom(part, (size_t)I.K * E, nch, w.a, I.K, I.D, I.DP, I.N, alphas + I.a_off,
+                   means + I.m_off, qd + I.m_off, l + I.l_off, ct[w.inst], d_alphas + I.a_off,
+                   d_means + I.m_off, d_qd + I.m_off, d_l + I.l_off, accumulate);
 }
 
 }  // namespace dexk
@@ -283,7 +280,7 @@ PlanBuild build_plan(const int64_t* shapes, int64_t B) {
       maxch = std::max(maxch, ch);
     }
     I.part_off = part;
-    part += maxch * I.K * (int64_t)bwd_slot(I.DP);
+    part += maxch * I.K * (int64_t)mom_slot(I.DP);
     part = (part + 63) / 64 * 64;
     for (int t = 0; t < I.Npad / 64; ++t) p.prepx.push_back({(int32_t)b, t, 0, 0});
     for (int k = 0; k < I.K; ++k) p.prepq.push_back({(int32_t)b, k, 0, 0});
@@ -317,7 +314,8 @@ PlanBuild build_plan(const int64_t* shapes, int64_t B) {
           const int64_t pts = std::min<int64_t>(bc.chunk, I.Npad - s * bc.chunk);
           // the busiest wave of the block bounds the item's time
           const int64_t per_wave = std::min(bc.gw, kk);
-          v.push_back({per_wave * pts * (dp_cost(I.DP) + (I.DP == 16 ? 1 : 3)),
+          // moment blocks per 32 points: 1 (DP = 16) or 3 (DP = 32)
+          v.push_back({per_wave * pts * (I.DP == 16 ? 1 : 3),
                        BItem{(int32_t)b, g, s, 0}});
         }
       }
@@ -473,16 +471,16 @@ dex_status gmm_batched_vjp(const dex_desc& d, int cfg, const void* plan, const G
   char* w = (char*)ws;
   const BBwd bc = bbwd_cfg(cfg);
   hipLaunchKernelGGL(fill_counters, dim3(1), dim3(64), 0, st, (int*)w, 64);
-#define DEX_BB(PB_, GW_)                                                                     \
-  hipLaunchKernelGGL((k_bgmm_bwd<PB_, GW_>), dim3(persistent_blocks()), dim3(256), 0, st, pl, \
+#define DEX_BB(GW_)                                                                     \
+  hipLaunchKernelGGL((k_bgmm_bwd<GW_>), dim3(persistent_blocks()), dim3(256), 0, st, pl, \
                      cfg, (const char*)cache, (const float*)f, (const float*)ct, w)
   ProfRange pr(DEX_PROF_BGMM_VJP, st);
-  if (bc.pb == 4 && bc.gw == 1)
-    DEX_BB(4, 1);
-  else if (bc.pb == 4)
-    DEX_BB(4, 2);
+  if (bc.gw == 1)
+    DEX_BB(1);
+  else if (bc.gw == 2)
+    DEX_BB(2);
   else
-    DEX_BB(2, 2);
+    DEX_BB(4);
 #undef DEX_BB
   pr.end(1);
   hipLaunchKernelGGL(k_bbwd_finalize, dim3((unsigned)sumK), dim3(256), 0, st, pl, cfg,

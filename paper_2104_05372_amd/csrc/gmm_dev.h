@@ -251,10 +251,71 @@ DEX_DEV void treduce_groups(float (&v)[NV]) {
   }
 }
 
+// Reverse pass as weighted moments. With y = Q~(x~ - mu) and r = x~ - mu, the
+// accumulated cotangent of Q_k is M_k = sum_i w y r^T = Q~_k C_k with
+// C_k = sum_i w (x~ - mu)(x~ - mu)^T = S_k - u mu^T - mu u^T + A mu mu^T, where
+//   S_k = sum_i w_ik x~_i x~_i^T,  u_k = sum_i w_ik x~_i,  A_k = sum_i w_ik.
+// So the per-point work of the reverse pass is the symmetric weighted second
+// moment S_k (a regular segmented reduction over i for each k, Sec. 6.1.3) plus
+// u_k and A_k; Y is not recomputed. The D x D products with Q_k are done once
+// per component in the final step.
+enum { MP_F32 = 0, MP_F16 = 1, MP_F16X3 = 2 };
+template <int PREC>
+struct MomOf {
+  static constexpr int MP = PREC == PREC_F32 ? MP_F32 : PREC == PREC_BF16 ? MP_F16 : MP_F16X3;
+};
+template <int MP>
+struct MomT {
+  using S = _Float16;
+  typedef _Float16 V8 __attribute__((ext_vector_type(8)));
+  typedef _Float16 V4 __attribute__((ext_vector_type(4)));
+  typedef _Float16 V2 __attribute__((ext_vector_type(2)));
+  static constexpr int NS = MP == MP_F16X3 ? 2 : 1;
+};
+template <>
+struct MomT<MP_F32> {
+  using S = float;
+  typedef float V8 __attribute__((ext_vector_type(8)));
+  typedef float V4 __attribute__((ext_vector_type(4)));
+  typedef float V2 __attribute__((ext_vector_type(2)));
+  static constexpr int NS = 1;
+};
+
+template <int MP>
+DEX_DEV void mom_store(typename MomT<MP>::S* hi, typename MomT<MP>::S* lo, size_t off, float v) {
+  if constexpr (MP == MP_F32) {
+    hi[off] = v;
+  } else {
+    const _Float16 h = (_Float16)v;
+    hi[off] = h;
+    if constexpr (MP == MP_F16X3) lo[off] = (_Float16)(v - (float)h);
+  }
+}
+
+template <int MP>
+DEX_DEV f32x4 mom_mma1(const typename MomT<MP>::V8& a, const typename MomT<MP>::V8& b, f32x4 c) {
+  if constexpr (MP == MP_F32) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], c, 0, 0, 0);
+  } else {
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  return c;
+}
+
+// Number of Q~ contraction chunks (depth CK) that meet the lower triangle.
+__host__ __device__ constexpr int fwd_nq(int DP, int CK) {
+  int n = 0;
+  for (int rb = 0; rb < DP / 16; ++rb)
+    for (int ch = 0; ch < DP / CK; ++ch)
+      if (CK * ch <= 16 * rb + 15) ++n;
+  return n;
+}
+
 // Operand cache of one instance (FP32 storage, matrix-core forms).
 struct MfmaOps {
   const void *xh, *xl;    // x~   [Npad x DP]
-  const void *xhT, *xlT;  // x~^T [DP x Npad]
+  const void *xhT, *xlT;  // x~^T [DP x Npad], moment precision (FP16 or FP32)
   const void *Qh, *Ql;    // Q~   [K x DP x DP]
   const float* negc;      // -c~  [K x DP]
   const float* kappa;     // alphas[k] + sum_d qd[k,d]   [K]
@@ -266,7 +327,8 @@ struct MfmaOps {
 template <int PREC, int DP>
 DEX_DEV void prep_x_tile(const float* __restrict__ x, int N, int D, int Npad, int p0,
                          typename Store<PREC>::S* xh, typename Store<PREC>::S* xl,
-                         typename Store<PREC>::S* xhT, typename Store<PREC>::S* xlT) {
+                         typename MomT<MomOf<PREC>::MP>::S* xhT,
+                         typename MomT<MomOf<PREC>::MP>::S* xlT) {
   __shared__ float tile[64][DP + 1];
   __syncthreads();
   for (int e = threadIdx.x; e < 64 * DP; e += blockDim.x) {
@@ -280,7 +342,7 @@ DEX_DEV void prep_x_tile(const float* __restrict__ x, int N, int D, int Npad, in
   }
   for (int e = threadIdx.x; e < 64 * DP; e += blockDim.x) {
     int b = e / 64, pp = e % 64;
-    store_split<PREC>(xhT, xlT, (size_t)b * Npad + p0 + pp, tile[pp][b]);
+    mom_store<MomOf<PREC>::MP>(xhT, xlT, (size_t)b * Npad + p0 + pp, tile[pp][b]);
   }
 }
 
@@ -359,25 +421,55 @@ DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0blk, int k0, in
     owner = g == 0;
   }
   float m = -INFINITY, lsum = 0.f;
+  if (k0 >= k1) {
+    if (owner) ml[p] = make_float2(m, lsum);
+    return;
+  }
+
+  // operands of component k: the Q~ chunks that meet the lower triangle, -c~
+  // and kappa; those of k+1 are loaded while k is computed
+  constexpr int NQ = fwd_nq(DP, CK);
+  Op<PREC, NV> qa[NQ];
+  f32x4 ci[NRB];
+  float kap;
+  auto load_k = [&](int k, Op<PREC, NV>(&q)[NQ], f32x4(&cc)[NRB], float& kp) {
+    const size_t qoff = (size_t)k * DP * DP;
+    int n = 0;
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+        if (CK * ch <= 16 * rb + 15)
+          q[n++] = load_op<PREC, NV>(Qh + qoff, Ql ? Ql + qoff : nullptr,
+                                     (size_t)(16 * rb + c) * DP + CK * ch + NV * g);
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+      cc[rb] = *reinterpret_cast<const f32x4*>(ops.negc + (size_t)k * DP + 16 * rb + 4 * g);
+    kp = ops.kappa[k];
+  };
+  load_k(k0, qa, ci, kap);
 
   for (int k = k0; k < k1; ++k) {
-    const size_t qoff = (size_t)k * DP * DP;
+    Op<PREC, NV> qn[NQ];
+    f32x4 cn[NRB];
+    float kn;
+    load_k(k + 1 < k1 ? k + 1 : k, qn, cn, kn);
     f32x4 acc[CB][NRB];
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb) {
-      const f32x4 ci = *reinterpret_cast<const f32x4*>(ops.negc + (size_t)k * DP + 16 * rb + 4 * g);
+    for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) acc[cb][rb] = ci;
-    }
+      for (int cb = 0; cb < CB; ++cb) acc[cb][rb] = ci[rb];
+    {
+      int n = 0;
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb) {
+      for (int rb = 0; rb < NRB; ++rb) {
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) {
-        if (CK * ch > 16 * rb + 15) continue;  // chunk wholly above the diagonal
-        const Op<PREC, NV> qa =
-            load_op<PREC, NV>(Qh + qoff, Ql ? Ql + qoff : nullptr, (size_t)(16 * rb + c) * DP + CK * ch + NV * g);
+        for (int ch = 0; ch < NCH; ++ch) {
+          if (CK * ch > 16 * rb + 15) continue;  // chunk wholly above the diagonal
+          const Op<PREC, NV>& q = qa[n++];
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) acc[cb][rb] = mma<PREC, NV>(qa, xb[cb][ch], acc[cb][rb]);
+          for (int cb = 0; cb < CB; ++cb) acc[cb][rb] = mma<PREC, NV>(q, xb[cb][ch], acc[cb][rb]);
+        }
       }
     }
     float s[CB];
@@ -391,7 +483,7 @@ DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0blk, int k0, in
       s[cb] = t;
     }
     treduce_groups<CB>(s);
-    const float b = ops.kappa[k] - 0.5f * s[0];
+    const float b = kap - 0.5f * s[0];
     if (owner && p < N) beta[(size_t)k * Npad + p] = b;
     const float d = b - m;
     if (d > 0.f) {
@@ -400,125 +492,146 @@ DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0blk, int k0, in
     } else {
       lsum += __expf(d);
     }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) qa[q] = qn[q];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) ci[rb] = cn[rb];
+    kap = kn;
   }
   if (owner) ml[p] = make_float2(m, lsum);
 }
 
 // ---------------------------------------------------------------------------
-// Reverse unit: wave wv handles components kbase+wv*GW .. +GW-1 over the points
-// [pbeg, pend), in tiles of 16*PB. Y (points x DP) = X~ Q~_k^T - c~ is
-// recomputed with points as rows, so a lane holds column a = 16 ab + c of rows
-// p = 16 pb + 4 g + i. Scaled by w, these registers are directly the B operand
-// of the weighted outer product
-//   M_k^T (DP x DP) += X~^T (DP x 32) (w Y) (32 x DP)
-// over 32-point chunks, where lane group g's contraction values are the points
-// {4g..4g+3, 16+4g..16+4g+3}; the A operand X~^T is loaded to match.
-// Partials per component: M (row stride DP, rows a >= b written), b at DP*DP,
-// A at DP*DP + DP; `part` points at the (chunk, component 0) slot, `pstride`
-// floats apart per component.
-template <int DP, int PREC, int PB, int GW, int CK>
-DEX_DEV void bwd_unit(const MfmaOps& ops, int N, int Npad, int K, int kbase, int pbeg, int pend,
-                      const float* __restrict__ beta, const float* __restrict__ f, float ctv,
-                      float* __restrict__ part, size_t pstride) {
-  using S = typename Store<PREC>::S;
-  constexpr int NV = CK / 4;
-  constexpr int NAB = DP / 16, NCH = DP / CK, NJ = PB / 2;
-  constexpr int NBLK = NAB * (NAB + 1) / 2;
+// Partial slot of one (point chunk, component): the lower 16x16 blocks of S in
+// matrix-core output order (block q = ab(ab+1)/2 + bb, then lane, then row i),
+// u at NBLK*256, A at NBLK*256 + DP; padded to a multiple of 4 floats.
+__host__ __device__ inline size_t mom_slot(int DP) {
+  const int nb = DP / 16;
+  return (size_t)(nb * (nb + 1) / 2) * 256 + DP + 4;
+}
+
+// Wave wv accumulates S, u, A for components kbase+wv*GW .. +GW-1 over the
+// points [pbeg, pend), 32 per step. Both operands come from x~^T: lane 16 g + c
+// holds feature row 16 bb + c and the points {4g..4g+3, 16+4g..16+4g+3} of the
+// step, in the order the matrix-core contraction pairs them; the A operand is
+// that row scaled by the point weights, the B operand the unscaled row.
+template <int DP, int MP, int GW>
+DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad, int K, int kbase,
+                          int pbeg, int pend, const float* __restrict__ beta,
+                          const float* __restrict__ f, float ctv, float* __restrict__ part,
+                          size_t pstride) {
+  using MT = MomT<MP>;
+  using S = typename MT::S;
+  using V8 = typename MT::V8;
+  using V4 = typename MT::V4;
+  constexpr int NB = DP / 16, NBLK = NB * (NB + 1) / 2, NS = MT::NS;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
   const int kw = kbase + wv * GW;
   if (kw >= K) return;
-  const S* xh = (const S*)ops.xh;
-  const S* xl = (const S*)ops.xl;
-  const S* xhT = (const S*)ops.xhT;
-  const S* xlT = (const S*)ops.xlT;
-  const S* Qh = (const S*)ops.Qh;
-  const S* Ql = (const S*)ops.Ql;
-  __shared__ float wsh[4][64];
+  const S* xh = (const S*)xT_hi;
+  const S* xl = (const S*)xT_lo;
+  __shared__ float wsh[4][32];
 
-  f32x4 macc[GW][NBLK];
-  float bacc[GW][NAB];
+  f32x4 sacc[GW][NBLK];
+  float uacc[GW][NB];
   float aacc[GW];
 #pragma unroll
   for (int gk = 0; gk < GW; ++gk) {
 #pragma unroll
-    for (int q = 0; q < NBLK; ++q) macc[gk][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < NBLK; ++q) sacc[gk][q] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ab = 0; ab < NAB; ++ab) bacc[gk][ab] = 0.f;
+    for (int ab = 0; ab < NB; ++ab) uacc[gk][ab] = 0.f;
     aacc[gk] = 0.f;
   }
 
-  for (int t0 = pbeg; t0 < pend; t0 += 16 * PB) {
-    Op<PREC, NV> xa[PB][NCH];
+  for (int t0 = pbeg; t0 < pend; t0 += 32) {
+    V8 xt[NB][NS];
 #pragma unroll
-    for (int pb = 0; pb < PB; ++pb)
+    for (int bb = 0; bb < NB; ++bb) {
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch)
-        xa[pb][ch] = load_op<PREC, NV>(xh, xl, (size_t)(t0 + 16 * pb + c) * DP + CK * ch + NV * g);
-    Op<PREC, 8> xt[NAB][NJ];
+      for (int s = 0; s < NS; ++s) {
+        const S* base = (s == 0 ? xh : xl) + (size_t)(16 * bb + c) * Npad + t0 + 4 * g;
+        const V4 a = *reinterpret_cast<const V4*>(base);
+        const V4 b = *reinterpret_cast<const V4*>(base + 16);
 #pragma unroll
-    for (int bb = 0; bb < NAB; ++bb)
-#pragma unroll
-      for (int j = 0; j < NJ; ++j)
-        xt[bb][j] = load_op_split<PREC>(xhT, xlT, (size_t)(16 * bb + c) * Npad + t0 + 32 * j + 4 * g);
-    const int pown = t0 + lane;
-    const bool vown = lane < 16 * PB && pown < N;
+        for (int e = 0; e < 4; ++e) {
+          xt[bb][s][e] = a[e];
+          xt[bb][s][e + 4] = b[e];
+        }
+      }
+    }
+    const int pown = t0 + (lane & 31);
+    const bool vown = pown < N;
     const float fown = vown ? f[pown] : 0.f;
-
 #pragma unroll
     for (int gk = 0; gk < GW; ++gk) {
       const int k = kw + gk;
       if (k >= K) break;
-      const size_t qoff = (size_t)k * DP * DP;
-      f32x4 acc[PB][NAB];
-#pragma unroll
-      for (int ab = 0; ab < NAB; ++ab) {
-        const float nc = ops.negc[(size_t)k * DP + 16 * ab + c];
-#pragma unroll
-        for (int pb = 0; pb < PB; ++pb) acc[pb][ab] = f32x4{nc, nc, nc, nc};
+      const float w = vown ? __expf(beta[(size_t)k * Npad + pown] - fown) * ctv : 0.f;
+      if (lane < 32) {
+        aacc[gk] += w;
+        wsh[wv][lane] = w;
       }
-#pragma unroll
-      for (int ab = 0; ab < NAB; ++ab) {
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-          if (CK * ch > 16 * ab + 15) continue;
-          const Op<PREC, NV> qb =
-              load_op<PREC, NV>(Qh + qoff, Ql ? Ql + qoff : nullptr, (size_t)(16 * ab + c) * DP + CK * ch + NV * g);
-#pragma unroll
-          for (int pb = 0; pb < PB; ++pb) acc[pb][ab] = mma<PREC, NV>(xa[pb][ch], qb, acc[pb][ab]);
-        }
-      }
-      // w for the point this lane owns, then broadcast through LDS to the
-      // lanes holding that point's row of Y
-      float w = 0.f;
-      if (vown) w = __expf(beta[(size_t)k * Npad + pown] - fown) * ctv;
-      aacc[gk] += w;
-      wsh[wv][lane] = w;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      f32x4 wr[PB];
-#pragma unroll
-      for (int pb = 0; pb < PB; ++pb) wr[pb] = *reinterpret_cast<const f32x4*>(&wsh[wv][16 * pb + 4 * g]);
+      const f32x4 w0 = *reinterpret_cast<const f32x4*>(&wsh[wv][4 * g]);
+      const f32x4 w1 = *reinterpret_cast<const f32x4*>(&wsh[wv][16 + 4 * g]);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
+      float w8[8];
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
+      for (int e = 0; e < 4; ++e) {
+        w8[e] = w0[e];
+        w8[e + 4] = w1[e];
+      }
 #pragma unroll
-        for (int ab = 0; ab < NAB; ++ab) {
-          float v[8];
+      for (int ab = 0; ab < NB; ++ab) {
+        V8 sa[NS];
+        if constexpr (MP == MP_F32) {
+          float ut = 0.f;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            v[e] = acc[2 * j][ab][e] * wr[2 * j][e];
-            v[e + 4] = acc[2 * j + 1][ab][e] * wr[2 * j + 1][e];
+          for (int e = 0; e < 8; ++e) {
+            sa[0][e] = xt[ab][0][e] * w8[e];
+            ut = fmaf(xt[ab][0][e], w8[e], ut);
           }
-          float t = 0.f;
+          uacc[gk][ab] += ut;
+        } else if constexpr (MP == MP_F16) {
+          V8 wh;
 #pragma unroll
-          for (int e = 0; e < 8; ++e) t += v[e];
-          bacc[gk][ab] += t;
-          const Op<PREC, 8> wy = to_op<PREC>(v);
-          const int q = ab * (ab + 1) / 2;
+          for (int e = 0; e < 8; ++e) wh[e] = (_Float16)w8[e];
+          sa[0] = xt[ab][0] * wh;
+          float ut = uacc[gk][ab];
 #pragma unroll
-          for (int bb = 0; bb <= ab; ++bb) macc[gk][q + bb] = mma<PREC, 8>(xt[bb][j], wy, macc[gk][q + bb]);
+          for (int e = 0; e < 8; e += 2) {
+            typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+            const h2 xa{xt[ab][0][e], xt[ab][0][e + 1]};
+            const h2 wa{wh[e], wh[e + 1]};
+            ut = __builtin_amdgcn_fdot2(xa, wa, ut, false);
+          }
+          uacc[gk][ab] = ut;
+        } else {
+          float ut = 0.f;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float xv = (float)xt[ab][0][e] + (float)xt[ab][1][e];
+            const float v = xv * w8[e];
+            ut = fmaf(xv, w8[e], ut);
+            const _Float16 h = (_Float16)v;
+            sa[0][e] = h;
+            sa[1][e] = (_Float16)(v - (float)h);
+          }
+          uacc[gk][ab] += ut;
+        }
+        const int q0 = ab * (ab + 1) / 2;
+#pragma unroll
+        for (int bb = 0; bb <= ab; ++bb) {
+          f32x4 acc = sacc[gk][q0 + bb];
+          if constexpr (MP == MP_F16X3) {
+            acc = mom_mma1<MP>(sa[1], xt[bb][0], acc);
+            acc = mom_mma1<MP>(sa[0], xt[bb][1], acc);
+          }
+          sacc[gk][q0 + bb] = mom_mma1<MP>(sa[0], xt[bb][0], acc);
         }
       }
     }
@@ -530,19 +643,112 @@ DEX_DEV void bwd_unit(const MfmaOps& ops, int N, int Npad, int K, int kbase, int
     if (k >= K) break;
     float* P = part + (size_t)k * pstride;
 #pragma unroll
-    for (int ab = 0; ab < NAB; ++ab) {
-      const int q = ab * (ab + 1) / 2;
+    for (int q = 0; q < NBLK; ++q) *reinterpret_cast<f32x4*>(&P[q * 256 + lane * 4]) = sacc[gk][q];
 #pragma unroll
-      for (int bb = 0; bb <= ab; ++bb)
-        *reinterpret_cast<f32x4*>(&P[(size_t)(16 * ab + c) * DP + 16 * bb + 4 * g]) = macc[gk][q + bb];
-      float bv = bacc[gk][ab];
-      bv += xor_lane(bv, 16);
-      bv += xor_lane(bv, 32);
-      if (g == 0) P[DP * DP + 16 * ab + c] = bv;
+    for (int ab = 0; ab < NB; ++ab) {
+      float uv = uacc[gk][ab];
+      uv += xor_lane(uv, 16);
+      uv += xor_lane(uv, 32);
+      if (g == 0) P[NBLK * 256 + 16 * ab + c] = uv;
     }
     const float av = wave_sum(aacc[gk]);
-    if (lane == 0) P[DP * DP + DP] = av;
+    if (lane == 0) P[NBLK * 256 + DP] = av;
   }
+}
+
+// Final step of the moment form for component k: fixed-order compensated sums
+// over the S partial slots, C_k, then M_k = Q_k C_k and the gradient assembly
+// (FP32 Q_k from qd and l).
+DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, int S, int k, int K,
+                              int D, int DP, int64_t N, const float* __restrict__ alphas,
+                              const float* __restrict__ means, const float* __restrict__ qd,
+                              const float* __restrict__ l, float ctv, float* __restrict__ d_alphas,
+                              float* __restrict__ d_means, float* __restrict__ d_qd,
+                              float* __restrict__ d_l, int accumulate) {
+  __shared__ float C[64][65], Qs[64][65];
+  __shared__ float us[64], mus[64], bq[64], Ash;
+  const int NB = DP / 16, NBLK = NB * (NB + 1) / 2;
+  const int L = D * (D - 1) / 2;
+  auto comp_sum = [&](size_t off) {
+    float s = 0.f, err = 0.f;
+    for (int sp = 0; sp < S; ++sp) {
+      float ns, ne;
+      two_sum<float>(s, part[(size_t)sp * sstride + off], ns, ne);
+      s = ns;
+      err += ne;
+    }
+    return s + err;
+  };
+  __syncthreads();
+  for (int e = threadIdx.x; e <= D; e += blockDim.x) {
+    if (e < D) {
+      us[e] = comp_sum((size_t)NBLK * 256 + e);
+      mus[e] = means[(size_t)k * D + e];
+    } else {
+      Ash = comp_sum((size_t)NBLK * 256 + DP);
+    }
+  }
+  for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
+    const int a = e / D, b = e % D;
+    float q = 0.f;
+    if (a == b)
+      q = expf(qd[(size_t)k * D + a]);
+    else if (a > b)
+      q = l[(size_t)k * L + a * (a - 1) / 2 + b];
+    Qs[a][b] = q;
+  }
+  __syncthreads();
+  const float A = Ash;
+  for (int e = threadIdx.x; e < NBLK * 256; e += blockDim.x) {
+    const int q = e >> 8, ln = (e >> 2) & 63, i = e & 3;
+    int ab = 0;
+    while ((ab + 1) * (ab + 2) / 2 <= q) ++ab;
+    const int bb = q - ab * (ab + 1) / 2;
+    const int r = 16 * bb + (ln & 15), s = 16 * ab + 4 * (ln >> 4) + i;
+    if (r >= D || s >= D || r > s) continue;
+    const float v = comp_sum((size_t)e) - us[r] * mus[s] - mus[r] * us[s] + A * mus[r] * mus[s];
+    C[r][s] = v;
+    C[s][r] = v;
+  }
+  __syncthreads();
+  const int nM = D * (D + 1) / 2;
+  for (int e = threadIdx.x; e < nM; e += blockDim.x) {
+    int a = (int)((sqrtf(8.f * e + 1.f) - 1.f) * 0.5f);
+    while (a * (a + 1) / 2 > e) --a;
+    while ((a + 1) * (a + 2) / 2 <= e) ++a;
+    const int b = e - a * (a + 1) / 2;
+    float m = 0.f;
+    for (int cc = 0; cc <= a; ++cc) m = fmaf(Qs[a][cc], C[cc][b], m);
+    if (a > b) {
+      float* o = d_l + (size_t)k * L + a * (a - 1) / 2 + b;
+      *o = accumulate ? *o - m : -m;
+    } else {
+      float* o = d_qd + (size_t)k * D + a;
+      const float gq = A - Qs[a][a] * m;
+      *o = accumulate ? *o + gq : gq;
+    }
+  }
+  for (int a = threadIdx.x; a < D; a += blockDim.x) {
+    float v = 0.f;
+    for (int cc = 0; cc <= a; ++cc) v = fmaf(Qs[a][cc], us[cc] - A * mus[cc], v);
+    bq[a] = v;
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < D; d += blockDim.x) {
+    float gm = 0.f;
+    for (int a = d; a < D; ++a) gm = fmaf(Qs[a][d], bq[a], gm);
+    float* om = d_means + (size_t)k * D + d;
+    *om = accumulate ? *om + gm : gm;
+  }
+  if (threadIdx.x == 0) {
+    float m = -INFINITY;
+    for (int j = 0; j < K; ++j) m = fmaxf(m, alphas[j]);
+    float z = 0.f;
+    for (int j = 0; j < K; ++j) z += expf(alphas[j] - m);
+    const float ga = A - ctv * (float)N * (expf(alphas[k] - m) / z);
+    d_alphas[k] = accumulate ? d_alphas[k] + ga : ga;
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------

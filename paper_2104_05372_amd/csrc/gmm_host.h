@@ -18,11 +18,8 @@ struct FwdCfg {
   int cb, sk, ck;  // points per wave / 16, k-splits, contraction chunk depth
 };
 struct BwdCfg {
-  int pb, gw, ck, s;  // points per tile / 16, components per wave, chunk depth, point chunks
+  int gw, s;  // components per wave, point chunks
 };
-
-// Partial slot size (floats) per (point chunk, component); a multiple of 4.
-__host__ __device__ inline size_t bwd_slot(int DP) { return (size_t)DP * DP + DP + 4; }
 
 // Point-chunk length (a multiple of 64) and count for `s` requested chunks.
 inline void bwd_chunks(int64_t Npad, int s, int64_t* chunk, int* n) {

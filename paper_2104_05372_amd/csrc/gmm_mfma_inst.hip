@@ -13,8 +13,8 @@ template <int PREC, int DP>
 __global__ void __launch_bounds__(256) k_prep_x(const float* __restrict__ x, int N, int D, int Npad,
                                                 typename Store<PREC>::S* xh,
                                                 typename Store<PREC>::S* xl,
-                                                typename Store<PREC>::S* xhT,
-                                                typename Store<PREC>::S* xlT) {
+                                                typename MomT<MomOf<PREC>::MP>::S* xhT,
+                                                typename MomT<MomOf<PREC>::MP>::S* xlT) {
   prep_x_tile<PREC, DP>(x, N, D, Npad, blockIdx.x * 64, xh, xl, xhT, xlT);
 }
 
@@ -37,16 +37,16 @@ __global__ void __launch_bounds__(256) k_gmm_fwd(MfmaOps ops, int N, int Npad, i
                              ml + (size_t)blockIdx.y * Npad);
 }
 
-template <int DP, int PREC, int PB, int GW, int CK>
+template <int DP, int PREC, int GW>
 __global__ void __launch_bounds__(256) k_gmm_bwd(MfmaOps ops, int N, int Npad, int K, int chunk,
                                                  const float* __restrict__ beta,
                                                  const float* __restrict__ f,
                                                  const float* __restrict__ ct,
                                                  float* __restrict__ part) {
   const int pbeg = blockIdx.y * chunk, pend = min(Npad, pbeg + chunk);
-  const size_t E = dexi::bwd_slot(DP);
-  bwd_unit<DP, PREC, PB, GW, CK>(ops, N, Npad, K, blockIdx.x * 4 * GW, pbeg, pend, beta, f, ct[0],
-                                 part + (size_t)blockIdx.y * K * E, E);
+  const size_t E = mom_slot(DP);
+  bwd_mom_unit<DP, MomOf<PREC>::MP, GW>(ops.xhT, ops.xlT, N, Npad, K, blockIdx.x * 4 * GW, pbeg,
+                                        pend, beta, f, ct[0], part + (size_t)blockIdx.y * K * E, E);
 }
 
 }  // namespace dexk
@@ -56,13 +56,14 @@ using namespace dexk;
 
 constexpr int P = DEX_PREC;
 using S = typename Store<P>::S;
+using SM = typename MomT<MomOf<P>::MP>::S;
 
 template <int DP>
 static void prep_dp(const GmmGeom& g, const float* x, const float* alphas, const float* means,
                     const float* qd, const float* l, void* xh, void* xl, void* xhT, void* xlT,
                     void* Qh, void* Ql, float* negc, float* kappa, hipStream_t st) {
   hipLaunchKernelGGL((k_prep_x<P, DP>), dim3((unsigned)(g.Npad / 64)), dim3(256), 0, st, x, (int)g.N,
-                     (int)g.D, (int)g.Npad, (S*)xh, (S*)xl, (S*)xhT, (S*)xlT);
+                     (int)g.D, (int)g.Npad, (S*)xh, (S*)xl, (SM*)xhT, (SM*)xlT);
   hipLaunchKernelGGL((k_prep_q<P, DP>), dim3((unsigned)g.K), dim3(256), 0, st, alphas, means, qd, l,
                      (int)g.D, (S*)Qh, (S*)Ql, negc, kappa);
 }
@@ -112,35 +113,26 @@ void mfma_fwd<P>(const GmmGeom& g, const FwdCfg& c, const MfmaOps& o, float* bet
     fwd_dp<64>(g, c, o, beta, ml, st);
 }
 
-template <int DP, int PB, int GW, int CK>
+template <int DP, int GW>
 static void bwd_launch(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const float* beta,
                        const float* f, const float* ct, float* part, hipStream_t st) {
   int64_t chunk;
   int n;
   bwd_chunks(g.Npad, c.s, &chunk, &n);
   dim3 grid((unsigned)((g.K + 4 * GW - 1) / (4 * GW)), (unsigned)n);
-  hipLaunchKernelGGL((k_gmm_bwd<DP, P, PB, GW, CK>), grid, dim3(256), 0, st, o, (int)g.N,
-                     (int)g.Npad, (int)g.K, (int)chunk, beta, f, ct, part);
-}
-
-template <int DP, int CK>
-static void bwd_ck(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const float* beta,
-                   const float* f, const float* ct, float* part, hipStream_t st) {
-  if (c.pb == 4 && c.gw == 2)
-    bwd_launch<DP, 4, 2, CK>(g, c, o, beta, f, ct, part, st);
-  else if (c.pb == 4)
-    bwd_launch<DP, 4, 1, CK>(g, c, o, beta, f, ct, part, st);
-  else
-    bwd_launch<DP, 2, 2, CK>(g, c, o, beta, f, ct, part, st);
+  hipLaunchKernelGGL((k_gmm_bwd<DP, P, GW>), grid, dim3(256), 0, st, o, (int)g.N, (int)g.Npad,
+                     (int)g.K, (int)chunk, beta, f, ct, part);
 }
 
 template <int DP>
 static void bwd_dp(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const float* beta,
                    const float* f, const float* ct, float* part, hipStream_t st) {
-  if (DP >= 32 && c.ck == 32)
-    bwd_ck<DP, (DP >= 32 ? 32 : 16)>(g, c, o, beta, f, ct, part, st);
+  if (c.gw == 4)
+    bwd_launch<DP, 4>(g, c, o, beta, f, ct, part, st);
+  else if (c.gw == 2)
+    bwd_launch<DP, 2>(g, c, o, beta, f, ct, part, st);
   else
-    bwd_ck<DP, 16>(g, c, o, beta, f, ct, part, st);
+    bwd_launch<DP, 1>(g, c, o, beta, f, ct, part, st);
 }
 
 template <>
