@@ -132,10 +132,11 @@ def run_headline(torch, dex, workloads, args, dev):
     vjp_ms = sum(b.elapsed_time(c) for _, b, c in ev) / len(ev)
     kf_ms, kf_n = dex.dex_profile_read("GMM_FWD")
     kb_ms, kb_n = dex.dex_profile_read("GMM_VJP")
-    tri = D * (D + 1) * N * K  # triangular multiply-adds x2 of y = Q r, per pass over (i, k)
+    tri = D * (D + 1) * N * K        # forward: y = Q r, triangular, 2 flops per multiply-add
+    mom = D * (D + 3) * N * K        # reverse: symmetric sum of w x x^T (D(D+1)/2 entries) and w x
     kern = {
         "gmm_fwd": {"avg_ms": kf_ms / max(kf_n, 1), "flop_per_launch": tri},
-        "gmm_vjp": {"avg_ms": kb_ms / max(kb_n, 1), "flop_per_launch": 2 * tri},
+        "gmm_vjp": {"avg_ms": kb_ms / max(kb_n, 1), "flop_per_launch": mom},
     }
     for k in kern.values():
         k["tflops"] = k["flop_per_launch"] / (k["avg_ms"] * 1e-3) / 1e12
@@ -146,8 +147,8 @@ def run_headline(torch, dex, workloads, args, dev):
             "traffic": traffic_from_profiles(dom),
             "kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "tflops": round(v["tflops"], 2),
                             "frac": round(v["tflops"] / peak, 4)} for k, v in kern.items()},
-            "flop_count": "D(D+1)NK per pass: triangular y = Q r (forward), "
-                          "recompute + weighted outer product (reverse: 2x)"}
+            "flop_count": "forward D(D+1)NK (triangular y = Q r); reverse D(D+3)NK (symmetric "
+                          "weighted moment sum_i w x x^T and sum_i w x per component)"}
     res = dict(value=args.steps / elapsed, ms=elapsed / args.steps * 1e3, fwd_ms=fwd_ms, vjp_ms=vjp_ms,
                roofline=roof, cfg=S["cfg"], g=g, S=S)
     return res
@@ -159,10 +160,10 @@ def run_fp32_form(torch, dex, g, dev, steps):
         S["fwd"]()
         S["vjp"]()
     ms = timed(lambda: (S["fwd"](), S["vjp"]()), steps, torch.cuda.synchronize) * 1e3
-    tri = g.D * (g.D + 1) * g.N * g.K
+    fl = (g.D * (g.D + 1) + g.D * (g.D + 3)) * g.N * g.K
     return {"grad_evals_per_s": round(1e3 / ms, 2), "ms_per_step": round(ms, 3),
-            "tflops": round(3 * tri / (ms * 1e-3) / 1e12, 2),
-            "frac_fp32_peak": round(3 * tri / (ms * 1e-3) / 1e12 / PEAK["fp32"], 4),
+            "tflops": round(fl / (ms * 1e-3) / 1e12, 2),
+            "frac_fp32_peak": round(fl / (ms * 1e-3) / 1e12 / PEAK["fp32"], 4),
             "config": list(S["cfg"])}
 
 
@@ -272,11 +273,12 @@ def row_batched(torch, dex, workloads, dev, steps):
     dex.dex_profile_enable(False)
     N, D, K = shapes[:, 0], shapes[:, 1], shapes[:, 2]
     tri = float(np.sum(D * (D + 1) * N * K))
+    mom = float(np.sum(D * (D + 3) * N * K))
     res = {"workload": "512 GMM instances, N~U[1000,50000], D in {8,16,32}, K~U[10,100], FP32",
            "fwd_ms": round(f_ms, 4), "vjp_ms": round(b_ms, 4), "bwd_fwd_ratio": round(b_ms / f_ms, 3),
            "grad_evals_per_s": round(1e3 / (f_ms + b_ms), 2), "config": [bf, bb],
-           "algorithmic_tflop": round(3 * tri / 1e12, 4)}
-    for k, fl in (("BGMM_FWD", tri), ("BGMM_VJP", 2 * tri)):
+           "algorithmic_tflop": round((tri + mom) / 1e12, 4)}
+    for k, fl in (("BGMM_FWD", tri), ("BGMM_VJP", mom)):
         ms, cnt = dex.dex_profile_read(k)
         a = fl / (ms / max(cnt, 1) * 1e-3) / 1e12
         res[k.lower()] = {"avg_ms": round(ms / max(cnt, 1), 4), "tflops": round(a, 2),
