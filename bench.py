@@ -168,7 +168,7 @@ def run_fp32_form(torch, dex, g, dev, steps):
 
 
 # ---------------------------------------------------------------------------
-def row_scatter(torch, dex, workloads, dev, steps):
+def row_scatter(torch, dex, workloads, dev, steps, scatter_config=1):
     import numpy as np
     c = workloads.SCATTER
     V, R, n = c["rows"], c["row_len"], c["n"]
@@ -183,12 +183,15 @@ def row_scatter(torch, dex, workloads, dev, steps):
     dT = torch.empty_like(T)
     dw = torch.empty_like(w)
     d = dex.gather_desc(V, R, n)
+    wsb = dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_VJP), dev)
+    dv = dex.gather_desc(V, R, n)
+    dv.config = scatter_config
 
     def fwd():
         dex.dex_fwd(d, [T, idx, w], [out], [])
 
     def vjp():
-        dex.dex_vjp(d, [T, idx, w], [], [g], [dT, dw], 0)
+        dex.dex_vjp(dv, [T, idx, w], [], [g], [dT, dw], 0, wsb)
 
     fwd()
     vjp()
@@ -199,6 +202,8 @@ def row_scatter(torch, dex, workloads, dev, steps):
     b_ms = timed(vjp, steps, torch.cuda.synchronize) * 1e3
     dex.dex_profile_enable(False)
     res = {"workload": f"gather/scatter table {V}x{R} f32, {n} Zipf(1.1) indices",
+           "scatter_form": {1: "block sort + run sums + atomics", 2: "radix sort, fixed-order run sums"}[
+               scatter_config],
            "fwd_ms": round(f_ms, 4), "vjp_ms": round(b_ms, 4), "bwd_fwd_ratio": round(b_ms / f_ms, 3),
            "touched_rows": touched}
     bytes_k = {"GATHER": 2 * n * 4 + 2 * n * R * 4, "SCATTER": 2 * n * 4 + n * R * 4 + touched * R * 4,
@@ -417,8 +422,10 @@ def main(argv=None):
             line["fp32_form"] = {"error": repr(e)}
     if not args.no_rows:
         rows = {}
-        sel = args.rows_only.split(",") if args.rows_only else ["scatter", "hist", "batched", "stencil"]
-        fns = {"scatter": row_scatter, "hist": row_histogram, "batched": row_batched, "stencil": row_stencil}
+        sel = args.rows_only.split(",") if args.rows_only else ["scatter", "scatter_det", "hist", "batched",
+                                                                "stencil"]
+        fns = {"scatter": row_scatter, "hist": row_histogram, "batched": row_batched, "stencil": row_stencil,
+               "scatter_det": lambda *a: row_scatter(*a, scatter_config=2)}
         for name in sel:
             log("row", name)
             try:

@@ -81,6 +81,8 @@ typedef int32_t dex_status;
 #define DEX_SYNC_CHECK   4u /* with DEX_CHECK_BOUNDS: wait for the stream and return
                                DEX_ERR_OUT_OF_RANGE if this call found any           */
 #define DEX_NO_DW        8u /* DEX_GATHER_SCALE dex_vjp: skip the cotangent of w      */
+#define DEX_DETERMINISTIC 16u /* dex_accum_scatter, float: sort-based form whose rounding
+                                order is fixed (bit-reproducible), no atomics        */
 
 /* workspace roles for dex_workspace_bytes */
 #define DEX_WS_FWD   0 /* scratch for dex_fwd                           */
@@ -150,6 +152,8 @@ typedef struct dex_buf {
  *   out    = out[n*R];  resid = none;  ct_out = g[n*R]
  *   ct_in  = dT[V*R], dw[n] (dw may be numel 0 with DEX_NO_DW)
  *   dT is the transposed gather: dT!(idx.j) += w.j * g.j (Sec. 5.3.3).
+ *   config 1 (default): block-local sort + run sums + atomics; config 2: the
+ *   DEX_DETERMINISTIC sorted form (needs DEX_WS_VJP workspace).
  *
  * DEX_STENCIL5 (dims {H, W, steps, every}; FP32): the State loop
  *     for t in 0..steps-1:  u := u + c (u[y+1,x]+u[y-1,x]+u[y,x+1]+u[y,x-1]-4u) + rho sin(u)
@@ -220,6 +224,9 @@ dex_status dex_vjp(const dex_desc* d,
  * accumulation is associative only up to rounding (Sec. 2.3.2): duplicate
  * indices are first summed in registers/LDS within a block, then added with
  * global atomics, so the rounding order is unspecified.
+ * With DEX_DETERMINISTIC (float only) the (index, position) pairs are radix
+ * sorted and each run of equal indices is summed in index order by one owner,
+ * so the result is bit-identical from run to run; needs the workspace below.
  * Integer with row_len == 1, vals == NULL and n_rows <= 65536 is the
  * histogram of Sec. 6.1.2 and uses LDS-private counters.
  */
@@ -233,7 +240,7 @@ dex_status dex_accum_scatter(void* acc, int32_t acc_dtype, int64_t n_rows, int64
 /* Scratch bytes that dex_accum_scatter needs for these arguments. */
 dex_status dex_accum_scatter_workspace_bytes(int32_t acc_dtype, int64_t n_rows,
                                              int64_t row_len, int64_t n, int32_t has_vals,
-                                             size_t* bytes);
+                                             uint32_t flags, size_t* bytes);
 
 /*
  * Host-side plan for DEX_GMM_BATCHED. `shapes` is host memory, B rows of

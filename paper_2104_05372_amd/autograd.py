@@ -75,7 +75,8 @@ class GatherScale(torch.autograd.Function):
         want_dw = ctx.needs_input_grad[2]
         dw = torch.empty_like(w) if want_dw else None
         flags = 0 if want_dw else dex.DEX_NO_DW
-        dex.dex_vjp(ctx.d, [T, idx, w], [], [g.contiguous()], [dT, dw], flags)
+        dex.dex_vjp(ctx.d, [T, idx, w], [], [g.contiguous()], [dT, dw], flags,
+                    _ws(ctx.d, dex.DEX_WS_VJP, T.device))
         return dT, None, dw
 
 

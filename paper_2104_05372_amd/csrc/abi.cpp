@@ -234,6 +234,9 @@ static size_t ws_bytes(const dex_desc& d, int role) {
       return gmm_batched_ws_bytes(d, role);
     case DEX_STENCIL5:
       return stencil_ws_bytes(d, role);
+    case DEX_GATHER_SCALE:
+      return role == DEX_WS_VJP ? scatter_ws_bytes(DEX_F32, d.dims[0], d.dims[1], d.dims[2], true, true)
+                                : 0;
     default:
       return 0;
   }
@@ -297,6 +300,9 @@ dex_status dex_num_configs(const dex_desc* d, int32_t role, int32_t* count) {
       break;
     case DEX_STENCIL5:
       *count = stencil_num_configs(*d, role);
+      break;
+    case DEX_GATHER_SCALE:
+      *count = role == DEX_WS_VJP ? 2 : 1;
       break;
     default:
       *count = 1;
@@ -470,7 +476,7 @@ dex_status dex_vjp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex
       DEX_TRY(want(ct_in, 1, "ct_in", DEX_F32, with_dw ? n : 0));
       if (!acc) DEX_TRY(fill_zero(ct_in[0].ptr, (size_t)(V * R) * 4, s));
       DEX_TRY(accum_scatter(ct_in[0].ptr, DEX_F32, V, R, in[1].ptr, DEX_I32, ct_out[0].ptr,
-                            (const float*)in[2].ptr, n, false, nullptr, nullptr, 0, cfg, s));
+                            (const float*)in[2].ptr, n, false, nullptr, workspace, ws_bytes_, cfg, s));
       if (with_dw)
         DEX_TRY(gather_dw((const float*)in[0].ptr, (const int32_t*)in[1].ptr,
                           (const float*)ct_out[0].ptr, V, R, n, (float*)ct_in[1].ptr, acc, s));
@@ -498,9 +504,11 @@ dex_status dex_vjp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex
 }
 
 dex_status dex_accum_scatter_workspace_bytes(int32_t acc_dtype, int64_t n_rows, int64_t row_len,
-                                             int64_t n, int32_t has_vals, size_t* bytes) {
+                                             int64_t n, int32_t has_vals, uint32_t flags,
+                                             size_t* bytes) {
   if (!bytes) return fail(DEX_ERR_INVALID_ARG, "null output");
-  *bytes = scatter_ws_bytes(acc_dtype, n_rows, row_len, n, has_vals != 0);
+  *bytes = scatter_ws_bytes(acc_dtype, n_rows, row_len, n, has_vals != 0,
+                            (flags & DEX_DETERMINISTIC) != 0);
   return DEX_OK;
 }
 
@@ -528,8 +536,11 @@ dex_status dex_accum_scatter(void* acc, int32_t acc_dtype, int64_t n_rows, int64
     DEX_TRY(check_hip(hipMemcpyAsync(&before, oob_count_dev, 8, hipMemcpyDeviceToHost, s), "oob read"));
     DEX_TRY(check_hip(hipStreamSynchronize(s), "sync"));
   }
+  const int path = (flags & DEX_DETERMINISTIC) ? 1 : 0;
+  if (path == 1 && acc_dtype != DEX_F32)
+    return fail(DEX_ERR_INVALID_ARG, "DEX_DETERMINISTIC applies to float accumulation");
   DEX_TRY(accum_scatter(acc, acc_dtype, n_rows, row_len, idx, idx_dtype, vals, scale, n, check,
-                        oob_count_dev, workspace, ws_bytes_, 0, s));
+                        oob_count_dev, workspace, ws_bytes_, path, s));
   if (sync) {
     DEX_TRY(check_hip(hipMemcpyAsync(&after, oob_count_dev, 8, hipMemcpyDeviceToHost, s), "oob read"));
     DEX_TRY(check_hip(hipStreamSynchronize(s), "sync"));

@@ -61,7 +61,7 @@ dex_status gmm_batched_vjp(const dex_desc& d, int cfg, const void* plan, const G
 
 // ------------------------------------------------ scatter / gather -----
 size_t scatter_ws_bytes(int32_t acc_dtype, int64_t n_rows, int64_t row_len, int64_t n,
-                        bool has_vals);
+                        bool has_vals, bool deterministic);
 dex_status accum_scatter(void* acc, int32_t acc_dtype, int64_t n_rows, int64_t row_len,
                          const void* idx, int32_t idx_dtype, const void* vals,
                          const float* scale, int64_t n, bool count_oob, int64_t* oob,

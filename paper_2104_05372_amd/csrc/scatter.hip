@@ -17,6 +17,7 @@
 // the end each block writes its counters to the workspace and a second kernel
 // adds them per bin. Integer addition is exact, so the result is identical
 // under any schedule.
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
@@ -311,6 +312,248 @@ __global__ void __launch_bounds__(256) gather_dw_kernel(const float* __restrict_
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Deterministic float scatter: a stable LSD radix sort of (row, position) pairs
+// followed by run sums with a fixed owner per run, so the rounding order of
+// every row's sum is fixed (bit-reproducible), and no atomics are used.
+constexpr int kRsTile = 8192;   // keys per sort block (1024 threads x 8 rounds)
+constexpr int kSeg = 256;       // sorted entries per wave in the run-sum pass
+
+// keys[j] = idx[j] if it is inside [0, n_rows), else n_rows (sorts last and is
+// skipped); vals[j] = j.
+template <typename IdxT>
+__global__ void __launch_bounds__(256) rs_init(const IdxT* __restrict__ idx, int64_t n,
+                                               int64_t n_rows, uint32_t* __restrict__ keys,
+                                               uint32_t* __restrict__ vals, int64_t* oob) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int bad = 0;
+  if (j < n) {
+    const int64_t v = load_index(idx, j);
+    const bool ok = v >= 0 && v < n_rows;
+    bad = !ok;
+    keys[j] = ok ? (uint32_t)v : (uint32_t)n_rows;
+    vals[j] = (uint32_t)j;
+  }
+  if (oob) count_oob(bad, oob);
+}
+
+// Digit counts of one tile: cnt[digit * ntiles + tile]. Exact, order-free.
+__global__ void __launch_bounds__(1024) rs_hist(const uint32_t* __restrict__ keys, int64_t n,
+                                                int shift, uint32_t* __restrict__ cnt, int ntiles) {
+  __shared__ uint32_t h[256];
+  if (threadIdx.x < 256) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t t0 = (int64_t)blockIdx.x * kRsTile;
+#pragma unroll
+  for (int r = 0; r < kRsTile / 1024; ++r) {
+    const int64_t j = t0 + r * 1024 + threadIdx.x;
+    if (j < n) atomicAdd(&h[(keys[j] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 256) cnt[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Per digit (one block each): exclusive prefix of the tile counts, and the total.
+__global__ void __launch_bounds__(256) rs_digit_scan(uint32_t* __restrict__ cnt, int ntiles,
+                                                     uint32_t* __restrict__ tot) {
+  __shared__ uint32_t sh[256];
+  uint32_t carry = 0;
+  uint32_t* row = cnt + (size_t)blockIdx.x * ntiles;
+  for (int b = 0; b < ntiles; b += 256) {
+    const int i = b + threadIdx.x;
+    const uint32_t v = i < ntiles ? row[i] : 0u;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {  // inclusive Hillis-Steele scan
+      const uint32_t t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0u;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < ntiles) row[i] = carry + sh[threadIdx.x] - v;
+    carry += sh[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
+// Lanes of this wave holding the same 8-bit digit as this lane (among `live`).
+DEX_DEV uint64_t digit_peers(uint32_t d, uint64_t live) {
+  uint64_t m = live;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint64_t bal = __ballot((d >> b) & 1u);
+    m &= ((d >> b) & 1u) ? bal : ~bal;
+  }
+  return m;
+}
+
+// Stable scatter of one tile by digit: keys are taken in index order (round r,
+// then thread), ranked within the wave by ballots and across waves by
+// per-wave digit counts in LDS; no atomics, so the output order is fixed.
+__global__ void __launch_bounds__(1024) rs_scatter(const uint32_t* __restrict__ kin,
+                                                   const uint32_t* __restrict__ vin,
+                                                   uint32_t* __restrict__ kout,
+                                                   uint32_t* __restrict__ vout, int64_t n,
+                                                   int shift, const uint32_t* __restrict__ cnt,
+                                                   const uint32_t* __restrict__ tot, int ntiles) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t whist[16][256];
+  __shared__ uint32_t wsum[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // exclusive scan of the digit totals by the first 4 waves (whole waves)
+  uint32_t v = 0, x = 0;
+  if (tid < 256) {
+    v = tot[tid];
+    x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+  }
+  __syncthreads();
+  if (tid < 256) {
+    uint32_t pre = 0;
+    for (int w = 0; w < wv; ++w) pre += wsum[w];
+    base[tid] = pre + x - v + cnt[(size_t)tid * ntiles + blockIdx.x];
+  }
+  const int64_t t0 = (int64_t)blockIdx.x * kRsTile;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kRsTile / 1024; ++r) {
+    for (int e = tid; e < 16 * 256; e += 1024) (&whist[0][0])[e] = 0u;
+    const int64_t j = t0 + r * 1024 + tid;
+    const bool valid = j < n;
+    const uint32_t key = valid ? kin[j] : 0u;
+    const uint32_t val = valid ? vin[j] : 0u;
+    const uint32_t d = (key >> shift) & 255u;
+    const uint64_t live = __ballot(valid);
+    const uint64_t peers = digit_peers(d, live);
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    __syncthreads();
+    if (valid && rank == 0) whist[wv][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (tid < 256) {
+      uint32_t run = base[tid];
+#pragma unroll
+      for (int w = 0; w < 16; ++w) {
+        const uint32_t c = whist[w][tid];
+        whist[w][tid] = run;
+        run += c;
+      }
+      base[tid] = run;
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t pos = whist[wv][d] + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+  }
+}
+
+// One wave per segment of kSeg sorted entries. Runs of equal rows are summed in
+// registers (row_len columns over the lanes); a run wholly inside the segment
+// is added to acc by this wave alone; a run that starts earlier leaves its
+// partial in part_first[seg], one that continues past the segment in
+// part_last[seg], for seg_fix.
+template <int U>
+__global__ void __launch_bounds__(256) seg_sum(const uint32_t* __restrict__ skey,
+                                               const uint32_t* __restrict__ spos, int64_t n,
+                                               uint32_t sentinel, const float* __restrict__ vals,
+                                               const float* __restrict__ scale, int R,
+                                               float* __restrict__ acc,
+                                               float* __restrict__ part_first,
+                                               float* __restrict__ part_last) {
+  const int lane = threadIdx.x & 63;
+  const int64_t seg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t e0 = seg * kSeg;
+  if (e0 >= n) return;
+  const int64_t e1 = min<int64_t>(n, e0 + kSeg);
+  const uint32_t first = skey[e0];
+  if (first == sentinel) return;
+  const bool cont_in = e0 > 0 && skey[e0 - 1] == first;
+  const uint32_t lastk = skey[e1 - 1];
+  const bool cont_out = e1 < n && skey[e1] == lastk && lastk != sentinel;
+  for (int c0 = 0; c0 < R; c0 += 64) {
+    const int col = c0 + lane;
+    const bool cv = col < R;
+    uint32_t cur = first;
+    bool started_before = cont_in;
+    float sum = 0.f;
+    auto flush = [&](bool continues) {
+      if (!cv || cur == sentinel) return;
+      if (started_before)
+        part_first[seg * R + col] = sum;
+      else if (continues)
+        part_last[seg * R + col] = sum;
+      else
+        acc[(int64_t)cur * R + col] += sum;
+    };
+    for (int64_t e = e0; e < e1; e += U) {
+      uint32_t kk[U];
+      float rv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool in = e + u < e1;
+        kk[u] = in ? skey[e + u] : sentinel;
+        rv[u] = 0.f;
+        if (in && kk[u] != sentinel && cv) {
+          const int64_t j = spos[e + u];
+          float v = vals ? vals[j * R + col] : 1.f;
+          if (scale) v *= scale[j];
+          rv[u] = v;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (kk[u] == sentinel) continue;
+        if (kk[u] != cur) {
+          flush(false);
+          cur = kk[u];
+          started_before = false;
+          sum = 0.f;
+        }
+        sum += rv[u];
+      }
+    }
+    flush(cont_out);
+  }
+}
+
+// For each segment whose last run starts in it and continues into the next
+// segments: add its partial and the following segments' first-run partials in
+// segment order, then add the total to acc.
+__global__ void __launch_bounds__(256) seg_fix(const uint32_t* __restrict__ skey, int64_t n,
+                                               uint32_t sentinel, int R, float* __restrict__ acc,
+                                               const float* __restrict__ part_first,
+                                               const float* __restrict__ part_last) {
+  const int lane = threadIdx.x & 63;
+  const int64_t seg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nseg = (n + kSeg - 1) / kSeg;
+  if (seg >= nseg) return;
+  const int64_t e0 = seg * kSeg, e1 = min<int64_t>(n, e0 + kSeg);
+  const uint32_t row = skey[e1 - 1];
+  if (row == sentinel) return;
+  const bool cont_out = e1 < n && skey[e1] == row;
+  if (!cont_out) return;
+  const bool whole_from_before = e0 > 0 && skey[e0 - 1] == row && skey[e0] == row;
+  if (whole_from_before) return;  // the run started in an earlier segment
+  for (int col = lane; col < R; col += 64) {
+    float total = part_last[seg * R + col];
+    for (int64_t s2 = seg + 1; s2 < nseg; ++s2) {
+      total += part_first[s2 * R + col];
+      const int64_t f0 = s2 * kSeg, f1 = min<int64_t>(n, f0 + kSeg);
+      const bool through = skey[f1 - 1] == row && f1 < n && skey[f1] == row;
+      if (!through) break;
+    }
+    acc[(int64_t)row * R + col] += total;
+  }
+}
+
 }  // namespace dexk
 
 // ===========================================================================
@@ -319,11 +562,13 @@ using namespace dexk;
 
 static int hist_blocks() { return num_cus(); }
 
+size_t sorted_scatter_ws_bytes(int64_t n, int64_t R);
+
 size_t scatter_ws_bytes(int32_t acc_dtype, int64_t n_rows, int64_t row_len, int64_t n,
-                        bool has_vals) {
-  (void)n;
+                        bool has_vals, bool deterministic) {
   if (acc_dtype == DEX_I32 && row_len == 1 && !has_vals && n_rows <= 65536)
     return align256((size_t)hist_blocks() * ((n_rows + 1) / 2) * 4);
+  if (acc_dtype == DEX_F32 && deterministic) return sorted_scatter_ws_bytes(n, row_len);
   return 0;
 }
 
@@ -346,7 +591,7 @@ static dex_status scatter_typed(void* acc, int32_t acc_dtype, int64_t n_rows, in
                                 int64_t* oob, void* ws, size_t ws_bytes, hipStream_t s) {
   if (acc_dtype == DEX_I32 && R == 1 && !vals && n_rows <= 65536) {
     const int nb = hist_blocks();
-    const size_t need = scatter_ws_bytes(acc_dtype, n_rows, R, n, false);
+    const size_t need = scatter_ws_bytes(acc_dtype, n_rows, R, n, false, false);
     if (!ws || ws_bytes < need)
       return fail(DEX_ERR_WORKSPACE, "histogram needs %zu workspace bytes, got %zu", need, ws_bytes);
     const int64_t per = ((n + nb - 1) / nb + 3) & ~int64_t(3);
@@ -388,13 +633,85 @@ static dex_status scatter_typed(void* acc, int32_t acc_dtype, int64_t n_rows, in
   return check_hip(hipGetLastError(), "accum_scatter");
 }
 
+// Workspace of the sorted (deterministic) float scatter.
+struct SortWs {
+  uint32_t *ka, *va, *kb, *vb, *cnt, *tot;
+  float *pf, *pl;
+  size_t bytes;
+};
+
+static SortWs sort_ws(int64_t n, int64_t R, char* base) {
+  SortWs w{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t at = o;
+    o += align256(b);
+    return base ? (void*)(base + at) : nullptr;
+  };
+  const int64_t ntiles = (n + kRsTile - 1) / kRsTile;
+  const int64_t nseg = (n + kSeg - 1) / kSeg;
+  w.ka = (uint32_t*)take((size_t)n * 4);
+  w.va = (uint32_t*)take((size_t)n * 4);
+  w.kb = (uint32_t*)take((size_t)n * 4);
+  w.vb = (uint32_t*)take((size_t)n * 4);
+  w.cnt = (uint32_t*)take((size_t)256 * ntiles * 4);
+  w.tot = (uint32_t*)take(256 * 4);
+  w.pf = (float*)take((size_t)nseg * R * 4);
+  w.pl = (float*)take((size_t)nseg * R * 4);
+  w.bytes = o;
+  return w;
+}
+
+size_t sorted_scatter_ws_bytes(int64_t n, int64_t R) { return sort_ws(n, R, nullptr).bytes; }
+
+template <typename IdxT>
+static dex_status scatter_sorted(float* acc, int64_t n_rows, int64_t R, const IdxT* idx,
+                                 const float* vals, const float* scale, int64_t n, int64_t* oob,
+                                 void* ws, size_t ws_bytes, hipStream_t s) {
+  if (n_rows > 0xFFFFFFFEll || n > 0xFFFFFFFFll)
+    return fail(DEX_ERR_UNSUPPORTED, "sorted scatter: at most 2^32-2 rows and 2^32 indices");
+  const SortWs w = sort_ws(n, R, (char*)ws);
+  if (!ws || ws_bytes < w.bytes)
+    return fail(DEX_ERR_WORKSPACE, "sorted scatter needs %zu workspace bytes, got %zu", w.bytes, ws_bytes);
+  const int ntiles = (int)((n + kRsTile - 1) / kRsTile);
+  const int64_t nseg = (n + kSeg - 1) / kSeg;
+  const int nbits = 64 - __builtin_clzll((unsigned long long)n_rows);  // n_rows itself is the sentinel
+  const int passes = (nbits + 7) / 8;
+  ProfRange pr(DEX_PROF_SCATTER, s);
+  hipLaunchKernelGGL((rs_init<IdxT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, idx, n,
+                     n_rows, w.ka, w.va, oob);
+  uint32_t *kin = w.ka, *vin = w.va, *kout = w.kb, *vout = w.vb;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    hipLaunchKernelGGL(rs_hist, dim3(ntiles), dim3(1024), 0, s, kin, n, shift, w.cnt, ntiles);
+    hipLaunchKernelGGL(rs_digit_scan, dim3(256), dim3(256), 0, s, w.cnt, ntiles, w.tot);
+    hipLaunchKernelGGL(rs_scatter, dim3(ntiles), dim3(1024), 0, s, kin, vin, kout, vout, n, shift,
+                       w.cnt, w.tot, ntiles);
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+  const unsigned sb = (unsigned)((nseg + 3) / 4);
+  hipLaunchKernelGGL((seg_sum<8>), dim3(sb), dim3(256), 0, s, kin, vin, n, (uint32_t)n_rows, vals,
+                     scale, (int)R, acc, w.pf, w.pl);
+  hipLaunchKernelGGL(seg_fix, dim3(sb), dim3(256), 0, s, kin, n, (uint32_t)n_rows, (int)R, acc,
+                     w.pf, w.pl);
+  pr.end(1);
+  return check_hip(hipGetLastError(), "sorted scatter");
+}
+
 dex_status accum_scatter(void* acc, int32_t acc_dtype, int64_t n_rows, int64_t row_len,
                          const void* idx, int32_t idx_dtype, const void* vals,
                          const float* scale, int64_t n, bool count_oob, int64_t* oob, void* ws,
                          size_t ws_bytes, int cfg, hipStream_t s) {
-  (void)cfg;
   if (n == 0) return DEX_OK;
   int64_t* o = count_oob ? oob : nullptr;
+  if (cfg == 1 && acc_dtype == DEX_F32) {
+    if (idx_dtype == DEX_I32)
+      return scatter_sorted<int32_t>((float*)acc, n_rows, row_len, (const int32_t*)idx,
+                                     (const float*)vals, scale, n, o, ws, ws_bytes, s);
+    return scatter_sorted<uint32_t>((float*)acc, n_rows, row_len, (const uint32_t*)idx,
+                                    (const float*)vals, scale, n, o, ws, ws_bytes, s);
+  }
   if (idx_dtype == DEX_I32)
     return scatter_typed<int32_t>(acc, acc_dtype, n_rows, row_len, (const int32_t*)idx, vals,
                                   scale, n, o, ws, ws_bytes, s);

@@ -31,7 +31,7 @@ DEX_GMM, DEX_GMM_BATCHED, DEX_GATHER_SCALE, DEX_STENCIL5 = 1, 2, 3, 4
 DEX_GMM_PLAIN, DEX_GMM_BF16, DEX_GMM_BF16X3 = 0, 1, 2
 DEX_STENCIL_RECOMPUTE, DEX_STENCIL_LINEAR = 0, 1
 # flags
-DEX_ACCUMULATE, DEX_CHECK_BOUNDS, DEX_SYNC_CHECK, DEX_NO_DW = 1, 2, 4, 8
+DEX_ACCUMULATE, DEX_CHECK_BOUNDS, DEX_SYNC_CHECK, DEX_NO_DW, DEX_DETERMINISTIC = 1, 2, 4, 8, 16
 # workspace roles
 DEX_WS_FWD, DEX_WS_VJP, DEX_WS_RESID = 0, 1, 2
 
@@ -87,7 +87,8 @@ def lib():
         L.dex_vjp.restype = S
         L.dex_accum_scatter.argtypes = [P, I32, I64, I64, P, I32, P, P, I64, ctypes.c_uint32, P, P, SZ, P]
         L.dex_accum_scatter.restype = S
-        L.dex_accum_scatter_workspace_bytes.argtypes = [I32, I64, I64, I64, I32, ctypes.POINTER(SZ)]
+        L.dex_accum_scatter_workspace_bytes.argtypes = [I32, I64, I64, I64, I32, ctypes.c_uint32,
+                                                        ctypes.POINTER(SZ)]
         L.dex_accum_scatter_workspace_bytes.restype = S
         L.dex_gmm_batched_plan.argtypes = [P, I64, I32, DP, P, ctypes.POINTER(SZ)]
         L.dex_gmm_batched_plan.restype = S
@@ -221,10 +222,10 @@ def dex_vjp(d: DexDesc, ins, resid, ct_out, ct_in, flags=0, ws: torch.Tensor | N
                         stream_ptr(stream)))
 
 
-def dex_accum_scatter_workspace_bytes(acc_dtype, n_rows, row_len, n, has_vals) -> int:
+def dex_accum_scatter_workspace_bytes(acc_dtype, n_rows, row_len, n, has_vals, flags=0) -> int:
     b = ctypes.c_size_t(0)
     check(lib().dex_accum_scatter_workspace_bytes(acc_dtype, n_rows, row_len, n, int(bool(has_vals)),
-                                                  ctypes.byref(b)))
+                                                  flags, ctypes.byref(b)))
     return b.value
 
 
@@ -239,7 +240,7 @@ def dex_accum_scatter(acc: torch.Tensor, idx: torch.Tensor, vals: torch.Tensor |
     idt = idx_dtype if idx_dtype is not None else dtype_code(idx)
     n = idx.numel()
     if ws is None:
-        nb = dex_accum_scatter_workspace_bytes(acc_dt, n_rows, row_len, n, vals is not None)
+        nb = dex_accum_scatter_workspace_bytes(acc_dt, n_rows, row_len, n, vals is not None, flags)
         ws = workspace(nb, acc.device) if nb else None
     for t in (acc, idx, vals, scale):
         if t is not None and not t.is_contiguous():

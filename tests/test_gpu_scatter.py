@@ -17,7 +17,7 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def gather_vjp(T, idx, w, g, dev, want_dw=True):
+def gather_vjp(T, idx, w, g, dev, want_dw=True, config=0):
     from paper_2104_05372_amd import dex
     V, R = T.shape
     n = idx.shape[0]
@@ -31,16 +31,20 @@ def gather_vjp(T, idx, w, g, dev, want_dw=True):
     dex.dex_fwd(d, [tT, ti, tw], [out], [])
     dT = torch.empty_like(tT)
     dw = torch.empty_like(tw) if want_dw else None
-    dex.dex_vjp(d, [tT, ti, tw], [], [tg], [dT, dw], 0 if want_dw else dex.DEX_NO_DW)
+    d.config = config
+    ws = dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_VJP), dev)
+    dex.dex_vjp(d, [tT, ti, tw], [], [tg], [dT, dw], 0 if want_dw else dex.DEX_NO_DW, ws)
     torch.cuda.synchronize()
     return out.cpu().numpy(), dT.cpu().numpy(), (dw.cpu().numpy() if want_dw else None)
 
 
+@pytest.mark.parametrize("config", [1, 2])
 @pytest.mark.parametrize("V,R,n,seed", [(50, 8, 1000, 0), (1000, 128, 50_000, 1), (7, 3, 5000, 2),
-                                        (300, 100, 4097, 3), (20_000, 130, 2049, 4), (1, 64, 3000, 5)])
-def test_gather_and_transpose(dev, V, R, n, seed):
+                                        (300, 100, 4097, 3), (20_000, 130, 2049, 4), (1, 64, 3000, 5),
+                                        (70_000, 16, 9000, 6)])
+def test_gather_and_transpose(dev, V, R, n, seed, config):
     si = workloads.scatter_inputs(V, R, n, 1.1, seed)
-    out, dT, dw = gather_vjp(si.table, si.idx, si.w, si.g, dev)
+    out, dT, dw = gather_vjp(si.table, si.idx, si.w, si.g, dev, config=config)
     assert rel(out, osc.gather(si.table, si.idx, si.w)) <= 1e-6
     want = osc.scatter(V, si.idx, si.w, si.g)
     assert rel(dT, want) <= 1e-5
@@ -57,8 +61,9 @@ def test_dense_one_hot_invariant(dev):
     assert rel(dT, S.T @ (si.w[:, None].astype(np.float64) * si.g)) <= 1e-5
 
 
+@pytest.mark.parametrize("config", [1, 2])
 @pytest.mark.parametrize("order", ["equal", "sorted", "reverse", "distinct"])
-def test_contention_patterns(dev, order):
+def test_contention_patterns(dev, order, config):
     rng = np.random.default_rng(7)
     n, V, R = 200_000, 5000, 32
     if order == "equal":
@@ -73,13 +78,42 @@ def test_contention_patterns(dev, order):
     w = rng.uniform(-1, 1, n).astype(np.float32)
     g = rng.standard_normal((n, R)).astype(np.float32)
     T = rng.standard_normal((V, R)).astype(np.float32)
-    _, dT, _ = gather_vjp(T, idx, w, g, dev, want_dw=False)
+    _, dT, _ = gather_vjp(T, idx, w, g, dev, want_dw=False, config=config)
     if order == "equal":
         want = np.zeros((V, R))
         want[17] = (w[:, None].astype(np.float64) * g).sum(0)
     else:
         want = osc.scatter(V, idx, w, g)
     assert rel(dT, want) <= 1e-5
+
+
+def test_deterministic_scatter_is_bit_reproducible(dev):
+    """The sorted form fixes every row's summation order: repeated runs agree
+    bit for bit (and with the oracle to FP32 accuracy), including hot rows."""
+    from paper_2104_05372_amd import dex
+    si = workloads.scatter_inputs(20_000, 64, 300_000, 1.1, 8)
+    res = []
+    for _ in range(3):
+        acc = torch.zeros(20_000, 64, device=dev)
+        dex.dex_accum_scatter(acc, torch.tensor(si.idx, device=dev), torch.tensor(si.g, device=dev),
+                              torch.tensor(si.w, device=dev), flags=dex.DEX_DETERMINISTIC)
+        res.append(acc.cpu().numpy())
+    assert np.array_equal(res[0], res[1]) and np.array_equal(res[0], res[2])
+    assert rel(res[0], osc.scatter(20_000, si.idx, si.w, si.g)) <= 1e-5
+
+
+def test_deterministic_scatter_bounds_and_accumulate(dev):
+    from paper_2104_05372_amd import dex
+    rng = np.random.default_rng(9)
+    idx = rng.integers(-3, 1003, 7000).astype(np.int32)
+    vals = rng.standard_normal((7000, 9)).astype(np.float32)
+    acc = torch.full((1000, 9), -1.5, device=dev)
+    oob = torch.zeros(1, dtype=torch.int64, device=dev)
+    dex.dex_accum_scatter(acc, torch.tensor(idx, device=dev), torch.tensor(vals, device=dev), None,
+                          dex.DEX_DETERMINISTIC | dex.DEX_CHECK_BOUNDS, oob)
+    want, nbad = osc.scatter(1000, idx, None, vals, check_bounds=True)
+    assert oob.item() == nbad
+    assert rel(acc.cpu().numpy() + 1.5, want) <= 1e-5
 
 
 def test_accum_scatter_entry_point_and_bounds(dev):
@@ -151,11 +185,12 @@ def test_histogram_out_of_range_keys(dev):
     assert oob.item() == 2 and hh[2] == 2 and hh[1] == 1 and hh[65535] == 1 and hh.sum() == 4
 
 
-def test_full_size_scatter_sampled(dev):
+@pytest.mark.parametrize("config", [1, 2])
+def test_full_size_scatter_sampled(dev, config):
     """1e6 x 128 table, 2^22 Zipf(1.1) indices, as benchmarked; sampled rows."""
     c = workloads.SCATTER
     si = workloads.scatter_inputs(c["rows"], c["row_len"], c["n"], c["s"], c["seed"])
-    out, dT, dw = gather_vjp(si.table, si.idx, si.w, si.g, dev)
+    out, dT, dw = gather_vjp(si.table, si.idx, si.w, si.g, dev, config=config)
     rng = np.random.default_rng(0)
     js = np.concatenate([[0, c["n"] - 1], rng.integers(0, c["n"], 64)])
     assert rel(out[js], osc.gather(si.table, si.idx, si.w, js)) <= 1e-6
