@@ -182,14 +182,25 @@ __global__ void __launch_bounds__(1024) hist_private_kernel(int32_t* __restrict_
     for (int64_t j = b0 + threadIdx.x; j < min(a0, b1); j += blockDim.x) bump(load_index(keys, j));
     typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
     const u32x4* k4 = reinterpret_cast<const u32x4*>(keys);
-    for (int64_t q = a0 / 4 + threadIdx.x; q < a1 / 4; q += blockDim.x) {
-      const u32x4 v = __builtin_nontemporal_load(k4 + q);
+    // four 16-byte loads in flight per thread before the LDS updates
+    const int64_t q1 = a1 / 4;
+    const int64_t step = (int64_t)blockDim.x;
+    for (int64_t q = a0 / 4 + threadIdx.x; q < q1; q += 4 * step) {
+      u32x4 v[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if constexpr (IdxT(-1) < IdxT(0))
-          bump((int64_t)(int32_t)v[e]);
-        else
-          bump((int64_t)v[e]);
+      for (int i = 0; i < 4; ++i)
+        v[i] = (q + i * step < q1) ? __builtin_nontemporal_load(k4 + q + i * step)
+                                   : u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (q + i * step >= q1) break;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if constexpr (IdxT(-1) < IdxT(0))
+            bump((int64_t)(int32_t)v[i][e]);
+          else
+            bump((int64_t)v[i][e]);
+        }
       }
     }
     for (int64_t j = max(a1, a0) + threadIdx.x; j < b1; j += blockDim.x) bump(load_index(keys, j));

@@ -52,6 +52,73 @@ __global__ void __launch_bounds__(256) stencil_step_vec(const float* __restrict_
   if (snap) *reinterpret_cast<float4*>(snap + (int64_t)y * W + x0) = cc;
 }
 
+// Strip form (W % 256 == 0, H % (4 RB) == 0): each wave owns 256 columns
+// (4 per lane) of RB consecutive rows. The RB + 2 input rows it needs are
+// loaded once into registers; left and right neighbours come from the
+// adjacent lanes, and only the two strip-edge cells are read separately. In
+// the adjoint (ADJ) the same body computes S^T g + rho cos(u) g.
+template <int RB, bool ADJ>
+__global__ void __launch_bounds__(256) stencil_strip(const float* __restrict__ u,
+                                                     float* __restrict__ out,
+                                                     float* __restrict__ snap,
+                                                     const float* __restrict__ ustate, int H, int W,
+                                                     float c, float rho, int accumulate) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int x0 = blockIdx.x * 256;
+  const int y0 = (blockIdx.y * 4 + wv) * RB;
+  const int xl = x0 == 0 ? W - 1 : x0 - 1;
+  const int xr = x0 + 256 == W ? 0 : x0 + 256;
+  f32x4 r[RB + 2];
+  float el[RB + 2], er[RB + 2];
+#pragma unroll
+  for (int q = 0; q < RB + 2; ++q) {
+    int y = y0 - 1 + q;
+    y = y < 0 ? y + H : (y >= H ? y - H : y);
+    const float* row = u + (int64_t)y * W;
+    r[q] = *reinterpret_cast<const f32x4*>(row + x0 + 4 * lane);
+    el[q] = row[xl];
+    er[q] = row[xr];
+  }
+  const float a = 1.f - 4.f * c;
+#pragma unroll
+  for (int q = 1; q <= RB; ++q) {
+    const f32x4 cc = r[q], nn = r[q - 1], ss = r[q + 1];
+    float lf = __shfl_up(cc[3], 1, 64);
+    float rt = __shfl_down(cc[0], 1, 64);
+    if (lane == 0) lf = el[q];
+    if (lane == 63) rt = er[q];
+    const int64_t off = (int64_t)(y0 + q - 1) * W + x0 + 4 * lane;
+    f32x4 o;
+    if constexpr (!ADJ) {
+      o[0] = cc[0] + c * (((ss[0] + nn[0]) + cc[1]) + lf - 4.f * cc[0]);
+      o[1] = cc[1] + c * (((ss[1] + nn[1]) + cc[2]) + cc[0] - 4.f * cc[1]);
+      o[2] = cc[2] + c * (((ss[2] + nn[2]) + cc[3]) + cc[1] - 4.f * cc[2]);
+      o[3] = cc[3] + c * (((ss[3] + nn[3]) + rt) + cc[2] - 4.f * cc[3]);
+      if (rho != 0.f) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) o[e] += rho * sinf(cc[e]);
+      }
+      if (snap) *reinterpret_cast<f32x4*>(snap + off) = cc;
+    } else {
+      o[0] = a * cc[0] + c * (((ss[0] + nn[0]) + cc[1]) + lf);
+      o[1] = a * cc[1] + c * (((ss[1] + nn[1]) + cc[2]) + cc[0]);
+      o[2] = a * cc[2] + c * (((ss[2] + nn[2]) + cc[3]) + cc[1]);
+      o[3] = a * cc[3] + c * (((ss[3] + nn[3]) + rt) + cc[2]);
+      if (rho != 0.f) {
+        const f32x4 us = *reinterpret_cast<const f32x4*>(ustate + off);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) o[e] += rho * cosf(us[e]) * cc[e];
+      }
+      if (accumulate) {
+        const f32x4 p = *reinterpret_cast<const f32x4*>(out + off);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) o[e] += p[e];
+      }
+    }
+    *reinterpret_cast<f32x4*>(out + off) = o;
+  }
+}
+
 __global__ void __launch_bounds__(256) stencil_step_scalar(const float* __restrict__ u,
                                                            float* __restrict__ un,
                                                            float* __restrict__ snap, int H,
@@ -218,8 +285,14 @@ St st_of(const dex_desc& d) {
   return s;
 }
 
+constexpr int kRB = 16;
+bool strip_ok(const St& s) { return s.W % 256 == 0 && s.H % (4 * kRB) == 0; }
+
 void step(const St& s, const float* u, float* un, float* snap, hipStream_t st) {
-  if (s.vec) {
+  if (strip_ok(s)) {
+    hipLaunchKernelGGL((stencil_strip<kRB, false>), dim3(s.W / 256, s.H / (4 * kRB)), dim3(256), 0,
+                       st, u, un, snap, nullptr, s.H, s.W, s.c, s.rho, 0);
+  } else if (s.vec) {
     const int64_t nt = s.n / 4;
     hipLaunchKernelGGL(stencil_step_vec, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, u,
                        un, snap, s.H, s.W, s.c, s.rho);
@@ -236,6 +309,9 @@ void adj(const St& s, int form, const float* g, const float* u, float* out, bool
     if (!accumulate) fill_zero(out, (size_t)s.n * 4, st);
     hipLaunchKernelGGL(stencil_adj_scatter, dim3(nb), dim3(256), 0, st, g, u, out, s.H, s.W, s.c,
                        s.rho);
+  } else if (strip_ok(s)) {
+    hipLaunchKernelGGL((stencil_strip<kRB, true>), dim3(s.W / 256, s.H / (4 * kRB)), dim3(256), 0,
+                       st, g, out, nullptr, u, s.H, s.W, s.c, s.rho, accumulate ? 1 : 0);
   } else if (s.vec) {
     hipLaunchKernelGGL(stencil_adj_gather_vec, dim3((unsigned)((s.n / 4 + 255) / 256)), dim3(256),
                        0, st, g, u, out, s.H, s.W, s.c, s.rho, accumulate ? 1 : 0);

@@ -38,7 +38,8 @@ def run(u0, target, steps, every, rho=0.0, variant=0, vcfg=0, dev="cuda", ct=1.0
 
 
 @pytest.mark.parametrize("H,W,steps,every", [(32, 24, 7, 3), (16, 16, 50, 32), (9, 13, 11, 4),
-                                             (64, 64, 100, 32), (8, 40, 1, 1), (12, 12, 0, 5)])
+                                             (64, 64, 100, 32), (8, 40, 1, 1), (12, 12, 0, 5),
+                                             (64, 256, 20, 8), (128, 512, 33, 32)])
 def test_matches_oracle(dev, H, W, steps, every):
     u0, tg = workloads.stencil_inputs(H, W, 1)
     L, uT, du, ck = run(u0, tg, steps, every)
@@ -66,9 +67,10 @@ def test_scatter_form_adjoint(dev):
     assert rel(g_scatter, ost.loss_and_grad(u0, tg, 30)[2]) <= 1e-5
 
 
+@pytest.mark.parametrize("H,W", [(40, 36), (64, 256)])
 @pytest.mark.parametrize("rho", [0.05, -0.2])
-def test_nonlinear_term_needs_recompute(dev, rho):
-    u0, tg = workloads.stencil_inputs(40, 36, 5)
+def test_nonlinear_term_needs_recompute(dev, rho, H, W):
+    u0, tg = workloads.stencil_inputs(H, W, 5)
     L, uT, du, _ = run(u0, tg, 40, 6, rho=rho)
     Lo, uTo, duo = ost.loss_and_grad(u0, tg, 40, rho=rho)
     assert abs(L - Lo) <= 1e-5 * abs(Lo)
