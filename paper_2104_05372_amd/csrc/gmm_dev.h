@@ -447,29 +447,21 @@ DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0blk, int k0, in
       cc[rb] = *reinterpret_cast<const f32x4*>(ops.negc + (size_t)k * DP + 16 * rb + 4 * g);
     kp = ops.kappa[k];
   };
-  load_k(k0, qa, ci, kap);
-
-  for (int k = k0; k < k1; ++k) {
-    Op<PREC, NV> qn[NQ];
-    f32x4 cn[NRB];
-    float kn;
-    load_k(k + 1 < k1 ? k + 1 : k, qn, cn, kn);
+  auto compute_k = [&](int k, const Op<PREC, NV>(&q)[NQ], const f32x4(&cc)[NRB], float kp) {
     f32x4 acc[CB][NRB];
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) acc[cb][rb] = ci[rb];
-    {
-      int n = 0;
+      for (int cb = 0; cb < CB; ++cb) acc[cb][rb] = cc[rb];
+    int n = 0;
 #pragma unroll
-      for (int rb = 0; rb < NRB; ++rb) {
+    for (int rb = 0; rb < NRB; ++rb) {
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-          if (CK * ch > 16 * rb + 15) continue;  // chunk wholly above the diagonal
-          const Op<PREC, NV>& q = qa[n++];
+      for (int ch = 0; ch < NCH; ++ch) {
+        if (CK * ch > 16 * rb + 15) continue;  // chunk wholly above the diagonal
+        const Op<PREC, NV>& qq = q[n++];
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) acc[cb][rb] = mma<PREC, NV>(q, xb[cb][ch], acc[cb][rb]);
-        }
+        for (int cb = 0; cb < CB; ++cb) acc[cb][rb] = mma<PREC, NV>(qq, xb[cb][ch], acc[cb][rb]);
       }
     }
     float s[CB];
@@ -483,7 +475,7 @@ DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0blk, int k0, in
       s[cb] = t;
     }
     treduce_groups<CB>(s);
-    const float b = kap - 0.5f * s[0];
+    const float b = kp - 0.5f * s[0];
     if (owner && p < N) beta[(size_t)k * Npad + p] = b;
     const float d = b - m;
     if (d > 0.f) {
@@ -492,12 +484,22 @@ DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0blk, int k0, in
     } else {
       lsum += __expf(d);
     }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) qa[q] = qn[q];
-#pragma unroll
-    for (int rb = 0; rb < NRB; ++rb) ci[rb] = cn[rb];
-    kap = kn;
+  };
+
+  // two operand sets in turn: the next component's loads are in flight while
+  // the current one is computed, without register copies
+  Op<PREC, NV> qb[NQ];
+  f32x4 cb2[NRB];
+  float kb;
+  load_k(k0, qa, ci, kap);
+  int k = k0;
+  for (; k + 1 < k1; k += 2) {
+    load_k(k + 1, qb, cb2, kb);
+    compute_k(k, qa, ci, kap);
+    if (k + 2 < k1) load_k(k + 2, qa, ci, kap);
+    compute_k(k + 1, qb, cb2, kb);
   }
+  if (k < k1) compute_k(k, qa, ci, kap);
   if (owner) ml[p] = make_float2(m, lsum);
 }
 
