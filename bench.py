@@ -382,6 +382,8 @@ def main(argv=None):
     ap.add_argument("--variant", choices=["bf16", "bf16x3", "fp32"], default="bf16")
     ap.add_argument("--no-rows", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="also run one 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--configs", default=None,
                     help="forward,reverse tile configuration (1-based); skips the autotuner")
     ap.add_argument("--rows-only", default=None, help="comma list of rows to run (scatter,hist,batched,stencil)")
@@ -398,6 +400,15 @@ def main(argv=None):
     dex.dex_init()
     log("headline: GMM gradient N=100000 D=64 K=200", args.variant)
     H = run_headline(torch, dex, workloads, args, dev)
+    if args.calibration_copy:
+        # a device copy of known size (256 MiB read + 256 MiB written): the
+        # reference for scaling the HBM byte counters of a profiled run
+        src = torch.ones(64 << 20, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     line = {
         "metric": METRIC, "value": round(H["value"], 3), "unit": "grad evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(H["ms"], 4),

@@ -74,6 +74,117 @@ __device__ inline MfmaOps bops(const BInst& I, const char* cache) {
   return o;
 }
 
+// ---------------------------------------------------------------------------
+// D <= 8: the 16x16 matrix-core tiles would be mostly padding, so these
+// instances run on the vector units, one lane per point. Q~, -c~ and kappa are
+// read from the same operand cache (DP = 16, row-major, zero padded).
+template <int DV>
+DEX_DEV void fwd_unit_valu(const MfmaOps& o, int N, int Npad, int p0blk, int npts, int K,
+                           float* __restrict__ beta, float2* __restrict__ ml) {
+  const int p = p0blk + (int)threadIdx.x;
+  if ((int)threadIdx.x >= npts) return;
+  const float* xh = (const float*)o.xh;
+  const float* Q = (const float*)o.Qh;
+  float x[DV];
+#pragma unroll
+  for (int b = 0; b < DV; ++b) x[b] = xh[(size_t)p * 16 + b];
+  float m = -INFINITY, lsum = 0.f;
+  for (int k = 0; k < K; ++k) {
+    const float* Qk = Q + (size_t)k * 256;
+    float s = 0.f;
+#pragma unroll
+    for (int a = 0; a < DV; ++a) {
+      float y = o.negc[(size_t)k * 16 + a];
+#pragma unroll
+      for (int b = 0; b <= a; ++b) y = fmaf(Qk[a * 16 + b], x[b], y);
+      s = fmaf(y, y, s);
+    }
+    const float bv = o.kappa[k] - 0.5f * s;
+    if (p < N) beta[(size_t)k * Npad + p] = bv;
+    const float d = bv - m;
+    if (d > 0.f) {
+      lsum = lsum * __expf(-d) + 1.f;
+      m = bv;
+    } else {
+      lsum += __expf(d);
+    }
+  }
+  ml[p] = make_float2(m, lsum);
+}
+
+// Reverse for D <= 8: wave wv accumulates, per component, the lane-private sums
+// of w x_a x_b (a >= b), w x_a and w over the points [pbeg, pend), reduces them
+// across the wave and writes them in the partial-slot layout of bwd_mom_unit
+// (DP = 16, one 16x16 block).
+template <int DV, int GW>
+DEX_DEV void bwd_unit_valu(const float* __restrict__ xh, int N, int Npad, int K, int kbase,
+                           int pbeg, int pend, const float* __restrict__ beta,
+                           const float* __restrict__ f, float ctv, float* __restrict__ part,
+                           size_t pstride) {
+  constexpr int NS = DV * (DV + 1) / 2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int kw = kbase + wv * GW;
+  if (kw >= K) return;
+  float sacc[GW][NS], uacc[GW][DV], aacc[GW];
+#pragma unroll
+  for (int gk = 0; gk < GW; ++gk) {
+#pragma unroll
+    for (int e = 0; e < NS; ++e) sacc[gk][e] = 0.f;
+#pragma unroll
+    for (int a = 0; a < DV; ++a) uacc[gk][a] = 0.f;
+    aacc[gk] = 0.f;
+  }
+  for (int t0 = pbeg; t0 < pend; t0 += 64) {
+    const int p = t0 + lane;
+    const bool valid = p < N;
+    float x[DV];
+#pragma unroll
+    for (int b = 0; b < DV; ++b) x[b] = xh[(size_t)p * 16 + b];
+    const float fp = valid ? f[p] : 0.f;
+#pragma unroll
+    for (int gk = 0; gk < GW; ++gk) {
+      const int k = kw + gk;
+      if (k >= K) break;
+      const float w = valid ? __expf(beta[(size_t)k * Npad + p] - fp) * ctv : 0.f;
+      aacc[gk] += w;
+      float wx[DV];
+#pragma unroll
+      for (int a = 0; a < DV; ++a) {
+        wx[a] = w * x[a];
+        uacc[gk][a] += wx[a];
+      }
+      int e = 0;
+#pragma unroll
+      for (int a = 0; a < DV; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+          sacc[gk][e] = fmaf(wx[a], x[b], sacc[gk][e]);
+          ++e;
+        }
+    }
+  }
+#pragma unroll
+  for (int gk = 0; gk < GW; ++gk) {
+    const int k = kw + gk;
+    if (k >= K) break;
+    float* P = part + (size_t)k * pstride;
+    int e = 0;
+#pragma unroll
+    for (int a = 0; a < DV; ++a) {
+#pragma unroll
+      for (int b = 0; b <= a; ++b) {
+        const float v = wave_sum(sacc[gk][e++]);
+        // entry (r = b, s = a) of the 16x16 block, in matrix-core output order
+        if (lane == 0) P[(16 * (a >> 2) + b) * 4 + (a & 3)] = v;
+      }
+      const float uv = wave_sum(uacc[gk][a]);
+      if (lane == 0) P[256 + a] = uv;
+    }
+    const float av = wave_sum(aacc[gk]);
+    if (lane == 0) P[256 + 16] = av;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_bprep_x(const char* __restrict__ plan,
                                                  const float* __restrict__ x, char* cache) {
   const PlanHeader* h = hdr(plan);
@@ -135,7 +246,9 @@ __global__ void __launch_bounds__(256) k_bgmm_fwd(const char* __restrict__ plan,
     const BInst I = inst[w.inst];
     const MfmaOps o = bops(I, cache);
     float* beta = (float*)(cache + I.beta_off);
-    if (I.DP == 16)
+    if (I.D <= 8)
+      fwd_unit_valu<8>(o, I.N, (int)I.Npad, w.a * 64 * CB, 64 * CB, I.K, beta, ml + I.ml_off);
+    else if (I.DP == 16)
       fwd_unit<16, PREC_F32, CB, 16>(o, I.N, (int)I.Npad, w.a * 64 * CB, 0, I.K, beta, ml + I.ml_off);
     else
       fwd_unit<32, PREC_F32, CB, 16>(o, I.N, (int)I.Npad, w.a * 64 * CB, 0, I.K, beta, ml + I.ml_off);
@@ -187,7 +300,10 @@ __global__ void __launch_bounds__(256) k_bgmm_bwd(const char* __restrict__ plan,
     const int pend = (int)std::min<int64_t>(I.Npad, pbeg + chunk);
     const size_t E = mom_slot(I.DP);
     float* P = part + I.part_off + (size_t)w.b * I.K * E;
-    if (I.DP == 16)
+    if (I.D <= 8)
+      bwd_unit_valu<8, GW>((const float*)(cache + I.xh_off), I.N, (int)I.Npad, I.K, w.a * 4 * GW,
+                           pbeg, pend, beta, f + I.f_off, ct[w.inst], P, E);
+    else if (I.DP == 16)
       bwd_mom_unit<16, MP_F32, GW>(cache + I.xhT_off, nullptr, I.N, (int)I.Npad, I.K, w.a * 4 * GW,
                                    pbeg, pend, beta, f + I.f_off, ct[w.inst], P, E);
     else
