@@ -298,7 +298,9 @@ def row_stencil(torch, dex, workloads, dev, steps):
     u0 = torch.randn(H, W, device=dev, generator=gen)
     tg = torch.randn(H, W, device=dev, generator=gen)
     out = {"workload": f"{H}x{W} f32 periodic 5-point diffusion, {T} steps, checkpoint every {every}"}
-    for name, variant in (("recompute", dex.DEX_STENCIL_RECOMPUTE), ("linear", dex.DEX_STENCIL_LINEAR)):
+    for name, variant, fc, vc in (("recompute", dex.DEX_STENCIL_RECOMPUTE, 0, 0),
+                                  ("linear", dex.DEX_STENCIL_LINEAR, 0, 0),
+                                  ("recompute_vector_kernels", dex.DEX_STENCIL_RECOMPUTE, 2, 3)):
         d = dex.stencil_desc(H, W, T, every, 0.2, 0.0, variant)
         nck = (T + every - 1) // every
         L = torch.empty(1, device=dev)
@@ -310,9 +312,11 @@ def row_stencil(torch, dex, workloads, dev, steps):
         ct = torch.ones(1, device=dev)
 
         def fwd():
+            d.config = fc
             dex.dex_fwd(d, [u0, tg], [L, uT], [ck, uT], wsf)
 
         def vjp():
+            d.config = vc
             dex.dex_vjp(d, [u0, tg], [ck, uT], [ct], [du], 0, wsb)
 
         fwd()

@@ -167,6 +167,11 @@ typedef struct dex_buf {
  *   The reverse pass runs the time loop backwards (ForTranspose); with
  *   DEX_STENCIL_RECOMPUTE it rebuilds each segment's states from its
  *   checkpoint first (only non-linear terms read them, Sec. 5.3.2).
+ *   configs: fwd 1 row-strip kernel (default; used where W % 256 == 0 and
+ *   H % 32 == 0, else the vector kernel), 2 vector kernel; vjp 1 gather-form
+ *   adjoint with row-strip kernels where allowed (default), 2 scatter-form
+ *   adjoint (atomics), 3 gather form with vector kernels. All configs compute
+ *   the same values.
  */
 
 /* Message for a status code (static storage). */

@@ -36,8 +36,12 @@ UNITS = [
 # -packed-fp32-ops: no packed FP32 instructions are generated (they are kept
 # out of every kernel on purpose). The host pass warns that it does not know
 # the feature; that warning is harmless.
+# -amdgpu-mfma-vgpr-form: matrix-core results stay in ordinary VGPRs, so the
+# epilogues read them without accumulator-register copies and the kernels need
+# about half the registers (more waves per SIMD).
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-munsafe-fp-atomics",
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument", "-I", os.path.join(os.path.dirname(PKG), "include"),
 ]

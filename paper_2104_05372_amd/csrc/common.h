@@ -16,9 +16,27 @@ typedef __attribute__((__vector_size__(8 * sizeof(float)))) float f32x8;
 constexpr int kWave = 64;
 
 // ---- wave-level exchange -------------------------------------------------
+// Value of `v` held by lane (lane ^ 32) / (lane ^ 16), through the gfx950 lane
+// swaps (VALU, no LDS traffic, no lgkm wait). The swap leaves the lane's own
+// value in one of the two results and its partner's in the other; the own
+// value is recognised by its bits, so the choice does not depend on which
+// half the instruction moves.
+DEX_DEV uint32_t swap_partner32(uint32_t v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return r[0] == v ? r[1] : r[0];
+}
+DEX_DEV uint32_t swap_partner16(uint32_t v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return r[0] == v ? r[1] : r[0];
+}
+
 // Value of `v` held by lane (lane ^ mask).
 template <typename T>
 DEX_DEV T xor_lane(T v, int mask) {
+  if constexpr (sizeof(T) == 4) {
+    if (mask == 32) return __builtin_bit_cast(T, swap_partner32(__builtin_bit_cast(uint32_t, v)));
+    if (mask == 16) return __builtin_bit_cast(T, swap_partner16(__builtin_bit_cast(uint32_t, v)));
+  }
   return __shfl_xor(v, mask, kWave);
 }
 

@@ -190,12 +190,16 @@ __global__ void __launch_bounds__(256) k_bwd_finalize(const TP* __restrict__ par
                            means, ct[0], d_alphas, d_means, d_qd, d_l, accumulate);
 }
 
+// Split reverse pass (see FlatSplit): component k's partials are those of
+// the waves that owned part of its group's point steps.
 __global__ void __launch_bounds__(256) k_bwd_finalize_mom(
-    const float* __restrict__ part, size_t E, int S, int K, int D, int DP, int64_t N,
-    const float* __restrict__ alphas, const float* __restrict__ means, const float* __restrict__ qd,
-    const float* __restrict__ l, const float* __restrict__ ct, float* __restrict__ d_alphas,
-    float* __restrict__ d_means, float* __restrict__ d_qd, float* __restrict__ d_l, int accumulate) {
+    const float* __restrict__ part, size_t E, int gw, int64_t nsteps, int64_t Tu, int64_t Wu,
+    int K, int D, int DP, int64_t N, const float* __restrict__ alphas,
+    const float* __restrict__ means, const float* __restrict__ qd, const float* __restrict__ l,
+    const float* __restrict__ ct, float* __restrict__ d_alphas, float* __restrict__ d_means,
+    float* __restrict__ d_qd, float* __restrict__ d_l, int accumulate) {
   const int k = blockIdx.x;
+  const int S = split_slots((int64_t)(k / gw) * nsteps, nsteps, Tu, Wu);
   bwd_finalize_mom(part + (size_t)k * E, (size_t)K * E, S, k, K, D, DP, N, alphas, means, qd, l,
                    ct[0], d_alphas, d_means, d_qd, d_l, accumulate);
 }
@@ -230,21 +234,18 @@ Shape shape_of(const dex_desc& d) {
   return s;
 }
 
-// forward candidates: (points per wave / 16, k-splits, chunk depth)
-const FwdCfg kFwdBF[] = {{4, 1, 32}, {4, 2, 32}, {2, 1, 32}, {4, 1, 16}, {4, 2, 16}, {2, 2, 32}};
-const FwdCfg kFwdF32[] = {{4, 1, 16}, {4, 2, 16}, {2, 1, 16}, {2, 2, 16}};
-// reverse candidates: (points per tile / 16, components per wave, chunk depth, point chunks)
-// reverse candidates: (components per wave, point chunks)
-const BwdCfg kBwdBF[] = {{2, 16}, {2, 32}, {4, 16}, {4, 32}, {1, 16}, {1, 32}, {2, 8}, {4, 8}};
-const BwdCfg kBwdF32[] = {{2, 16}, {1, 16}, {4, 16}, {2, 32}, {1, 32}};
-constexpr int kMaxSk = 2;
-constexpr int kMaxS = 32;
+// forward candidates: (components resident per wave, waves per SIMD (0: all resident))
+const FwdCfg kFwdBF[] = {{4, 0}, {4, 1}, {4, 2}, {2, 0}, {2, 2}, {2, 3}};
+const FwdCfg kFwdF32[] = {{2, 0}, {2, 1}, {2, 2}, {2, 3}};
+// reverse candidates: (components per wave, waves per SIMD (0: all resident))
+const BwdCfg kBwdBF[] = {{2, 0}, {1, 0}, {4, 0}, {2, 2}, {1, 2}, {1, 3}, {2, 1}, {4, 1}};
+const BwdCfg kBwdF32[] = {{2, 0}, {1, 0}, {4, 0}, {2, 2}, {1, 2}};
 constexpr int kValuS = 16;
 
-int nfwd(const Shape& s) { return s.prec == PREC_F32 ? 4 : 6; }
+int nfwd(const Shape& s) { return s.prec == PREC_BF16 ? 6 : 4; }
 int nbwd(const Shape& s) { return s.prec == PREC_F32 ? 5 : 8; }
 size_t mom_es(const Shape& s) { return s.prec == PREC_F32 ? 4 : 2; }
-FwdCfg fwd_cfg(const Shape& s, int i) { return s.prec == PREC_F32 ? kFwdF32[i] : kFwdBF[i]; }
+FwdCfg fwd_cfg(const Shape& s, int i) { return s.prec == PREC_BF16 ? kFwdBF[i] : kFwdF32[i]; }
 BwdCfg bwd_cfg(const Shape& s, int i) { return s.prec == PREC_F32 ? kBwdF32[i] : kBwdBF[i]; }
 
 struct CacheLayout {
@@ -271,7 +272,7 @@ CacheLayout cache_layout(const Shape& s) {
     c.Ql = lo ? take(g.K * g.DP * g.DP * es) : 0;
     c.negc = take(g.K * g.DP * 4);
     c.kappa = take(g.K * 4);
-    c.beta = take(g.K * g.Npad * 4);
+    c.beta = take(beta_rows(g.K) * g.Npad * 4);
   } else {
     c.beta = take(g.K * g.N * s.tsize);
   }
@@ -357,10 +358,11 @@ size_t gmm_ws_bytes(const dex_desc& d, int role) {
   const size_t nblk = (size_t)(s.g.Npad / 256);
   if (role == DEX_WS_FWD) {
     size_t b = align256(nblk * 2 * s.tsize);
-    if (s.mfma) b += align256((size_t)kMaxSk * s.g.Npad * sizeof(float2));
+    if (s.mfma) b += align256((size_t)fwd_max_slots(s.g.K) * s.g.Npad * sizeof(float2));
     return b;
   }
-  if (s.mfma) return align256((size_t)kMaxS * s.g.K * mom_slot(s.g.DP) * 4);
+  if (s.mfma)
+    return align256((size_t)bwd_max_slots(s.g.Npad, s.g.K) * s.g.K * mom_slot(s.g.DP) * 4);
   return align256((size_t)kValuS * s.g.K * (s.g.D * s.g.D + s.g.D + 1) * s.tsize);
 }
 
@@ -397,12 +399,13 @@ dex_status gmm_fwd(const dex_desc& d, int cfg, const GmmPtrs& in, void* F, void*
   void *xh = cc + cl.xh, *xl = cc + cl.xl, *xhT = cc + cl.xhT, *xlT = cc + cl.xlT, *Qh = cc + cl.Qh,
        *Ql = cc + cl.Ql;
   float *negc = (float*)(cc + cl.negc), *kappa = (float*)(cc + cl.kappa);
+  FlatSplit sp{};
   switch (s.prec) {
     case PREC_BF16:
       mfma_prep<PREC_BF16>(s.g, x, al, mu, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
       {
         ProfRange pr(DEX_PROF_GMM_FWD, st);
-        mfma_fwd<PREC_BF16>(s.g, c, o, beta, ml, st);
+        sp = mfma_fwd<PREC_BF16>(s.g, c, o, beta, ml, st);
         pr.end(1);
       }
       break;
@@ -410,7 +413,7 @@ dex_status gmm_fwd(const dex_desc& d, int cfg, const GmmPtrs& in, void* F, void*
       mfma_prep<PREC_BF16X3>(s.g, x, al, mu, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
       {
         ProfRange pr(DEX_PROF_GMM_FWD, st);
-        mfma_fwd<PREC_BF16X3>(s.g, c, o, beta, ml, st);
+        sp = mfma_fwd<PREC_BF16X3>(s.g, c, o, beta, ml, st);
         pr.end(1);
       }
       break;
@@ -418,11 +421,11 @@ dex_status gmm_fwd(const dex_desc& d, int cfg, const GmmPtrs& in, void* F, void*
       mfma_prep<PREC_F32>(s.g, x, al, mu, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
       {
         ProfRange pr(DEX_PROF_GMM_FWD, st);
-        mfma_fwd<PREC_F32>(s.g, c, o, beta, ml, st);
+        sp = mfma_fwd<PREC_F32>(s.g, c, o, beta, ml, st);
         pr.end(1);
       }
   }
-  hipLaunchKernelGGL((k_merge_lse<float>), dim3((unsigned)nblk), dim3(256), 0, st, ml, c.sk,
+  hipLaunchKernelGGL((k_merge_lse<float>), dim3((unsigned)nblk), dim3(256), 0, st, ml, sp.sk,
                      (int)s.g.N, (int)s.g.Npad, (float*)f, fpart);
   hipLaunchKernelGGL((k_finalize_F<float>), dim3(1), dim3(256), 0, st, fpart, (int)nblk, al,
                      (int)s.g.K, s.g.N, (float*)F);
@@ -455,25 +458,24 @@ dex_status gmm_vjp(const dex_desc& d, int cfg, const GmmPtrs& in, const void* f,
   const float* beta = (const float*)(cc + cl.beta);
   float* part = (float*)ws;
   ProfRange pr(DEX_PROF_GMM_VJP, st);
+  FlatSplit sp{};
   switch (s.prec) {
     case PREC_BF16:
-      mfma_bwd<PREC_BF16>(s.g, c, o, beta, (const float*)f, (const float*)ct, part, st);
+      sp = mfma_bwd<PREC_BF16>(s.g, c, o, beta, (const float*)f, (const float*)ct, part, st);
       break;
     case PREC_BF16X3:
-      mfma_bwd<PREC_BF16X3>(s.g, c, o, beta, (const float*)f, (const float*)ct, part, st);
+      sp = mfma_bwd<PREC_BF16X3>(s.g, c, o, beta, (const float*)f, (const float*)ct, part, st);
       break;
     default:
-      mfma_bwd<PREC_F32>(s.g, c, o, beta, (const float*)f, (const float*)ct, part, st);
+      sp = mfma_bwd<PREC_F32>(s.g, c, o, beta, (const float*)f, (const float*)ct, part, st);
   }
   pr.end(1);
-  int64_t chunk;
-  int nch;
-  bwd_chunks(s.g.Npad, c.s, &chunk, &nch);
   hipLaunchKernelGGL(k_bwd_finalize_mom, dim3((unsigned)s.g.K), dim3(256), 0, st, (const float*)part,
-                     mom_slot(s.g.DP), nch, (int)s.g.K, (int)s.g.D, s.g.DP, s.g.N,
-                     (const float*)in.alphas, (const float*)in.means, (const float*)in.qd,
-                     (const float*)in.l, (const float*)ct, (float*)out.d_alphas,
-                     (float*)out.d_means, (float*)out.d_qd, (float*)out.d_l, accumulate ? 1 : 0);
+                     mom_slot(s.g.DP), sp.gw, sp.nsteps, sp.T, (int64_t)sp.W, (int)s.g.K,
+                     (int)s.g.D, s.g.DP, s.g.N, (const float*)in.alphas, (const float*)in.means,
+                     (const float*)in.qd, (const float*)in.l, (const float*)ct,
+                     (float*)out.d_alphas, (float*)out.d_means, (float*)out.d_qd, (float*)out.d_l,
+                     accumulate ? 1 : 0);
   return check_hip(hipGetLastError(), "gmm_vjp (MFMA)");
 }
 

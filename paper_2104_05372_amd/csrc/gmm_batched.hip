@@ -249,9 +249,11 @@ __global__ void __launch_bounds__(256) k_bgmm_fwd(const char* __restrict__ plan,
     if (I.D <= 8)
       fwd_unit_valu<8>(o, I.N, (int)I.Npad, w.a * 64 * CB, 64 * CB, I.K, beta, ml + I.ml_off);
     else if (I.DP == 16)
-      fwd_unit<16, PREC_F32, CB, 16>(o, I.N, (int)I.Npad, w.a * 64 * CB, 0, I.K, beta, ml + I.ml_off);
+      fwd_unit<16, PREC_F32, CB, 16>(o, I.N, (int)I.Npad, w.a * 64 * CB + (threadIdx.x >> 6) * 16 * CB,
+                                     0, I.K, beta, ml + I.ml_off);
     else
-      fwd_unit<32, PREC_F32, CB, 16>(o, I.N, (int)I.Npad, w.a * 64 * CB, 0, I.K, beta, ml + I.ml_off);
+      fwd_unit<32, PREC_F32, CB, 16>(o, I.N, (int)I.Npad, w.a * 64 * CB + (threadIdx.x >> 6) * 16 * CB,
+                                     0, I.K, beta, ml + I.ml_off);
   }
 }
 
@@ -304,10 +306,12 @@ __global__ void __launch_bounds__(256) k_bgmm_bwd(const char* __restrict__ plan,
       bwd_unit_valu<8, GW>((const float*)(cache + I.xh_off), I.N, (int)I.Npad, I.K, w.a * 4 * GW,
                            pbeg, pend, beta, f + I.f_off, ct[w.inst], P, E);
     else if (I.DP == 16)
-      bwd_mom_unit<16, MP_F32, GW>(cache + I.xhT_off, nullptr, I.N, (int)I.Npad, I.K, w.a * 4 * GW,
+      bwd_mom_unit<16, MP_F32, GW>(cache + I.xhT_off, nullptr, I.N, (int)I.Npad, I.K,
+                                   w.a * 4 * GW + (threadIdx.x >> 6) * GW,
                                    pbeg, pend, beta, f + I.f_off, ct[w.inst], P, E);
     else
-      bwd_mom_unit<32, MP_F32, GW>(cache + I.xhT_off, nullptr, I.N, (int)I.Npad, I.K, w.a * 4 * GW,
+      bwd_mom_unit<32, MP_F32, GW>(cache + I.xhT_off, nullptr, I.N, (int)I.Npad, I.K,
+                                   w.a * 4 * GW + (threadIdx.x >> 6) * GW,
                                    pbeg, pend, beta, f + I.f_off, ct[w.inst], P, E);
   }
 }

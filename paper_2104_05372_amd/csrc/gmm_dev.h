@@ -303,6 +303,19 @@ DEX_DEV f32x4 mom_mma1(const typename MomT<MP>::V8& a, const typename MomT<MP>::
   return c;
 }
 
+// Even split of T equal work units over W waves (W <= T, so no wave is idle):
+// wave w owns the units [split_lo(w), split_lo(w + 1)).
+__host__ __device__ inline int64_t split_lo(int64_t w, int64_t T, int64_t W) { return T * w / W; }
+// The wave that owns unit i.
+__host__ __device__ inline int64_t split_owner(int64_t i, int64_t T, int64_t W) {
+  return ((i + 1) * W - 1) / T;
+}
+// Number of waves owning part of the units [a, a + len): the partial results
+// a segment of that length is split into.
+__host__ __device__ inline int split_slots(int64_t a, int64_t len, int64_t T, int64_t W) {
+  return (int)(split_owner(a + len - 1, T, W) - split_owner(a, T, W) + 1);
+}
+
 // Number of Q~ contraction chunks (depth CK) that meet the lower triangle.
 __host__ __device__ constexpr int fwd_nq(int DP, int CK) {
   int n = 0;
@@ -383,19 +396,18 @@ DEX_DEV void prep_q_comp(const float* __restrict__ alphas, const float* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Forward unit: 4 waves x 16*CB points from p0, components [k0, k1).
-// Each wave builds Y^T (DP x 16*CB) = Q~_k X~^T - c~ from 16x16 tiles (row
+// Forward unit of one wave: 16*CB points from p0, components [k0, k1).
+// The wave builds Y^T (DP x 16*CB) = Q~_k X~^T - c~ from 16x16 tiles (row
 // block rb of Q, column block cb of points). A point's squared norm reduces
 // across the 4 lane groups, after which each lane owns one point and keeps its
 // running log-sum-exp over the k-range.
 template <int DP, int PREC, int CB, int CK>
-DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0blk, int k0, int k1,
+DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0, int k0, int k1,
                       float* __restrict__ beta, float2* __restrict__ ml) {
   using S = typename Store<PREC>::S;
   constexpr int NV = CK / 4;
   constexpr int NRB = DP / 16, NCH = DP / CK;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
-  const int p0 = p0blk + wv * (16 * CB);
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   const S* xh = (const S*)ops.xh;
   const S* xl = (const S*)ops.xl;
   const S* Qh = (const S*)ops.Qh;
@@ -476,18 +488,24 @@ DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0blk, int k0, in
     }
     treduce_groups<CB>(s);
     const float b = kp - 0.5f * s[0];
-    if (owner && p < N) beta[(size_t)k * Npad + p] = b;
+    // every lane stores: lanes that share a point hold bit-identical totals,
+    // and the padded points (p < Npad) have finite residuals nobody reads.
+    // No branch here keeps the operand prefetch of the next component alive.
+    // The residual streams out (read again only by the reverse pass), so it
+    // is stored non-temporally and does not evict the Q~ operands from L2.
+    __builtin_nontemporal_store(b, &beta[(size_t)k * Npad + p]);
     const float d = b - m;
-    if (d > 0.f) {
-      lsum = lsum * __expf(-d) + 1.f;
-      m = b;
-    } else {
-      lsum += __expf(d);
-    }
+    const float e = __expf(-fabsf(d));
+    lsum = d > 0.f ? fmaf(lsum, e, 1.f) : lsum + e;
+    m = fmaxf(m, b);
   };
 
   // two operand sets in turn: the next component's loads are in flight while
-  // the current one is computed, without register copies
+  // the current one is computed, without register copies. The scheduling
+  // barriers keep the issue order loads(k+1), compute(k), store(k),
+  // loads(k+2), ...: the wait for a set then never covers the loads issued
+  // after it, and the residual store before it has had a whole component's
+  // compute to complete (vector memory operations retire in issue order).
   Op<PREC, NV> qb[NQ];
   f32x4 cb2[NRB];
   float kb;
@@ -495,12 +513,121 @@ DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0blk, int k0, in
   int k = k0;
   for (; k + 1 < k1; k += 2) {
     load_k(k + 1, qb, cb2, kb);
+    __builtin_amdgcn_sched_barrier(0);
     compute_k(k, qa, ci, kap);
-    if (k + 2 < k1) load_k(k + 2, qa, ci, kap);
+    __builtin_amdgcn_sched_barrier(0);
+    load_k(min(k + 2, k1 - 1), qa, ci, kap);  // unconditional: no branch between loads and use
+    __builtin_amdgcn_sched_barrier(0);
     compute_k(k + 1, qb, cb2, kb);
+    __builtin_amdgcn_sched_barrier(0);
   }
   if (k < k1) compute_k(k, qa, ci, kap);
   if (owner) ml[p] = make_float2(m, lsum);
+}
+
+// ---------------------------------------------------------------------------
+// Forward unit of one wave, components resident: the Q~ operands, -c~ and
+// kappa of the NKQ components k0 .. k0+NKQ-1 stay in registers while the
+// 16-point tiles t0 .. t1-1 of x~ stream through them (the next tile is loaded
+// while the current one is computed). Every Q~ chunk load thus serves all the
+// wave's tiles, instead of one tile set per load. Per tile, the squared norms
+// of the NKQ components reduce across the 4 lane groups so that lane group
+// jown(g) owns component k0 + jown of point c; it stores beta (rows padded to
+// a multiple of 4 components, so the padding components of the last group
+// need no mask) and the tile's (max, sum) log-sum-exp partial over the
+// group's valid components.
+template <int DP, int PREC, int NKQ, int CK>
+DEX_DEV void fwd_unit_kq(const MfmaOps& ops, int Npad, int K, int k0, int t0, int t1,
+                         float* __restrict__ beta, float2* __restrict__ mlg) {
+  static_assert(NKQ == 2 || NKQ == 4, "components per wave");
+  using S = typename Store<PREC>::S;
+  constexpr int NV = CK / 4;
+  constexpr int NRB = DP / 16, NCH = DP / CK;
+  constexpr int NQ = fwd_nq(DP, CK);
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const S* xh = (const S*)ops.xh;
+  const S* xl = (const S*)ops.xl;
+  const S* Qh = (const S*)ops.Qh;
+  const S* Ql = (const S*)ops.Ql;
+
+  Op<PREC, NV> q[NKQ][NQ];
+  f32x4 nc[NKQ][NRB];
+#pragma unroll
+  for (int j = 0; j < NKQ; ++j) {
+    const int k = min(k0 + j, K - 1);  // past K: computed, stored in padding rows, not merged
+    const size_t qoff = (size_t)k * DP * DP;
+    int n = 0;
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+        if (CK * ch <= 16 * rb + 15)
+          q[j][n++] = load_op<PREC, NV>(Qh + qoff, Ql ? Ql + qoff : nullptr,
+                                        (size_t)(16 * rb + c) * DP + CK * ch + NV * g);
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+      nc[j][rb] = *reinterpret_cast<const f32x4*>(ops.negc + (size_t)k * DP + 16 * rb + 4 * g);
+  }
+  const int jown = NKQ == 4 ? g : g >> 1;
+  const int kown = k0 + jown;
+  const bool vown = kown < K;
+  const float kap = ops.kappa[min(kown, K - 1)];
+  float* brow = beta + (size_t)kown * Npad;
+
+  auto load_x = [&](int t, Op<PREC, NV>(&xb)[NCH]) {
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+      xb[ch] = load_op<PREC, NV>(xh, xl, (size_t)(16 * t + c) * DP + CK * ch + NV * g);
+  };
+  auto compute = [&](int t, const Op<PREC, NV>(&xb)[NCH]) {
+    float sq[NKQ];
+#pragma unroll
+    for (int j = 0; j < NKQ; ++j) {
+      f32x4 acc[NRB];
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb) acc[rb] = nc[j][rb];
+      int n = 0;
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+          if (CK * ch <= 16 * rb + 15) acc[rb] = mma<PREC, NV>(q[j][n++], xb[ch], acc[rb]);
+      float t2 = 0.f;
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t2 = fmaf(acc[rb][i], acc[rb][i], t2);
+      sq[j] = t2;
+    }
+    treduce_groups<NKQ>(sq);
+    const float b = kap - 0.5f * sq[0];
+    const int p = 16 * t + c;
+    // lanes that own the same (component, point) hold bit-identical values
+    __builtin_nontemporal_store(b, &brow[p]);
+    // log-sum-exp over the group's valid components of point p
+    float m = vown ? b : -INFINITY;
+    if constexpr (NKQ == 4) m = fmaxf(m, xor_lane(m, 16));
+    m = fmaxf(m, xor_lane(m, 32));
+    float e = vown ? __expf(b - m) : 0.f;
+    if constexpr (NKQ == 4) e = e + xor_lane(e, 16);
+    e = e + xor_lane(e, 32);
+    mlg[p] = make_float2(m, e);
+  };
+
+  Op<PREC, NV> xa[NCH], xb[NCH];
+  if (t0 < t1) load_x(t0, xa);
+  int t = t0;
+  for (; t + 1 < t1; t += 2) {
+    load_x(t + 1, xb);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(t, xa);
+    __builtin_amdgcn_sched_barrier(0);
+    load_x(min(t + 2, t1 - 1), xa);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(t + 1, xb);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (t < t1) compute(t, xa);
 }
 
 // ---------------------------------------------------------------------------
@@ -512,13 +639,13 @@ __host__ __device__ inline size_t mom_slot(int DP) {
   return (size_t)(nb * (nb + 1) / 2) * 256 + DP + 4;
 }
 
-// Wave wv accumulates S, u, A for components kbase+wv*GW .. +GW-1 over the
-// points [pbeg, pend), 32 per step. Both operands come from x~^T: lane 16 g + c
+// One wave accumulates S, u, A for components kw .. kw+GW-1 over the points
+// [pbeg, pend), 32 per step. Both operands come from x~^T: lane 16 g + c
 // holds feature row 16 bb + c and the points {4g..4g+3, 16+4g..16+4g+3} of the
 // step, in the order the matrix-core contraction pairs them; the A operand is
 // that row scaled by the point weights, the B operand the unscaled row.
 template <int DP, int MP, int GW>
-DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad, int K, int kbase,
+DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad, int K, int kw,
                           int pbeg, int pend, const float* __restrict__ beta,
                           const float* __restrict__ f, float ctv, float* __restrict__ part,
                           size_t pstride) {
@@ -528,11 +655,10 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
   using V4 = typename MT::V4;
   constexpr int NB = DP / 16, NBLK = NB * (NB + 1) / 2, NS = MT::NS;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
-  const int kw = kbase + wv * GW;
   if (kw >= K) return;
   const S* xh = (const S*)xT_hi;
   const S* xl = (const S*)xT_lo;
-  __shared__ float wsh[4][32];
+  __shared__ float wsh[4][GW][32];
 
   f32x4 sacc[GW][NBLK];
   float uacc[GW][NB];
@@ -546,13 +672,15 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
     aacc[gk] = 0.f;
   }
 
-  for (int t0 = pbeg; t0 < pend; t0 += 32) {
-    V8 xt[NB][NS];
+  // Steps of 32 points; [pbeg, pend) is a multiple of 32 long. The x~^T rows,
+  // beta and f of the next step are loaded while the current one is computed
+  // (every load in bounds: the last step reloads itself, f is clamped to N-1).
+  auto load_x = [&](int t, V8(&xt)[NB][NS]) {
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb) {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const S* base = (s == 0 ? xh : xl) + (size_t)(16 * bb + c) * Npad + t0 + 4 * g;
+        const S* base = (s == 0 ? xh : xl) + (size_t)(16 * bb + c) * Npad + t + 4 * g;
         const V4 a = *reinterpret_cast<const V4*>(base);
         const V4 b = *reinterpret_cast<const V4*>(base + 16);
 #pragma unroll
@@ -562,30 +690,57 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
         }
       }
     }
+  };
+  auto load_w = [&](int t, float(&bt)[GW], float& ft) {
+    const int p = t + (lane & 31);
+    ft = f[min(p, N - 1)];
+#pragma unroll
+    for (int gk = 0; gk < GW; ++gk)
+      bt[gk] = __builtin_nontemporal_load(&beta[(size_t)min(kw + gk, K - 1) * Npad + p]);
+  };
+  V8 xt[NB][NS];
+  float bt[GW], ft;
+  if (pbeg < pend) {
+    load_x(pbeg, xt);
+    load_w(pbeg, bt, ft);
+  }
+  for (int t0 = pbeg; t0 < pend; t0 += 32) {
+    const int tn = t0 + 32 < pend ? t0 + 32 : t0;
+    V8 xn[NB][NS];
+    float bn[GW], fn;
+    load_x(tn, xn);
+    load_w(tn, bn, fn);
+    __builtin_amdgcn_sched_barrier(0);
+    // point weights of this step for all GW components, one LDS round trip:
+    // lanes l and l + 32 hold the same point and write the same value
     const int pown = t0 + (lane & 31);
     const bool vown = pown < N;
-    const float fown = vown ? f[pown] : 0.f;
+#pragma unroll
+    for (int gk = 0; gk < GW; ++gk) {
+      const float w = vown ? __expf(bt[gk] - ft) * ctv : 0.f;
+      aacc[gk] += lane < 32 ? w : 0.f;
+      wsh[wv][gk][lane & 31] = w;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    f32x4 wq0[GW], wq1[GW];
+#pragma unroll
+    for (int gk = 0; gk < GW; ++gk) {
+      wq0[gk] = *reinterpret_cast<const f32x4*>(&wsh[wv][gk][4 * g]);
+      wq1[gk] = *reinterpret_cast<const f32x4*>(&wsh[wv][gk][16 + 4 * g]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int gk = 0; gk < GW; ++gk) {
       const int k = kw + gk;
       if (k >= K) break;
-      const float w = vown ? __expf(beta[(size_t)k * Npad + pown] - fown) * ctv : 0.f;
-      if (lane < 32) {
-        aacc[gk] += w;
-        wsh[wv][lane] = w;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const f32x4 w0 = *reinterpret_cast<const f32x4*>(&wsh[wv][4 * g]);
-      const f32x4 w1 = *reinterpret_cast<const f32x4*>(&wsh[wv][16 + 4 * g]);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
       float w8[8];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        w8[e] = w0[e];
-        w8[e + 4] = w1[e];
+        w8[e] = wq0[gk][e];
+        w8[e + 4] = wq1[gk][e];
       }
 #pragma unroll
       for (int ab = 0; ab < NB; ++ab) {
@@ -637,6 +792,14 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
         }
       }
     }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) xt[bb][s] = xn[bb][s];
+#pragma unroll
+    for (int gk = 0; gk < GW; ++gk) bt[gk] = bn[gk];
+    ft = fn;
   }
 
 #pragma unroll
@@ -671,9 +834,23 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
   __shared__ float us[64], mus[64], bq[64], Ash;
   const int NB = DP / 16, NBLK = NB * (NB + 1) / 2;
   const int L = D * (D - 1) / 2;
+  // slots in a fixed order; the loads of 8 slots are issued together
   auto comp_sum = [&](size_t off) {
     float s = 0.f, err = 0.f;
-    for (int sp = 0; sp < S; ++sp) {
+    int sp = 0;
+    for (; sp + 8 <= S; sp += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(sp + u) * sstride + off];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        float ns, ne;
+        two_sum<float>(s, v[u], ns, ne);
+        s = ns;
+        err += ne;
+      }
+    }
+    for (; sp < S; ++sp) {
       float ns, ne;
       two_sum<float>(s, part[(size_t)sp * sstride + off], ns, ne);
       s = ns;
@@ -681,6 +858,24 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
     }
     return s + err;
   };
+  __shared__ float red[8];
+  // softmax weight of alpha_k, by the whole block
+  float am = -INFINITY;
+  for (int j = threadIdx.x; j < K; j += blockDim.x) am = fmaxf(am, alphas[j]);
+  am = wave_max(am);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = am;
+  __syncthreads();
+  am = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) am = fmaxf(am, red[w]);
+  float az = 0.f;
+  for (int j = threadIdx.x; j < K; j += blockDim.x) az += expf(alphas[j] - am);
+  az = wave_sum(az);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[4 + (threadIdx.x >> 6)] = az;
+  __syncthreads();
+  az = 0.f;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) az += red[4 + w];
   __syncthreads();
   for (int e = threadIdx.x; e <= D; e += blockDim.x) {
     if (e < D) {
@@ -743,11 +938,7 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
     *om = accumulate ? *om + gm : gm;
   }
   if (threadIdx.x == 0) {
-    float m = -INFINITY;
-    for (int j = 0; j < K; ++j) m = fmaxf(m, alphas[j]);
-    float z = 0.f;
-    for (int j = 0; j < K; ++j) z += expf(alphas[j] - m);
-    const float ga = A - ctv * (float)N * (expf(alphas[k] - m) / z);
+    const float ga = A - ctv * (float)N * (expf(alphas[k] - am) / az);
     d_alphas[k] = accumulate ? d_alphas[k] + ga : ga;
   }
   __syncthreads();

@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "gmm_dev.h"
 
 namespace dexi {
@@ -14,19 +16,38 @@ struct GmmGeom {
   int DP;
 };
 
+// wps: waves per SIMD to launch (0: as many as can be resident).
 struct FwdCfg {
-  int cb, sk, ck;  // points per wave / 16, k-splits, contraction chunk depth
+  int nkq, wps;  // components resident per wave (2 or 4; 4 for BF16 only), waves per SIMD
 };
 struct BwdCfg {
-  int gw, s;  // components per wave, point chunks
+  int gw, wps;  // components per wave, waves per SIMD
 };
 
-// Point-chunk length (a multiple of 64) and count for `s` requested chunks.
-inline void bwd_chunks(int64_t Npad, int s, int64_t* chunk, int* n) {
-  int64_t c = (Npad + s - 1) / s;
-  c = (c + 63) / 64 * 64;
-  *chunk = c;
-  *n = (int)((Npad + c - 1) / c);
+// The single-instance forward and reverse kernels split their work evenly
+// over W waves (split_lo). Forward units are (group of nkq components,
+// 16-point tile), group-major; each group leaves one log-sum-exp partial per
+// point (sk = number of groups). Reverse units are (group of gw components,
+// 32-point step), group-major, nsteps per group; each wave writes one moment
+// partial per group it touches.
+struct FlatSplit {
+  int64_t T;
+  int W;
+  int sk;  // forward
+  int gw;  // reverse
+  int64_t nsteps;
+};
+
+// Waves a launch may use at most (256 CUs x 4 SIMDs x 8 waves).
+constexpr int kMaxWaves = 8192;
+
+// Forward log-sum-exp partials per point: one per group of >= 2 components.
+inline int64_t fwd_max_slots(int64_t K) { return (K + 1) / 2; }
+// beta rows: K rounded up to whole groups of 4 components
+inline int64_t beta_rows(int64_t K) { return (K + 3) / 4 * 4; }
+// Reverse partials per component: the launch keeps W <= (slots - 1) * groups.
+inline int64_t bwd_max_slots(int64_t Npad, int64_t K) {
+  return std::max<int64_t>(2, std::min<int64_t>(Npad / 32, 9600 / K));
 }
 
 template <int PREC>
@@ -34,11 +55,11 @@ void mfma_prep(const GmmGeom& g, const float* x, const float* alphas, const floa
                const float* qd, const float* l, void* xh, void* xl, void* xhT, void* xlT, void* Qh,
                void* Ql, float* negc, float* kappa, hipStream_t st);
 template <int PREC>
-void mfma_fwd(const GmmGeom& g, const FwdCfg& c, const dexk::MfmaOps& o, float* beta, float2* ml,
-              hipStream_t st);
+FlatSplit mfma_fwd(const GmmGeom& g, const FwdCfg& c, const dexk::MfmaOps& o, float* beta,
+                   float2* ml, hipStream_t st);
 template <int PREC>
-void mfma_bwd(const GmmGeom& g, const BwdCfg& c, const dexk::MfmaOps& o, const float* beta,
-              const float* f, const float* ct, float* part, hipStream_t st);
+FlatSplit mfma_bwd(const GmmGeom& g, const BwdCfg& c, const dexk::MfmaOps& o, const float* beta,
+                   const float* f, const float* ct, float* part, hipStream_t st);
 
 template <>
 void mfma_prep<dexk::PREC_F32>(const GmmGeom&, const float*, const float*, const float*,
@@ -53,22 +74,22 @@ void mfma_prep<dexk::PREC_BF16X3>(const GmmGeom&, const float*, const float*, co
                                   const float*, const float*, void*, void*, void*, void*, void*,
                                   void*, float*, float*, hipStream_t);
 template <>
-void mfma_fwd<dexk::PREC_F32>(const GmmGeom&, const FwdCfg&, const dexk::MfmaOps&, float*,
+FlatSplit mfma_fwd<dexk::PREC_F32>(const GmmGeom&, const FwdCfg&, const dexk::MfmaOps&, float*,
                               float2*, hipStream_t);
 template <>
-void mfma_fwd<dexk::PREC_BF16>(const GmmGeom&, const FwdCfg&, const dexk::MfmaOps&, float*,
+FlatSplit mfma_fwd<dexk::PREC_BF16>(const GmmGeom&, const FwdCfg&, const dexk::MfmaOps&, float*,
                                float2*, hipStream_t);
 template <>
-void mfma_fwd<dexk::PREC_BF16X3>(const GmmGeom&, const FwdCfg&, const dexk::MfmaOps&, float*,
+FlatSplit mfma_fwd<dexk::PREC_BF16X3>(const GmmGeom&, const FwdCfg&, const dexk::MfmaOps&, float*,
                                  float2*, hipStream_t);
 template <>
-void mfma_bwd<dexk::PREC_F32>(const GmmGeom&, const BwdCfg&, const dexk::MfmaOps&, const float*,
+FlatSplit mfma_bwd<dexk::PREC_F32>(const GmmGeom&, const BwdCfg&, const dexk::MfmaOps&, const float*,
                               const float*, const float*, float*, hipStream_t);
 template <>
-void mfma_bwd<dexk::PREC_BF16>(const GmmGeom&, const BwdCfg&, const dexk::MfmaOps&, const float*,
+FlatSplit mfma_bwd<dexk::PREC_BF16>(const GmmGeom&, const BwdCfg&, const dexk::MfmaOps&, const float*,
                                const float*, const float*, float*, hipStream_t);
 template <>
-void mfma_bwd<dexk::PREC_BF16X3>(const GmmGeom&, const BwdCfg&, const dexk::MfmaOps&,
+FlatSplit mfma_bwd<dexk::PREC_BF16X3>(const GmmGeom&, const BwdCfg&, const dexk::MfmaOps&,
                                  const float*, const float*, const float*, float*, hipStream_t);
 
 }  // namespace dexi

@@ -1,5 +1,7 @@
 // Grid kernels of the single-instance GMM matrix-core path for one operand
 // precision, selected at compile time by DEX_PREC (0 FP32, 1 BF16, 2 split-BF16).
+#include <algorithm>
+
 #include "gmm_host.h"
 #include "internal.h"
 
@@ -29,24 +31,59 @@ __global__ void __launch_bounds__(256) k_prep_q(const float* __restrict__ alphas
   prep_q_comp<PREC, DP>(alphas, means, qd, l, D, blockIdx.x, Qh, Ql, negc, kappa);
 }
 
-template <int DP, int PREC, int CB, int CK>
-__global__ void __launch_bounds__(256) k_gmm_fwd(MfmaOps ops, int N, int Npad, int K, int kchunk,
-                                                 float* __restrict__ beta, float2* __restrict__ ml) {
-  const int k0 = blockIdx.y * kchunk, k1 = min(K, k0 + kchunk);
-  fwd_unit<DP, PREC, CB, CK>(ops, N, Npad, blockIdx.x * 64 * CB, k0, k1, beta,
-                             ml + (size_t)blockIdx.y * Npad);
+// Both grid kernels split their work evenly over W waves (split_lo), so every
+// wave does the same amount of work whatever N, K and the CU count are, and no
+// partly filled second wave of blocks trails the launch. Forward units are
+// (group of NKQ components, 16-point tile), group-major: a wave loads a
+// group's operands once and streams its tiles; its range covers at most a few
+// groups.
+template <int DP, int PREC, int NKQ, int CK>
+__global__ void __launch_bounds__(256) k_gmm_fwd(MfmaOps ops, int Npad, int K, int64_t T, int W,
+                                                 float* __restrict__ beta,
+                                                 float2* __restrict__ ml) {
+  // wave index, made explicitly uniform so the split arithmetic and the loop
+  // control stay in scalar registers
+  const int w = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (w >= W) return;
+  const int64_t ntiles = Npad / 16;
+  int64_t pos = split_lo(w, T, W);
+  const int64_t hi = split_lo(w + 1, T, W);
+  while (pos < hi) {
+    const int64_t grp = pos / ntiles;
+    const int64_t ta = pos - grp * ntiles;
+    const int64_t tb = min<int64_t>(ntiles, ta + (hi - pos));
+    fwd_unit_kq<DP, PREC, NKQ, CK>(ops, Npad, K, (int)grp * NKQ, (int)ta, (int)tb, beta,
+                                   ml + (size_t)grp * Npad);
+    pos += tb - ta;
+  }
 }
 
+// Reverse units are (group of GW components, 32-point step), group-major; for
+// each group it touches a wave writes one partial moment slot.
 template <int DP, int PREC, int GW>
-__global__ void __launch_bounds__(256) k_gmm_bwd(MfmaOps ops, int N, int Npad, int K, int chunk,
-                                                 const float* __restrict__ beta,
+__global__ void __launch_bounds__(256) k_gmm_bwd(MfmaOps ops, int N, int Npad, int K, int64_t T,
+                                                 int W, const float* __restrict__ beta,
                                                  const float* __restrict__ f,
                                                  const float* __restrict__ ct,
                                                  float* __restrict__ part) {
-  const int pbeg = blockIdx.y * chunk, pend = min(Npad, pbeg + chunk);
+  // wave index, made explicitly uniform so the split arithmetic and the loop
+  // control stay in scalar registers
+  const int w = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (w >= W) return;
   const size_t E = mom_slot(DP);
-  bwd_mom_unit<DP, MomOf<PREC>::MP, GW>(ops.xhT, ops.xlT, N, Npad, K, blockIdx.x * 4 * GW, pbeg,
-                                        pend, beta, f, ct[0], part + (size_t)blockIdx.y * K * E, E);
+  const int64_t nsteps = Npad / 32;
+  int64_t pos = split_lo(w, T, W);
+  const int64_t hi = split_lo(w + 1, T, W);
+  while (pos < hi) {
+    const int64_t kg = pos / nsteps;
+    const int64_t s0 = pos - kg * nsteps;
+    const int64_t s1 = min<int64_t>(nsteps, s0 + (hi - pos));
+    const int slot = (int)(w - split_owner(kg * nsteps, T, W));
+    bwd_mom_unit<DP, MomOf<PREC>::MP, GW>(ops.xhT, ops.xlT, N, Npad, K, (int)kg * GW,
+                                          (int)(s0 * 32), (int)(s1 * 32), beta, f, ct[0],
+                                          part + (size_t)slot * K * E, E);
+    pos += s1 - s0;
+  }
 }
 
 }  // namespace dexk
@@ -80,70 +117,87 @@ void mfma_prep<P>(const GmmGeom& g, const float* x, const float* alphas, const f
     prep_dp<64>(g, x, alphas, means, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
 }
 
-template <int DP, int CB, int CK>
-static void fwd_launch(const GmmGeom& g, const FwdCfg& c, const MfmaOps& o, float* beta, float2* ml,
-                       hipStream_t st) {
-  const int kchunk = (int)((g.K + c.sk - 1) / c.sk);
-  dim3 grid((unsigned)(g.Npad / (64 * CB)), (unsigned)c.sk);
-  hipLaunchKernelGGL((k_gmm_fwd<DP, P, CB, CK>), grid, dim3(256), 0, st, o, (int)g.N, (int)g.Npad,
-                     (int)g.K, kchunk, beta, ml);
+// Resident 256-thread blocks of `kernel` per CU.
+template <typename Kern>
+static int blocks_per_cu(Kern kernel) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, 256, 0) != hipSuccess ||
+      blocks < 1)
+    blocks = 1;
+  return blocks;
 }
 
+// Waves to launch: all that can be resident (one block puts one wave on each
+// SIMD of a CU), capped by wps waves per SIMD when wps > 0.
+static int launch_waves(int bpc, int wps) {
+  int w = bpc * 4;
+  if (wps > 0) w = std::min(w, 4 * wps);
+  return std::min(kMaxWaves, w * num_cus());
+}
+
+template <int DP, int NKQ, int CK>
+static FlatSplit fwd_launch(const GmmGeom& g, const FwdCfg& c, const MfmaOps& o, float* beta,
+                            float2* ml, hipStream_t st) {
+  static const int bpc = blocks_per_cu(k_gmm_fwd<DP, P, NKQ, CK>);
+  FlatSplit sp{};
+  sp.sk = (int)((g.K + NKQ - 1) / NKQ);
+  sp.T = (int64_t)sp.sk * (g.Npad / 16);
+  sp.W = (int)std::min<int64_t>(sp.T, launch_waves(bpc, c.wps));
+  hipLaunchKernelGGL((k_gmm_fwd<DP, P, NKQ, CK>), dim3((unsigned)((sp.W + 3) / 4)), dim3(256), 0, st,
+                     o, (int)g.Npad, (int)g.K, sp.T, sp.W, beta, ml);
+  return sp;
+}
+
+// operand chunk depth: 32 for the 16-bit products when DP >= 32, else 16
 template <int DP>
-static void fwd_dp(const GmmGeom& g, const FwdCfg& c, const MfmaOps& o, float* beta, float2* ml,
-                   hipStream_t st) {
-  const int ck = DP == 16 ? 16 : c.ck;
-  if (c.cb == 4) {
-    if (ck == 32) fwd_launch<DP, 4, (DP >= 32 ? 32 : 16)>(g, c, o, beta, ml, st);
-    else fwd_launch<DP, 4, 16>(g, c, o, beta, ml, st);
-  } else {
-    if (ck == 32) fwd_launch<DP, 2, (DP >= 32 ? 32 : 16)>(g, c, o, beta, ml, st);
-    else fwd_launch<DP, 2, 16>(g, c, o, beta, ml, st);
+static FlatSplit fwd_dp(const GmmGeom& g, const FwdCfg& c, const MfmaOps& o, float* beta,
+                        float2* ml, hipStream_t st) {
+  constexpr int CK = (P != PREC_F32 && DP >= 32) ? 32 : 16;
+  if constexpr (P == PREC_BF16) {
+    if (c.nkq == 4) return fwd_launch<DP, 4, CK>(g, c, o, beta, ml, st);
   }
+  return fwd_launch<DP, 2, CK>(g, c, o, beta, ml, st);
 }
 
 template <>
-void mfma_fwd<P>(const GmmGeom& g, const FwdCfg& c, const MfmaOps& o, float* beta, float2* ml,
-                 hipStream_t st) {
-  if (g.DP == 16)
-    fwd_dp<16>(g, c, o, beta, ml, st);
-  else if (g.DP == 32)
-    fwd_dp<32>(g, c, o, beta, ml, st);
-  else
-    fwd_dp<64>(g, c, o, beta, ml, st);
+FlatSplit mfma_fwd<P>(const GmmGeom& g, const FwdCfg& c, const MfmaOps& o, float* beta,
+                      float2* ml, hipStream_t st) {
+  if (g.DP == 16) return fwd_dp<16>(g, c, o, beta, ml, st);
+  if (g.DP == 32) return fwd_dp<32>(g, c, o, beta, ml, st);
+  return fwd_dp<64>(g, c, o, beta, ml, st);
 }
 
 template <int DP, int GW>
-static void bwd_launch(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const float* beta,
-                       const float* f, const float* ct, float* part, hipStream_t st) {
-  int64_t chunk;
-  int n;
-  bwd_chunks(g.Npad, c.s, &chunk, &n);
-  dim3 grid((unsigned)((g.K + 4 * GW - 1) / (4 * GW)), (unsigned)n);
-  hipLaunchKernelGGL((k_gmm_bwd<DP, P, GW>), grid, dim3(256), 0, st, o, (int)g.N, (int)g.Npad,
-                     (int)g.K, (int)chunk, beta, f, ct, part);
+static FlatSplit bwd_launch(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const float* beta,
+                            const float* f, const float* ct, float* part, hipStream_t st) {
+  FlatSplit sp{};
+  sp.gw = GW;
+  sp.nsteps = g.Npad / 32;
+  const int64_t groups = (g.K + GW - 1) / GW;
+  sp.T = groups * sp.nsteps;
+  // at most bwd_max_slots partial slots per group: W <= (slots - 1) * groups
+  const int64_t wcap = (bwd_max_slots(g.Npad, g.K) - 1) * groups;
+  static const int bpc = blocks_per_cu(k_gmm_bwd<DP, P, GW>);
+  sp.W = (int)std::min<int64_t>(std::min<int64_t>(sp.T, wcap), launch_waves(bpc, c.wps));
+  hipLaunchKernelGGL((k_gmm_bwd<DP, P, GW>), dim3((unsigned)((sp.W + 3) / 4)), dim3(256), 0, st, o,
+                     (int)g.N, (int)g.Npad, (int)g.K, sp.T, sp.W, beta, f, ct, part);
+  return sp;
 }
 
 template <int DP>
-static void bwd_dp(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const float* beta,
-                   const float* f, const float* ct, float* part, hipStream_t st) {
-  if (c.gw == 4)
-    bwd_launch<DP, 4>(g, c, o, beta, f, ct, part, st);
-  else if (c.gw == 2)
-    bwd_launch<DP, 2>(g, c, o, beta, f, ct, part, st);
-  else
-    bwd_launch<DP, 1>(g, c, o, beta, f, ct, part, st);
+static FlatSplit bwd_dp(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const float* beta,
+                        const float* f, const float* ct, float* part, hipStream_t st) {
+  if (c.gw == 4) return bwd_launch<DP, 4>(g, c, o, beta, f, ct, part, st);
+  if (c.gw == 2) return bwd_launch<DP, 2>(g, c, o, beta, f, ct, part, st);
+  return bwd_launch<DP, 1>(g, c, o, beta, f, ct, part, st);
 }
 
 template <>
-void mfma_bwd<P>(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const float* beta,
-                 const float* f, const float* ct, float* part, hipStream_t st) {
-  if (g.DP == 16)
-    bwd_dp<16>(g, c, o, beta, f, ct, part, st);
-  else if (g.DP == 32)
-    bwd_dp<32>(g, c, o, beta, f, ct, part, st);
-  else
-    bwd_dp<64>(g, c, o, beta, f, ct, part, st);
+FlatSplit mfma_bwd<P>(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const float* beta,
+                      const float* f, const float* ct, float* part, hipStream_t st) {
+  if (g.DP == 16) return bwd_dp<16>(g, c, o, beta, f, ct, part, st);
+  if (g.DP == 32) return bwd_dp<32>(g, c, o, beta, f, ct, part, st);
+  return bwd_dp<64>(g, c, o, beta, f, ct, part, st);
 }
 
 }  // namespace dexi

@@ -81,7 +81,9 @@ DEX_DEV void lds_bitonic_sort(uint64_t* key) {
 
 // acc[idx[j], :] += scale[j] * vals[j, :] for float or int rows.
 // Sorted keys hold (row << 12) | local position; invalid rows sort last.
-template <typename T, typename IdxT, int U>
+// HV: vals given (else ones); HS: scale given. Both are template parameters so
+// the hot loop has no branches between its loads and their use.
+template <typename T, typename IdxT, int U, bool HV, bool HS>
 __global__ void __launch_bounds__(256) scatter_rows_kernel(T* __restrict__ acc, int64_t n_rows,
                                                            int R, const IdxT* __restrict__ idx,
                                                            const T* __restrict__ vals,
@@ -105,44 +107,60 @@ __global__ void __launch_bounds__(256) scatter_rows_kernel(T* __restrict__ acc, 
   if (oob) count_oob(bad, oob);
   lds_bitonic_sort(key);
 
-  // each wave takes a contiguous slice of the sorted chunk
+  // each wave takes a contiguous slice of the sorted chunk. The values of the
+  // next U sorted entries are loaded before the run sums (and atomics) of the
+  // current U are issued: vector memory operations retire in issue order, so
+  // waiting for a batch of loads never waits for atomics issued after it.
+  // Loads are unconditional (clamped to a valid element, then masked), which
+  // keeps branches out from between loads and their use.
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int per = (kChunk + nw - 1) / nw;
   const int e0 = wv * per, e1 = min(kChunk, e0 + per);
+  constexpr uint64_t kNone = ~uint64_t(0);
   for (int c0 = 0; c0 < R; c0 += 64) {
     const int col = c0 + lane;
     const bool cv = col < R;
-    uint64_t cur = ~uint64_t(0);
-    T sum = 0;
-    for (int e = e0; e < e1; e += U) {
-      T r[U];
-      uint64_t kk[U];
+    const int colc = cv ? col : R - 1;
+    auto fetch = [&](int e, uint64_t(&kk)[U], T(&r)[U]) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        kk[u] = (e + u < e1) ? key[e + u] : ~uint64_t(0);
-        r[u] = 0;
-        if (kk[u] != ~uint64_t(0) && cv) {
-          const int64_t j = j0 + (int64_t)(kk[u] & 4095u);
-          T v = vals ? vals[j * R + col] : T(1);
-          if constexpr (std::is_floating_point<T>::value) {
-            if (scale) v = v * scale[j];
-          }
-          r[u] = v;
-        }
+        kk[u] = (e + u < e1) ? key[e + u] : kNone;
+        const bool ok = kk[u] != kNone;
+        const int64_t j = j0 + (ok ? (int64_t)(kk[u] & 4095u) : 0);
+        T v = T(1);
+        if constexpr (HV) v = vals[j * R + colc];
+        if constexpr (HS) v = v * scale[j];
+        r[u] = ok ? v : T(0);
       }
+    };
+    uint64_t cur = kNone;
+    T sum = 0;
+    auto consume = [&](const uint64_t(&kk)[U], const T(&r)[U]) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (kk[u] == ~uint64_t(0)) continue;
-        const uint64_t row = kk[u] >> 12;
-        if (row != (cur >> 12)) {
-          if (cur != ~uint64_t(0) && cv) atomicAdd(&acc[(int64_t)(cur >> 12) * R + col], sum);
+        if (kk[u] == kNone) continue;
+        if ((kk[u] >> 12) != (cur >> 12)) {
+          if (cur != kNone && cv) atomicAdd(&acc[(int64_t)(cur >> 12) * R + col], sum);
           cur = kk[u];
           sum = 0;
         }
         sum += r[u];
       }
+    };
+    uint64_t ka[U], kb[U];
+    T ra[U], rb[U];
+    fetch(e0, ka, ra);
+    for (int e = e0; e < e1; e += 2 * U) {
+      fetch(e + U, kb, rb);
+      __builtin_amdgcn_sched_barrier(0);
+      consume(ka, ra);
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(e + 2 * U, ka, ra);
+      __builtin_amdgcn_sched_barrier(0);
+      consume(kb, rb);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    if (cur != ~uint64_t(0) && cv) atomicAdd(&acc[(int64_t)(cur >> 12) * R + col], sum);
+    if (cur != kNone && cv) atomicAdd(&acc[(int64_t)(cur >> 12) * R + col], sum);
   }
 }
 
@@ -470,8 +488,12 @@ __global__ void __launch_bounds__(1024) rs_scatter(const uint32_t* __restrict__ 
 // registers (row_len columns over the lanes); a run wholly inside the segment
 // is added to acc by this wave alone; a run that starts earlier leaves its
 // partial in part_first[seg], one that continues past the segment in
-// part_last[seg], for seg_fix.
-template <int U>
+// part_last[seg], for seg_fix. Every row thus receives exactly one addition
+// (here or in seg_fix), so a non-returning atomic add gives a fixed result and
+// never stalls the loop; the segment's keys and positions are staged in LDS
+// and the values of the next U entries are loaded before the current U are
+// summed (loads retire in issue order, so they never wait for the adds).
+template <int U, bool HV, bool HS>
 __global__ void __launch_bounds__(256) seg_sum(const uint32_t* __restrict__ skey,
                                                const uint32_t* __restrict__ spos, int64_t n,
                                                uint32_t sentinel, const float* __restrict__ vals,
@@ -479,19 +501,30 @@ __global__ void __launch_bounds__(256) seg_sum(const uint32_t* __restrict__ skey
                                                float* __restrict__ acc,
                                                float* __restrict__ part_first,
                                                float* __restrict__ part_last) {
-  const int lane = threadIdx.x & 63;
-  const int64_t seg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  __shared__ uint32_t sk[4][kSeg], sp[4][kSeg];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t seg = (int64_t)blockIdx.x * 4 + wv;
   const int64_t e0 = seg * kSeg;
   if (e0 >= n) return;
-  const int64_t e1 = min<int64_t>(n, e0 + kSeg);
-  const uint32_t first = skey[e0];
+  const int len = (int)min<int64_t>(kSeg, n - e0);
+#pragma unroll
+  for (int q = 0; q < kSeg / 64; ++q) {
+    const int e = q * 64 + lane;
+    sk[wv][e] = e < len ? skey[e0 + e] : sentinel;
+    sp[wv][e] = e < len ? spos[e0 + e] : 0u;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint32_t first = sk[wv][0];
   if (first == sentinel) return;
   const bool cont_in = e0 > 0 && skey[e0 - 1] == first;
-  const uint32_t lastk = skey[e1 - 1];
-  const bool cont_out = e1 < n && skey[e1] == lastk && lastk != sentinel;
+  const uint32_t lastk = sk[wv][len - 1];
+  const bool cont_out = e0 + len < n && skey[e0 + len] == lastk && lastk != sentinel;
   for (int c0 = 0; c0 < R; c0 += 64) {
     const int col = c0 + lane;
     const bool cv = col < R;
+    const int colc = cv ? col : R - 1;
     uint32_t cur = first;
     bool started_before = cont_in;
     float sum = 0.f;
@@ -502,23 +535,22 @@ __global__ void __launch_bounds__(256) seg_sum(const uint32_t* __restrict__ skey
       else if (continues)
         part_last[seg * R + col] = sum;
       else
-        acc[(int64_t)cur * R + col] += sum;
+        atomicAdd(&acc[(int64_t)cur * R + col], sum);
     };
-    for (int64_t e = e0; e < e1; e += U) {
-      uint32_t kk[U];
-      float rv[U];
+    auto fetch = [&](int e, uint32_t(&kk)[U], float(&rv)[U]) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const bool in = e + u < e1;
-        kk[u] = in ? skey[e + u] : sentinel;
-        rv[u] = 0.f;
-        if (in && kk[u] != sentinel && cv) {
-          const int64_t j = spos[e + u];
-          float v = vals ? vals[j * R + col] : 1.f;
-          if (scale) v *= scale[j];
-          rv[u] = v;
-        }
+        const int ec = min(e + u, kSeg - 1);
+        kk[u] = e + u < len ? sk[wv][ec] : sentinel;
+        const bool ok = kk[u] != sentinel;
+        const int64_t j = ok ? (int64_t)sp[wv][ec] : 0;
+        float v = 1.f;
+        if constexpr (HV) v = vals[j * R + colc];
+        if constexpr (HS) v *= scale[j];
+        rv[u] = ok ? v : 0.f;
       }
+    };
+    auto consume = [&](const uint32_t(&kk)[U], const float(&rv)[U]) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (kk[u] == sentinel) continue;
@@ -530,38 +562,69 @@ __global__ void __launch_bounds__(256) seg_sum(const uint32_t* __restrict__ skey
         }
         sum += rv[u];
       }
+    };
+    uint32_t ka[U], kb[U];
+    float ra[U], rb[U];
+    fetch(0, ka, ra);
+    for (int e = 0; e < len; e += 2 * U) {
+      fetch(e + U, kb, rb);
+      __builtin_amdgcn_sched_barrier(0);
+      consume(ka, ra);
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(e + 2 * U, ka, ra);
+      __builtin_amdgcn_sched_barrier(0);
+      consume(kb, rb);
+      __builtin_amdgcn_sched_barrier(0);
     }
     flush(cont_out);
   }
 }
 
 // For each segment whose last run starts in it and continues into the next
-// segments: add its partial and the following segments' first-run partials in
-// segment order, then add the total to acc.
+// segments: the run's end is found by binary search in the sorted keys; the
+// block then adds the segment's partial and the following segments' first-run
+// partials in a fixed order (wave w takes every fourth segment, the four wave
+// sums are combined in wave order) and adds the total to acc, the row's only
+// addition. One block per segment; most exit after two key reads.
 __global__ void __launch_bounds__(256) seg_fix(const uint32_t* __restrict__ skey, int64_t n,
                                                uint32_t sentinel, int R, float* __restrict__ acc,
                                                const float* __restrict__ part_first,
                                                const float* __restrict__ part_last) {
-  const int lane = threadIdx.x & 63;
-  const int64_t seg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t nseg = (n + kSeg - 1) / kSeg;
-  if (seg >= nseg) return;
+  __shared__ float wsum[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t seg = blockIdx.x;
   const int64_t e0 = seg * kSeg, e1 = min<int64_t>(n, e0 + kSeg);
+  if (e0 >= n) return;
   const uint32_t row = skey[e1 - 1];
   if (row == sentinel) return;
   const bool cont_out = e1 < n && skey[e1] == row;
   if (!cont_out) return;
   const bool whole_from_before = e0 > 0 && skey[e0 - 1] == row && skey[e0] == row;
   if (whole_from_before) return;  // the run started in an earlier segment
-  for (int col = lane; col < R; col += 64) {
-    float total = part_last[seg * R + col];
-    for (int64_t s2 = seg + 1; s2 < nseg; ++s2) {
-      total += part_first[s2 * R + col];
-      const int64_t f0 = s2 * kSeg, f1 = min<int64_t>(n, f0 + kSeg);
-      const bool through = skey[f1 - 1] == row && f1 < n && skey[f1] == row;
-      if (!through) break;
+  // last position of the run: largest q with skey[q] == row (keys ascending)
+  int64_t lo = e1, hi = n - 1;
+  while (lo < hi) {
+    const int64_t mid = hi - (hi - lo) / 2;
+    if (skey[mid] == row)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int64_t send = lo / kSeg;  // segments seg+1 .. send hold the rest of the run
+  for (int c0 = 0; c0 < R; c0 += 64) {
+    const int col = c0 + lane;
+    const bool cv = col < R;
+    float s = 0.f;
+    if (cv)
+      for (int64_t s2 = seg + 1 + wv; s2 <= send; s2 += 4) s += part_first[s2 * R + col];
+    __syncthreads();
+    wsum[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && cv) {
+      const float total =
+          part_last[seg * R + col] + (((wsum[0][lane] + wsum[1][lane]) + wsum[2][lane]) + wsum[3][lane]);
+      atomicAdd(&acc[(int64_t)row * R + col], total);  // the row's only addition
     }
-    acc[(int64_t)row * R + col] += total;
   }
 }
 
@@ -628,8 +691,20 @@ static dex_status scatter_typed(void* acc, int32_t acc_dtype, int64_t n_rows, in
   if (n_rows >= (int64_t(1) << 51)) return fail(DEX_ERR_UNSUPPORTED, "n_rows too large");
   if (acc_dtype == DEX_F32) {
     ProfRange pr(DEX_PROF_SCATTER, s);
-    hipLaunchKernelGGL((scatter_rows_kernel<float, IdxT, 8>), dim3(nchunks), dim3(256), 0, s,
-                       (float*)acc, n_rows, (int)R, idx, (const float*)vals, scale, n, oob);
+    float* a = (float*)acc;
+    const float* v = (const float*)vals;
+    if (vals && scale)
+      hipLaunchKernelGGL((scatter_rows_kernel<float, IdxT, 8, true, true>), dim3(nchunks),
+                         dim3(256), 0, s, a, n_rows, (int)R, idx, v, scale, n, oob);
+    else if (vals)
+      hipLaunchKernelGGL((scatter_rows_kernel<float, IdxT, 8, true, false>), dim3(nchunks),
+                         dim3(256), 0, s, a, n_rows, (int)R, idx, v, scale, n, oob);
+    else if (scale)
+      hipLaunchKernelGGL((scatter_rows_kernel<float, IdxT, 8, false, true>), dim3(nchunks),
+                         dim3(256), 0, s, a, n_rows, (int)R, idx, v, scale, n, oob);
+    else
+      hipLaunchKernelGGL((scatter_rows_kernel<float, IdxT, 8, false, false>), dim3(nchunks),
+                         dim3(256), 0, s, a, n_rows, (int)R, idx, v, scale, n, oob);
     pr.end(1);
   } else {
     if (R <= 4) {
@@ -637,8 +712,14 @@ static dex_status scatter_typed(void* acc, int32_t acc_dtype, int64_t n_rows, in
       hipLaunchKernelGGL((scatter_int_generic<IdxT>), dim3((unsigned)((tot + 255) / 256)), dim3(256),
                          0, s, (int32_t*)acc, n_rows, R, idx, (const int32_t*)vals, n, oob);
     } else {
-      hipLaunchKernelGGL((scatter_rows_kernel<int32_t, IdxT, 8>), dim3(nchunks), dim3(256), 0, s,
-                         (int32_t*)acc, n_rows, (int)R, idx, (const int32_t*)vals, nullptr, n, oob);
+      if (vals)
+        hipLaunchKernelGGL((scatter_rows_kernel<int32_t, IdxT, 8, true, false>), dim3(nchunks),
+                           dim3(256), 0, s, (int32_t*)acc, n_rows, (int)R, idx,
+                           (const int32_t*)vals, nullptr, n, oob);
+      else
+        hipLaunchKernelGGL((scatter_rows_kernel<int32_t, IdxT, 8, false, false>), dim3(nchunks),
+                           dim3(256), 0, s, (int32_t*)acc, n_rows, (int)R, idx,
+                           (const int32_t*)vals, nullptr, n, oob);
     }
   }
   return check_hip(hipGetLastError(), "accum_scatter");
@@ -702,10 +783,20 @@ static dex_status scatter_sorted(float* acc, int64_t n_rows, int64_t R, const Id
     std::swap(vin, vout);
   }
   const unsigned sb = (unsigned)((nseg + 3) / 4);
-  hipLaunchKernelGGL((seg_sum<8>), dim3(sb), dim3(256), 0, s, kin, vin, n, (uint32_t)n_rows, vals,
-                     scale, (int)R, acc, w.pf, w.pl);
-  hipLaunchKernelGGL(seg_fix, dim3(sb), dim3(256), 0, s, kin, n, (uint32_t)n_rows, (int)R, acc,
-                     w.pf, w.pl);
+  if (vals && scale)
+    hipLaunchKernelGGL((seg_sum<8, true, true>), dim3(sb), dim3(256), 0, s, kin, vin, n,
+                       (uint32_t)n_rows, vals, scale, (int)R, acc, w.pf, w.pl);
+  else if (vals)
+    hipLaunchKernelGGL((seg_sum<8, true, false>), dim3(sb), dim3(256), 0, s, kin, vin, n,
+                       (uint32_t)n_rows, vals, scale, (int)R, acc, w.pf, w.pl);
+  else if (scale)
+    hipLaunchKernelGGL((seg_sum<8, false, true>), dim3(sb), dim3(256), 0, s, kin, vin, n,
+                       (uint32_t)n_rows, vals, scale, (int)R, acc, w.pf, w.pl);
+  else
+    hipLaunchKernelGGL((seg_sum<8, false, false>), dim3(sb), dim3(256), 0, s, kin, vin, n,
+                       (uint32_t)n_rows, vals, scale, (int)R, acc, w.pf, w.pl);
+  hipLaunchKernelGGL(seg_fix, dim3((unsigned)nseg), dim3(256), 0, s, kin, n, (uint32_t)n_rows,
+                     (int)R, acc, w.pf, w.pl);
   pr.end(1);
   return check_hip(hipGetLastError(), "sorted scatter");
 }

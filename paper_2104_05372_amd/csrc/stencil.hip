@@ -285,11 +285,12 @@ St st_of(const dex_desc& d) {
   return s;
 }
 
-constexpr int kRB = 16;
+constexpr int kRB = 8;
 bool strip_ok(const St& s) { return s.W % 256 == 0 && s.H % (4 * kRB) == 0; }
 
-void step(const St& s, const float* u, float* un, float* snap, hipStream_t st) {
-  if (strip_ok(s)) {
+// strip: use the strip kernels where the grid allows them (a tuning config).
+void step(const St& s, const float* u, float* un, float* snap, bool strip, hipStream_t st) {
+  if (strip && strip_ok(s)) {
     hipLaunchKernelGGL((stencil_strip<kRB, false>), dim3(s.W / 256, s.H / (4 * kRB)), dim3(256), 0,
                        st, u, un, snap, nullptr, s.H, s.W, s.c, s.rho, 0);
   } else if (s.vec) {
@@ -302,6 +303,7 @@ void step(const St& s, const float* u, float* un, float* snap, hipStream_t st) {
   }
 }
 
+// form: 0 gather (strip kernel where the grid allows), 1 scatter, 2 gather (vector kernel).
 void adj(const St& s, int form, const float* g, const float* u, float* out, bool accumulate,
          hipStream_t st) {
   const unsigned nb = (unsigned)((s.n + 255) / 256);
@@ -309,7 +311,7 @@ void adj(const St& s, int form, const float* g, const float* u, float* out, bool
     if (!accumulate) fill_zero(out, (size_t)s.n * 4, st);
     hipLaunchKernelGGL(stencil_adj_scatter, dim3(nb), dim3(256), 0, st, g, u, out, s.H, s.W, s.c,
                        s.rho);
-  } else if (strip_ok(s)) {
+  } else if (form == 0 && strip_ok(s)) {
     hipLaunchKernelGGL((stencil_strip<kRB, true>), dim3(s.W / 256, s.H / (4 * kRB)), dim3(256), 0,
                        st, g, out, nullptr, u, s.H, s.W, s.c, s.rho, accumulate ? 1 : 0);
   } else if (s.vec) {
@@ -336,12 +338,14 @@ size_t stencil_ws_bytes(const dex_desc& d, int role) {
 
 int stencil_num_configs(const dex_desc& d, int role) {
   (void)d;
-  return role == DEX_WS_VJP ? 2 : 1;  // vjp: 0 gather form, 1 scatter form
+  // fwd: 0 strip kernel (where the grid allows), 1 vector kernel; vjp: 0 gather
+  // form (strip kernels where allowed), 1 scatter form, 2 gather form with
+  // vector kernels
+  return role == DEX_WS_VJP ? 3 : 2;
 }
 
 dex_status stencil_fwd(const dex_desc& d, int cfg, const float* u0, const float* target, float* L,
                        float* uT, float* ckpt, void* ws, hipStream_t st) {
-  (void)cfg;
   St s = st_of(d);
   float* other = (float*)ws;
   double* part = (double*)((char*)ws + align256((size_t)s.n * 4));
@@ -351,7 +355,7 @@ dex_status stencil_fwd(const dex_desc& d, int cfg, const float* u0, const float*
   for (int t = 0; t < s.T; ++t) {
     float* dst = ((s.T - 1 - t) % 2 == 0) ? uT : other;
     float* snap = (t % s.every == 0) ? ckpt + (int64_t)(t / s.every) * s.n : nullptr;
-    step(s, cur, dst, snap, st);
+    step(s, cur, dst, snap, cfg == 0, st);
     cur = dst;
   }
   pr.end(s.T);
@@ -369,7 +373,7 @@ dex_status stencil_vjp(const dex_desc& d, int cfg, const float* u0, const float*
                        bool accumulate, void* ws, hipStream_t st) {
   (void)u0;
   St s = st_of(d);
-  const int form = cfg == 1 ? 1 : 0;
+  const int form = cfg;
   const size_t fb = align256((size_t)s.n * 4);
   float* lamA = (float*)ws;
   float* lamB = (float*)((char*)ws + fb);
@@ -403,7 +407,7 @@ dex_status stencil_vjp(const dex_desc& d, int cfg, const float* u0, const float*
       const float* cur = ck;
       for (int q = 1; q < len; ++q) {
         float* dst = seg + (int64_t)(q - 1) * (fb / 4);
-        step(s, cur, dst, nullptr, st);
+        step(s, cur, dst, nullptr, form == 0, st);
         cur = dst;
         ++launches;
       }

@@ -16,17 +16,19 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def run(u0, target, steps, every, rho=0.0, variant=0, vcfg=0, dev="cuda", ct=1.0):
+def run(u0, target, steps, every, rho=0.0, variant=0, vcfg=0, dev="cuda", ct=1.0, fcfg=0):
     from paper_2104_05372_amd import dex
     H, W = u0.shape
     d = dex.stencil_desc(H, W, steps, every, 0.2, rho, variant)
+    d.config = fcfg
     tu = torch.tensor(u0, device=dev)
     tt = torch.tensor(target, device=dev)
     nck = (steps + every - 1) // every
     L = torch.empty(1, device=dev)
     uT = torch.empty_like(tu)
     ck = torch.empty(nck * H * W, device=dev)
-    print(f"  stencil {H}x{W} steps={steps} every={every} rho={rho} variant={variant} cfg={vcfg}",
+    print(f"  stencil {H}x{W} steps={steps} every={every} rho={rho} variant={variant} "
+          f"cfg={fcfg},{vcfg}",
           flush=True)
     dex.dex_fwd(d, [tu, tt], [L, uT], [ck, uT], dex.workspace(dex.dex_workspace_bytes(d, 0), dev))
     d.config = vcfg
@@ -77,6 +79,22 @@ def test_nonlinear_term_needs_recompute(dev, rho, H, W):
     assert rel(uT, uTo) <= 1e-5 and rel(du, duo) <= 1e-5
     du1 = run(u0, tg, 40, 1, rho=rho)[2]
     assert np.array_equal(du1, du)
+
+
+@pytest.mark.parametrize("H,W,steps,every,rho", [(64, 256, 20, 8, 0.0), (128, 512, 33, 32, 0.0),
+                                                 (64, 512, 17, 5, 0.05), (32, 256, 3, 1, 0.0),
+                                                 (40, 256, 9, 4, 0.0)])
+def test_vector_kernels(dev, H, W, steps, every, rho):
+    """Vector kernels (forward config 2, reverse config 3) against the oracle
+    and the default row-strip kernels; (40, 256) does not tile into strips, so
+    both use the vector kernels there."""
+    u0, tg = workloads.stencil_inputs(H, W, 11)
+    L, uT, du, ck = run(u0, tg, steps, every, rho=rho, fcfg=2, vcfg=3)
+    Lo, uTo, duo = ost.loss_and_grad(u0, tg, steps, rho=rho)
+    assert abs(L - Lo) <= 1e-5 * abs(Lo)
+    assert rel(uT, uTo) <= 1e-5 and rel(du, duo) <= 1e-5
+    L2, uT2, du2, ck2 = run(u0, tg, steps, every, rho=rho)
+    assert rel(uT, uT2) <= 1e-6 and rel(du, du2) <= 1e-6 and rel(ck, ck2) <= 1e-6
 
 
 def test_cotangent_scaling(dev):
