@@ -16,26 +16,58 @@ typedef __attribute__((__vector_size__(8 * sizeof(float)))) float f32x8;
 constexpr int kWave = 64;
 
 // ---- wave-level exchange -------------------------------------------------
-// Value of `v` held by lane (lane ^ 32) / (lane ^ 16), through the gfx950 lane
-// swaps (VALU, no LDS traffic, no lgkm wait). The swap leaves the lane's own
-// value in one of the two results and its partner's in the other; the own
-// value is recognised by its bits, so the choice does not depend on which
-// half the instruction moves.
-DEX_DEV uint32_t swap_partner32(uint32_t v) {
-  const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-  return r[0] == v ? r[1] : r[0];
+// gfx950 lane swaps (VALU, no LDS traffic, no lgkm wait). As measured on the
+// hardware, swap32(a, b) returns {[a_lo, b_lo], [a_hi, b_hi]} where lo / hi
+// are lanes 0-31 / 32-63, and swap16(a, b) returns
+// {[a_r0, b_r0, a_r2, b_r2], [a_r1, b_r1, a_r3, b_r3]} where r is a row of 16
+// lanes. So, per lane, the two results of swap32(a, b) are a's (or b's, in the
+// upper half) values at lanes l and l ^ 32 in lane order, and likewise for
+// swap16 with rows.
+struct LanePair {
+  float first, second;  // value at the lower / upper lane of the pair
+};
+DEX_DEV LanePair swap32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return {__uint_as_float(r[0]), __uint_as_float(r[1])};
 }
-DEX_DEV uint32_t swap_partner16(uint32_t v) {
-  const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-  return r[0] == v ? r[1] : r[0];
+DEX_DEV LanePair swap16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return {__uint_as_float(r[0]), __uint_as_float(r[1])};
+}
+// Sum / max over the lane pair (l, l ^ 32) or (l, l ^ 16); both lanes get the
+// same bits (the lower lane's value is always the first operand).
+DEX_DEV float pair_sum32(float v) {
+  const LanePair p = swap32(v, v);
+  return p.first + p.second;
+}
+DEX_DEV float pair_sum16(float v) {
+  const LanePair p = swap16(v, v);
+  return p.first + p.second;
+}
+DEX_DEV float pair_max32(float v) {
+  const LanePair p = swap32(v, v);
+  return fmaxf(p.first, p.second);
+}
+DEX_DEV float pair_max16(float v) {
+  const LanePair p = swap16(v, v);
+  return fmaxf(p.first, p.second);
 }
 
 // Value of `v` held by lane (lane ^ mask).
 template <typename T>
 DEX_DEV T xor_lane(T v, int mask) {
   if constexpr (sizeof(T) == 4) {
-    if (mask == 32) return __builtin_bit_cast(T, swap_partner32(__builtin_bit_cast(uint32_t, v)));
-    if (mask == 16) return __builtin_bit_cast(T, swap_partner16(__builtin_bit_cast(uint32_t, v)));
+    const bool upper = (threadIdx.x & mask) != 0;
+    if (mask == 32) {
+      const LanePair p = swap32(__builtin_bit_cast(float, v), __builtin_bit_cast(float, v));
+      return __builtin_bit_cast(T, upper ? p.first : p.second);
+    }
+    if (mask == 16) {
+      const LanePair p = swap16(__builtin_bit_cast(float, v), __builtin_bit_cast(float, v));
+      return __builtin_bit_cast(T, upper ? p.first : p.second);
+    }
   }
   return __shfl_xor(v, mask, kWave);
 }

@@ -31,6 +31,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace dexk {
@@ -230,24 +232,19 @@ DEX_DEV double dlog<double>(double v) { return log(v); }
 // entry 0 and {2,3} entry 1, for NV = 1 every group owns the total.
 template <int NV>
 DEX_DEV void treduce_groups(float (&v)[NV]) {
-  const int lane = threadIdx.x & 63;
   if constexpr (NV == 4) {
-    const bool h5 = lane & 32;
-    float s0 = h5 ? v[0] : v[2], s1 = h5 ? v[1] : v[3];
-    float k0 = h5 ? v[2] : v[0], k1 = h5 ? v[3] : v[1];
-    k0 += xor_lane(s0, 32);
-    k1 += xor_lane(s1, 32);
-    const bool h4 = lane & 16;
-    float s = h4 ? k0 : k1, kk = h4 ? k1 : k0;
-    v[0] = kk + xor_lane(s, 16);
+    // entries 0 / 2 summed over lane pairs 32 apart (lower half keeps entry 0,
+    // upper half entry 2), likewise 1 / 3; then over rows 16 apart, row g
+    // keeping entry g
+    const LanePair a = swap32(v[0], v[2]);
+    const LanePair b = swap32(v[1], v[3]);
+    const LanePair r = swap16(a.first + a.second, b.first + b.second);
+    v[0] = r.first + r.second;
   } else if constexpr (NV == 2) {
-    const bool h5 = lane & 32;
-    float s = h5 ? v[0] : v[1], kk = h5 ? v[1] : v[0];
-    v[0] = kk + xor_lane(s, 32);
-    v[0] += xor_lane(v[0], 16);
+    const LanePair a = swap32(v[0], v[1]);
+    v[0] = pair_sum16(a.first + a.second);
   } else {
-    v[0] += xor_lane(v[0], 32);
-    v[0] += xor_lane(v[0], 16);
+    v[0] = pair_sum16(pair_sum32(v[0]));
   }
 }
 
@@ -280,6 +277,11 @@ struct MomT<MP_F32> {
   typedef float V2 __attribute__((ext_vector_type(2)));
   static constexpr int NS = 1;
 };
+
+// Position of point j (0..31) of a 32-point step in the x~^T layout: the 8
+// points lane group g contracts over ({4g..4g+3} and {16+4g..16+4g+3}, in the
+// order the matrix cores pair them) are stored contiguously at 8g.
+__host__ __device__ inline int mom_pos(int j) { return 8 * ((j & 15) >> 2) + (j & 3) + 4 * (j >> 4); }
 
 template <int MP>
 DEX_DEV void mom_store(typename MomT<MP>::S* hi, typename MomT<MP>::S* lo, size_t off, float v) {
@@ -354,8 +356,9 @@ DEX_DEV void prep_x_tile(const float* __restrict__ x, int N, int D, int Npad, in
     store_split<PREC>(xh, xl, (size_t)(p0 + pp) * DP + b, tile[pp][b]);
   }
   for (int e = threadIdx.x; e < 64 * DP; e += blockDim.x) {
-    int b = e / 64, pp = e % 64;
-    mom_store<MomOf<PREC>::MP>(xhT, xlT, (size_t)b * Npad + p0 + pp, tile[pp][b]);
+    int b = e / 64, pp = e % 64;  // p0 is a multiple of 64: 32-point steps align
+    mom_store<MomOf<PREC>::MP>(xhT, xlT, (size_t)b * Npad + p0 + (pp & 32) + mom_pos(pp & 31),
+                               tile[pp][b]);
   }
 }
 
@@ -605,12 +608,10 @@ DEX_DEV void fwd_unit_kq(const MfmaOps& ops, int Npad, int K, int k0, int t0, in
     // lanes that own the same (component, point) hold bit-identical values
     __builtin_nontemporal_store(b, &brow[p]);
     // log-sum-exp over the group's valid components of point p
-    float m = vown ? b : -INFINITY;
-    if constexpr (NKQ == 4) m = fmaxf(m, xor_lane(m, 16));
-    m = fmaxf(m, xor_lane(m, 32));
-    float e = vown ? __expf(b - m) : 0.f;
-    if constexpr (NKQ == 4) e = e + xor_lane(e, 16);
-    e = e + xor_lane(e, 32);
+    float m = pair_max32(vown ? b : -INFINITY);
+    if constexpr (NKQ == 4) m = pair_max16(m);
+    float e = pair_sum32(vown ? __expf(b - m) : 0.f);
+    if constexpr (NKQ == 4) e = pair_sum16(e);
     mlg[p] = make_float2(m, e);
   };
 
@@ -641,9 +642,11 @@ __host__ __device__ inline size_t mom_slot(int DP) {
 
 // One wave accumulates S, u, A for components kw .. kw+GW-1 over the points
 // [pbeg, pend), 32 per step. Both operands come from x~^T: lane 16 g + c
-// holds feature row 16 bb + c and the points {4g..4g+3, 16+4g..16+4g+3} of the
-// step, in the order the matrix-core contraction pairs them; the A operand is
-// that row scaled by the point weights, the B operand the unscaled row.
+// holds feature row 16 bb + c and the 8 points of group g (one 16-byte load
+// per row block in FP16); the A operand is that row scaled by the point
+// weights, the B operand the unscaled row. The weights of a step are computed
+// two components at a time (lanes 0-31 one component, 32-63 the next) and
+// exchanged through LDS in the same point order (FP16 for the FP16 moments).
 template <int DP, int MP, int GW>
 DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad, int K, int kw,
                           int pbeg, int pend, const float* __restrict__ beta,
@@ -652,54 +655,51 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
   using MT = MomT<MP>;
   using S = typename MT::S;
   using V8 = typename MT::V8;
-  using V4 = typename MT::V4;
+  using WT = typename std::conditional<MP == MP_F16, _Float16, float>::type;
   constexpr int NB = DP / 16, NBLK = NB * (NB + 1) / 2, NS = MT::NS;
+  constexpr int NP = (GW + 1) / 2;  // component pairs
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+  const int half = lane >> 5, j = lane & 31;
   if (kw >= K) return;
   const S* xh = (const S*)xT_hi;
   const S* xl = (const S*)xT_lo;
-  __shared__ float wsh[4][GW][32];
+  __shared__ __attribute__((aligned(16))) WT wsh[4][2 * NP][32];
 
   f32x4 sacc[GW][NBLK];
   float uacc[GW][NB];
-  float aacc[GW];
+  float aacc[NP];
 #pragma unroll
   for (int gk = 0; gk < GW; ++gk) {
 #pragma unroll
     for (int q = 0; q < NBLK; ++q) sacc[gk][q] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ab = 0; ab < NB; ++ab) uacc[gk][ab] = 0.f;
-    aacc[gk] = 0.f;
   }
+#pragma unroll
+  for (int pp = 0; pp < NP; ++pp) aacc[pp] = 0.f;
 
   // Steps of 32 points; [pbeg, pend) is a multiple of 32 long. The x~^T rows,
   // beta and f of the next step are loaded while the current one is computed
-  // (every load in bounds: the last step reloads itself, f is clamped to N-1).
+  // (every load in bounds: the last step reloads itself, f is clamped to N-1,
+  // components past K to K-1).
   auto load_x = [&](int t, V8(&xt)[NB][NS]) {
 #pragma unroll
-    for (int bb = 0; bb < NB; ++bb) {
+    for (int bb = 0; bb < NB; ++bb)
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const S* base = (s == 0 ? xh : xl) + (size_t)(16 * bb + c) * Npad + t + 4 * g;
-        const V4 a = *reinterpret_cast<const V4*>(base);
-        const V4 b = *reinterpret_cast<const V4*>(base + 16);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          xt[bb][s][e] = a[e];
-          xt[bb][s][e + 4] = b[e];
-        }
-      }
-    }
+      for (int s = 0; s < NS; ++s)
+        xt[bb][s] = *reinterpret_cast<const V8*>((s == 0 ? xh : xl) +
+                                                 (size_t)(16 * bb + c) * Npad + t + 8 * g);
   };
-  auto load_w = [&](int t, float(&bt)[GW], float& ft) {
-    const int p = t + (lane & 31);
+  auto load_w = [&](int t, float(&bt)[NP], float& ft) {
+    const int p = t + j;
     ft = f[min(p, N - 1)];
 #pragma unroll
-    for (int gk = 0; gk < GW; ++gk)
-      bt[gk] = __builtin_nontemporal_load(&beta[(size_t)min(kw + gk, K - 1) * Npad + p]);
+    for (int pp = 0; pp < NP; ++pp)
+      bt[pp] = __builtin_nontemporal_load(
+          &beta[(size_t)min(kw + 2 * pp + half, K - 1) * Npad + p]);
   };
   V8 xt[NB][NS];
-  float bt[GW], ft;
+  float bt[NP], ft;
   if (pbeg < pend) {
     load_x(pbeg, xt);
     load_w(pbeg, bt, ft);
@@ -707,41 +707,31 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
   for (int t0 = pbeg; t0 < pend; t0 += 32) {
     const int tn = t0 + 32 < pend ? t0 + 32 : t0;
     V8 xn[NB][NS];
-    float bn[GW], fn;
+    float bn[NP], fn;
     load_x(tn, xn);
     load_w(tn, bn, fn);
     __builtin_amdgcn_sched_barrier(0);
-    // point weights of this step for all GW components, one LDS round trip:
-    // lanes l and l + 32 hold the same point and write the same value
-    const int pown = t0 + (lane & 31);
-    const bool vown = pown < N;
+    const bool vown = t0 + j < N;
 #pragma unroll
-    for (int gk = 0; gk < GW; ++gk) {
-      const float w = vown ? __expf(bt[gk] - ft) * ctv : 0.f;
-      aacc[gk] += lane < 32 ? w : 0.f;
-      wsh[wv][gk][lane & 31] = w;
+    for (int pp = 0; pp < NP; ++pp) {
+      const bool vk = kw + 2 * pp + half < K && (GW > 1 || half == 0);
+      const float w = vown && vk ? __expf(bt[pp] - ft) * ctv : 0.f;
+      aacc[pp] += w;
+      wsh[wv][2 * pp + half][mom_pos(j)] = (WT)w;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    f32x4 wq0[GW], wq1[GW];
+    typedef WT W8 __attribute__((ext_vector_type(8)));
+    W8 wq[GW];
 #pragma unroll
-    for (int gk = 0; gk < GW; ++gk) {
-      wq0[gk] = *reinterpret_cast<const f32x4*>(&wsh[wv][gk][4 * g]);
-      wq1[gk] = *reinterpret_cast<const f32x4*>(&wsh[wv][gk][16 + 4 * g]);
-    }
+    for (int gk = 0; gk < GW; ++gk) wq[gk] = *reinterpret_cast<const W8*>(&wsh[wv][gk][8 * g]);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int gk = 0; gk < GW; ++gk) {
       const int k = kw + gk;
       if (k >= K) break;
-      float w8[8];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        w8[e] = wq0[gk][e];
-        w8[e + 4] = wq1[gk][e];
-      }
 #pragma unroll
       for (int ab = 0; ab < NB; ++ab) {
         V8 sa[NS];
@@ -749,21 +739,18 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
           float ut = 0.f;
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
-            sa[0][e] = xt[ab][0][e] * w8[e];
-            ut = fmaf(xt[ab][0][e], w8[e], ut);
+            sa[0][e] = xt[ab][0][e] * wq[gk][e];
+            ut = fmaf(xt[ab][0][e], wq[gk][e], ut);
           }
           uacc[gk][ab] += ut;
         } else if constexpr (MP == MP_F16) {
-          V8 wh;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) wh[e] = (_Float16)w8[e];
-          sa[0] = xt[ab][0] * wh;
+          sa[0] = xt[ab][0] * wq[gk];
           float ut = uacc[gk][ab];
 #pragma unroll
           for (int e = 0; e < 8; e += 2) {
             typedef _Float16 h2 __attribute__((ext_vector_type(2)));
             const h2 xa{xt[ab][0][e], xt[ab][0][e + 1]};
-            const h2 wa{wh[e], wh[e + 1]};
+            const h2 wa{wq[gk][e], wq[gk][e + 1]};
             ut = __builtin_amdgcn_fdot2(xa, wa, ut, false);
           }
           uacc[gk][ab] = ut;
@@ -772,8 +759,8 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
             const float xv = (float)xt[ab][0][e] + (float)xt[ab][1][e];
-            const float v = xv * w8[e];
-            ut = fmaf(xv, w8[e], ut);
+            const float v = xv * wq[gk][e];
+            ut = fmaf(xv, wq[gk][e], ut);
             const _Float16 h = (_Float16)v;
             sa[0][e] = h;
             sa[1][e] = (_Float16)(v - (float)h);
@@ -798,10 +785,19 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
 #pragma unroll
       for (int s = 0; s < NS; ++s) xt[bb][s] = xn[bb][s];
 #pragma unroll
-    for (int gk = 0; gk < GW; ++gk) bt[gk] = bn[gk];
+    for (int pp = 0; pp < NP; ++pp) bt[pp] = bn[pp];
     ft = fn;
   }
 
+  // A: lanes 0-31 hold component kw + 2pp, lanes 32-63 component kw + 2pp + 1
+  float asum[NP];
+#pragma unroll
+  for (int pp = 0; pp < NP; ++pp) {
+    float v = aacc[pp];
+#pragma unroll
+    for (int m = 16; m >= 1; m >>= 1) v += xor_lane(v, m);
+    asum[pp] = v;
+  }
 #pragma unroll
   for (int gk = 0; gk < GW; ++gk) {
     const int k = kw + gk;
@@ -816,8 +812,7 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
       uv += xor_lane(uv, 32);
       if (g == 0) P[NBLK * 256 + 16 * ab + c] = uv;
     }
-    const float av = wave_sum(aacc[gk]);
-    if (lane == 0) P[NBLK * 256 + DP] = av;
+    if (lane == 32 * (gk & 1)) P[NBLK * 256 + DP] = asum[gk >> 1];
   }
 }
 
