@@ -168,6 +168,52 @@ __global__ void __launch_bounds__(256) k_merge_lse(const float2* __restrict__ ml
 }
 
 template <typename T>
+__global__ void __launch_bounds__(256) k_merge_lse_quad(const float2* __restrict__ ml, int Sk,
+                                                        int N, int Npad, T* __restrict__ f,
+                                                        T* __restrict__ fpart) {
+  T s = 0, e = 0;
+  merge_lse_quad<T>(ml, Sk, N, Npad, blockIdx.x * 64, f, s, e);
+  if (threadIdx.x == 0) {
+    fpart[2 * blockIdx.x] = s;
+    fpart[2 * blockIdx.x + 1] = e;
+  }
+}
+
+// Fixed-order compensated sum of each component's partial moment slots (the
+// waves that owned part of its group's points), written back into slot 0, so
+// the per-component finalize reads a single slot. One thread per element.
+__global__ void __launch_bounds__(256) k_mom_reduce(float* __restrict__ part, int64_t E, int K,
+                                                    int gw, int64_t nsteps, int64_t Tu,
+                                                    int64_t Wu) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)K * E) return;
+  const int k = (int)(i / E);
+  const int S = split_slots((int64_t)(k / gw) * nsteps, nsteps, Tu, Wu);
+  const size_t stride = (size_t)K * E;
+  float s = 0.f, err = 0.f;
+  int sp = 0;
+  for (; sp + 8 <= S; sp += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(sp + u) * stride + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      float ns, ne;
+      two_sum<float>(s, v[u], ns, ne);
+      s = ns;
+      err += ne;
+    }
+  }
+  for (; sp < S; ++sp) {
+    float ns, ne;
+    two_sum<float>(s, part[(size_t)sp * stride + i], ns, ne);
+    s = ns;
+    err += ne;
+  }
+  part[i] = s + err;
+}
+
+template <typename T>
 __global__ void __launch_bounds__(256) k_finalize_F(const T* __restrict__ fpart, int nparts,
                                                     const T* __restrict__ alphas, int K, int64_t N,
                                                     T* __restrict__ F) {
@@ -190,16 +236,13 @@ __global__ void __launch_bounds__(256) k_bwd_finalize(const TP* __restrict__ par
                            means, ct[0], d_alphas, d_means, d_qd, d_l, accumulate);
 }
 
-// Split reverse pass (see FlatSplit): component k's partials are those of
-// the waves that owned part of its group's point steps.
+// Component k's moment partials, already summed into slot 0 (S = 1).
 __global__ void __launch_bounds__(256) k_bwd_finalize_mom(
-    const float* __restrict__ part, size_t E, int gw, int64_t nsteps, int64_t Tu, int64_t Wu,
-    int K, int D, int DP, int64_t N, const float* __restrict__ alphas,
-    const float* __restrict__ means, const float* __restrict__ qd, const float* __restrict__ l,
-    const float* __restrict__ ct, float* __restrict__ d_alphas, float* __restrict__ d_means,
-    float* __restrict__ d_qd, float* __restrict__ d_l, int accumulate) {
+    const float* __restrict__ part, size_t E, int S, int K, int D, int DP, int64_t N,
+    const float* __restrict__ alphas, const float* __restrict__ means, const float* __restrict__ qd,
+    const float* __restrict__ l, const float* __restrict__ ct, float* __restrict__ d_alphas,
+    float* __restrict__ d_means, float* __restrict__ d_qd, float* __restrict__ d_l, int accumulate) {
   const int k = blockIdx.x;
-  const int S = split_slots((int64_t)(k / gw) * nsteps, nsteps, Tu, Wu);
   bwd_finalize_mom(part + (size_t)k * E, (size_t)K * E, S, k, K, D, DP, N, alphas, means, qd, l,
                    ct[0], d_alphas, d_means, d_qd, d_l, accumulate);
 }
@@ -234,9 +277,10 @@ Shape shape_of(const dex_desc& d) {
   return s;
 }
 
-// forward candidates: (components resident per wave, waves per SIMD (0: all resident))
-const FwdCfg kFwdBF[] = {{4, 0}, {4, 1}, {4, 2}, {2, 0}, {2, 2}, {2, 3}};
-const FwdCfg kFwdF32[] = {{2, 0}, {2, 1}, {2, 2}, {2, 3}};
+// forward candidates: (components resident per wave, waves per SIMD (0: all
+// resident), x~ tiles loaded ahead)
+const FwdCfg kFwdBF[] = {{4, 0, 1}, {4, 0, 2}, {2, 0, 1}, {2, 0, 2}, {4, 1, 2}, {2, 2, 2}};
+const FwdCfg kFwdF32[] = {{2, 0, 1}, {2, 0, 2}, {2, 2, 1}, {2, 1, 2}};
 // reverse candidates: (components per wave, waves per SIMD (0: all resident))
 const BwdCfg kBwdBF[] = {{2, 0}, {1, 0}, {4, 0}, {2, 2}, {1, 2}, {1, 3}, {2, 1}, {4, 1}};
 const BwdCfg kBwdF32[] = {{2, 0}, {1, 0}, {4, 0}, {2, 2}, {1, 2}};
@@ -355,9 +399,9 @@ size_t gmm_ws_bytes(const dex_desc& d, int role) {
   Shape s = shape_of(d);
   if (!valid_shape(s)) return 0;
   if (role == DEX_WS_RESID) return cache_layout(s).total;
-  const size_t nblk = (size_t)(s.g.Npad / 256);
+  const size_t nparts = (size_t)(s.g.Npad / 64);  // objective partials (one per 64 points)
   if (role == DEX_WS_FWD) {
-    size_t b = align256(nblk * 2 * s.tsize);
+    size_t b = align256(nparts * 2 * s.tsize);
     if (s.mfma) b += align256((size_t)fwd_max_slots(s.g.K) * s.g.Npad * sizeof(float2));
     return b;
   }
@@ -378,7 +422,7 @@ dex_status gmm_fwd(const dex_desc& d, int cfg, const GmmPtrs& in, void* F, void*
   if (!valid_shape(s)) return fail(DEX_ERR_UNSUPPORTED, "GMM shape/dtype/variant not supported");
   CacheLayout cl = cache_layout(s);
   char* cc = (char*)cache;
-  const size_t nblk = (size_t)(s.g.Npad / 256);
+  const size_t nparts = (size_t)(s.g.Npad / 64);
   if (!s.mfma) {
     double* fpart = (double*)ws;
     launch_fwd_valu<double>(s, in, (double*)(cc + cl.beta), (double*)f, fpart, st);
@@ -390,7 +434,7 @@ dex_status gmm_fwd(const dex_desc& d, int cfg, const GmmPtrs& in, void* F, void*
   if (cfg < 0 || cfg >= nfwd(s)) return fail(DEX_ERR_INVALID_ARG, "GMM forward config %d out of range", cfg);
   const FwdCfg c = fwd_cfg(s, cfg);
   float* fpart = (float*)ws;
-  float2* ml = (float2*)((char*)ws + align256(nblk * 2 * 4));
+  float2* ml = (float2*)((char*)ws + align256(nparts * 2 * 4));
   float* beta = (float*)(cc + cl.beta);
   const MfmaOps o = ops_of(s, cl, cc);
   const float* x = (const float*)in.x;
@@ -425,9 +469,10 @@ dex_status gmm_fwd(const dex_desc& d, int cfg, const GmmPtrs& in, void* F, void*
         pr.end(1);
       }
   }
-  hipLaunchKernelGGL((k_merge_lse<float>), dim3((unsigned)nblk), dim3(256), 0, st, ml, sp.sk,
+  const unsigned nq = (unsigned)(s.g.Npad / 64);
+  hipLaunchKernelGGL((k_merge_lse_quad<float>), dim3(nq), dim3(256), 0, st, ml, sp.sk,
                      (int)s.g.N, (int)s.g.Npad, (float*)f, fpart);
-  hipLaunchKernelGGL((k_finalize_F<float>), dim3(1), dim3(256), 0, st, fpart, (int)nblk, al,
+  hipLaunchKernelGGL((k_finalize_F<float>), dim3(1), dim3(256), 0, st, fpart, (int)nq, al,
                      (int)s.g.K, s.g.N, (float*)F);
   return check_hip(hipGetLastError(), "gmm_fwd (MFMA)");
 }
@@ -470,8 +515,11 @@ dex_status gmm_vjp(const dex_desc& d, int cfg, const GmmPtrs& in, const void* f,
       sp = mfma_bwd<PREC_F32>(s.g, c, o, beta, (const float*)f, (const float*)ct, part, st);
   }
   pr.end(1);
+  const int64_t E = (int64_t)mom_slot(s.g.DP);
+  hipLaunchKernelGGL(k_mom_reduce, dim3((unsigned)((s.g.K * E + 255) / 256)), dim3(256), 0, st,
+                     part, E, (int)s.g.K, sp.gw, sp.nsteps, sp.T, (int64_t)sp.W);
   hipLaunchKernelGGL(k_bwd_finalize_mom, dim3((unsigned)s.g.K), dim3(256), 0, st, (const float*)part,
-                     mom_slot(s.g.DP), sp.gw, sp.nsteps, sp.T, (int64_t)sp.W, (int)s.g.K,
+                     (size_t)E, 1, (int)s.g.K,
                      (int)s.g.D, s.g.DP, s.g.N, (const float*)in.alphas, (const float*)in.means,
                      (const float*)in.qd, (const float*)in.l, (const float*)ct,
                      (float*)out.d_alphas, (float*)out.d_means, (float*)out.d_qd, (float*)out.d_l,

@@ -172,6 +172,26 @@ DEX_DEV float rounded(float v) {
   }
 }
 
+// Eight consecutive operand elements (one 16-byte store per array in 16 bits,
+// two in FP32); `off` is a multiple of 8.
+template <int PREC>
+DEX_DEV void store8_split(typename Store<PREC>::S* hi, typename Store<PREC>::S* lo, size_t off,
+                          const float (&v)[8]) {
+  if constexpr (PREC == PREC_F32) {
+    *reinterpret_cast<f32x4*>(hi + off) = f32x4{v[0], v[1], v[2], v[3]};
+    *reinterpret_cast<f32x4*>(hi + off + 4) = f32x4{v[4], v[5], v[6], v[7]};
+  } else {
+    bf16x8 h, l;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      h[i] = (__bf16)v[i];
+      if constexpr (PREC == PREC_BF16X3) l[i] = (__bf16)(v[i] - (float)h[i]);
+    }
+    *reinterpret_cast<bf16x8*>(hi + off) = h;
+    if constexpr (PREC == PREC_BF16X3) *reinterpret_cast<bf16x8*>(lo + off) = l;
+  }
+}
+
 // Error-free transformation of a + b (Knuth's TwoSum).
 template <typename T>
 DEX_DEV void two_sum(T a, T b, T& s, T& e) {
@@ -295,6 +315,24 @@ DEX_DEV void mom_store(typename MomT<MP>::S* hi, typename MomT<MP>::S* lo, size_
 }
 
 template <int MP>
+DEX_DEV void mom_store8(typename MomT<MP>::S* hi, typename MomT<MP>::S* lo, size_t off,
+                        const float (&v)[8]) {
+  if constexpr (MP == MP_F32) {
+    *reinterpret_cast<f32x4*>(hi + off) = f32x4{v[0], v[1], v[2], v[3]};
+    *reinterpret_cast<f32x4*>(hi + off + 4) = f32x4{v[4], v[5], v[6], v[7]};
+  } else {
+    typename MomT<MP>::V8 h, l;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      h[i] = (_Float16)v[i];
+      if constexpr (MP == MP_F16X3) l[i] = (_Float16)(v[i] - (float)h[i]);
+    }
+    *reinterpret_cast<typename MomT<MP>::V8*>(hi + off) = h;
+    if constexpr (MP == MP_F16X3) *reinterpret_cast<typename MomT<MP>::V8*>(lo + off) = l;
+  }
+}
+
+template <int MP>
 DEX_DEV f32x4 mom_mma1(const typename MomT<MP>::V8& a, const typename MomT<MP>::V8& b, f32x4 c) {
   if constexpr (MP == MP_F32) {
 #pragma unroll
@@ -351,14 +389,26 @@ DEX_DEV void prep_x_tile(const float* __restrict__ x, int N, int D, int Npad, in
     tile[pp][b] = (p < N && b < D) ? x[(size_t)p * D + b] : 0.f;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 64 * DP; e += blockDim.x) {
-    int pp = e / DP, b = e % DP;
-    store_split<PREC>(xh, xl, (size_t)(p0 + pp) * DP + b, tile[pp][b]);
+  // x~: eight consecutive features of a point per store
+  for (int e = threadIdx.x; e < 8 * DP; e += blockDim.x) {
+    const int pp = e / (DP / 8), b0 = 8 * (e % (DP / 8));
+    float v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = tile[pp][b0 + i];
+    store8_split<PREC>(xh, xl, (size_t)(p0 + pp) * DP + b0, v);
   }
-  for (int e = threadIdx.x; e < 64 * DP; e += blockDim.x) {
-    int b = e / 64, pp = e % 64;  // p0 is a multiple of 64: 32-point steps align
-    mom_store<MomOf<PREC>::MP>(xhT, xlT, (size_t)b * Npad + p0 + (pp & 32) + mom_pos(pp & 31),
-                               tile[pp][b]);
+  // x~^T: eight consecutive storage positions of a feature row per store (p0
+  // is a multiple of 64, so the 32-point steps align); position s of a step
+  // holds point 4(s/8) + s%4 + 16((s/4)%2)
+  for (int e = threadIdx.x; e < 8 * DP; e += blockDim.x) {
+    const int b = e / 8, s0 = 8 * (e % 8);
+    float v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int sp = s0 + i, st = sp & 32, q = sp & 31;
+      v[i] = tile[st + 4 * (q >> 3) + (q & 3) + 16 * ((q >> 2) & 1)][b];
+    }
+    mom_store8<MomOf<PREC>::MP>(xhT, xlT, (size_t)b * Npad + p0 + s0, v);
   }
 }
 
@@ -370,31 +420,46 @@ DEX_DEV void prep_q_comp(const float* __restrict__ alphas, const float* __restri
                          typename Store<PREC>::S* Qh, typename Store<PREC>::S* Ql, float* negc,
                          float* kappa) {
   __shared__ float qs[DP][DP + 1];
+  __shared__ float mus[DP], qds[DP];
   const int L = D * (D - 1) / 2;
-  __syncthreads();
-  for (int e = threadIdx.x; e < DP * DP; e += blockDim.x) {
-    int a = e / DP, b = e % DP;
-    float q = 0.f;
-    if (a < D && b < D) {
-      if (a == b)
-        q = expf(qd[(size_t)k * D + a]);
-      else if (a > b)
-        q = l[(size_t)k * L + a * (a - 1) / 2 + b];
-    }
-    store_split<PREC>(Qh, Ql, (size_t)k * DP * DP + e, q);
-    qs[a][b] = rounded<PREC>(q);
-  }
   __syncthreads();
   if (threadIdx.x < DP) {
     const int a = threadIdx.x;
+    mus[a] = a < D ? means[(size_t)k * D + a] : 0.f;
+    qds[a] = a < D ? qd[(size_t)k * D + a] : 0.f;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < DP * DP; e += blockDim.x) {
+    const int a = e / DP, b = e % DP;
+    float q = 0.f;
+    if (a < D && b < D) {
+      if (a == b)
+        q = expf(qds[a]);
+      else if (a > b)
+        q = l[(size_t)k * L + a * (a - 1) / 2 + b];
+    }
+    qs[a][b] = q;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < DP * DP / 8; e += blockDim.x) {
+    const int a = e / (DP / 8), b0 = 8 * (e % (DP / 8));
+    float v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = qs[a][b0 + i];
+    store8_split<PREC>(Qh, Ql, (size_t)k * DP * DP + (size_t)a * DP + b0, v);
+  }
+  if (threadIdx.x < DP) {
+    // -c~ with the operand values the products use
+    const int a = threadIdx.x;
     float c = 0.f;
-    for (int b = 0; b < D; ++b) c = fmaf(qs[a][b], means[(size_t)k * D + b], c);
+    for (int b = 0; b < D; ++b) c = fmaf(rounded<PREC>(qs[a][b]), mus[b], c);
     negc[(size_t)k * DP + a] = -c;
   }
-  if (threadIdx.x == 0) {
-    float s = alphas[k];
-    for (int d = 0; d < D; ++d) s += qd[(size_t)k * D + d];
-    kappa[k] = s;
+  if (threadIdx.x < 64) {
+    float s = 0.f;
+    for (int d = threadIdx.x; d < D; d += 64) s += qds[d];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) kappa[k] = alphas[k] + s;
   }
 }
 
@@ -531,15 +596,15 @@ DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0, int k0, int k
 // ---------------------------------------------------------------------------
 // Forward unit of one wave, components resident: the Q~ operands, -c~ and
 // kappa of the NKQ components k0 .. k0+NKQ-1 stay in registers while the
-// 16-point tiles t0 .. t1-1 of x~ stream through them (the next tile is loaded
-// while the current one is computed). Every Q~ chunk load thus serves all the
+// 16-point tiles t0 .. t1-1 of x~ stream through them (tile t + PD is loaded
+// while tile t is computed). Every Q~ chunk load thus serves all the
 // wave's tiles, instead of one tile set per load. Per tile, the squared norms
 // of the NKQ components reduce across the 4 lane groups so that lane group
 // jown(g) owns component k0 + jown of point c; it stores beta (rows padded to
 // a multiple of 4 components, so the padding components of the last group
 // need no mask) and the tile's (max, sum) log-sum-exp partial over the
 // group's valid components.
-template <int DP, int PREC, int NKQ, int CK>
+template <int DP, int PREC, int NKQ, int CK, int PD>
 DEX_DEV void fwd_unit_kq(const MfmaOps& ops, int Npad, int K, int k0, int t0, int t1,
                          float* __restrict__ beta, float2* __restrict__ mlg) {
   static_assert(NKQ == 2 || NKQ == 4, "components per wave");
@@ -582,25 +647,41 @@ DEX_DEV void fwd_unit_kq(const MfmaOps& ops, int Npad, int K, int k0, int t0, in
     for (int ch = 0; ch < NCH; ++ch)
       xb[ch] = load_op<PREC, NV>(xh, xl, (size_t)(16 * t + c) * DP + CK * ch + NV * g);
   };
+  auto products = [&](int j, const Op<PREC, NV>(&xb)[NCH], f32x4(&acc)[NRB]) {
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) acc[rb] = nc[j][rb];
+    int n = 0;
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+        if (CK * ch <= 16 * rb + 15) acc[rb] = mma<PREC, NV>(q[j][n++], xb[ch], acc[rb]);
+  };
+  auto sumsq = [&](const f32x4(&acc)[NRB]) {
+    float t2 = 0.f;
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) t2 = fmaf(acc[rb][i], acc[rb][i], t2);
+    return t2;
+  };
   auto compute = [&](int t, const Op<PREC, NV>(&xb)[NCH]) {
+    // the products of component j+1 are issued while the squared norm of
+    // component j is summed, so the matrix cores and the vector ALU overlap
     float sq[NKQ];
+    f32x4 acc[2][NRB];
+    products(0, xb, acc[0]);
 #pragma unroll
     for (int j = 0; j < NKQ; ++j) {
-      f32x4 acc[NRB];
+      if (j + 1 < NKQ) products(j + 1, xb, acc[(j + 1) & 1]);
+      sq[j] = sumsq(acc[j & 1]);
+      if (j + 1 < NKQ) {
 #pragma unroll
-      for (int rb = 0; rb < NRB; ++rb) acc[rb] = nc[j][rb];
-      int n = 0;
-#pragma unroll
-      for (int rb = 0; rb < NRB; ++rb)
-#pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-          if (CK * ch <= 16 * rb + 15) acc[rb] = mma<PREC, NV>(q[j][n++], xb[ch], acc[rb]);
-      float t2 = 0.f;
-#pragma unroll
-      for (int rb = 0; rb < NRB; ++rb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) t2 = fmaf(acc[rb][i], acc[rb][i], t2);
-      sq[j] = t2;
+        for (int i = 0; i < NQ; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix-core op
+          __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // then three vector ALU ops
+        }
+      }
     }
     treduce_groups<NKQ>(sq);
     const float b = kap - 0.5f * sq[0];
@@ -615,20 +696,23 @@ DEX_DEV void fwd_unit_kq(const MfmaOps& ops, int Npad, int K, int k0, int t0, in
     mlg[p] = make_float2(m, e);
   };
 
-  Op<PREC, NV> xa[NCH], xb[NCH];
-  if (t0 < t1) load_x(t0, xa);
-  int t = t0;
-  for (; t + 1 < t1; t += 2) {
-    load_x(t + 1, xb);
-    __builtin_amdgcn_sched_barrier(0);
-    compute(t, xa);
-    __builtin_amdgcn_sched_barrier(0);
-    load_x(min(t + 2, t1 - 1), xa);
-    __builtin_amdgcn_sched_barrier(0);
-    compute(t + 1, xb);
-    __builtin_amdgcn_sched_barrier(0);
+  // ring of PD + 1 tile buffers: tile t + PD is loaded while tile t is
+  // computed. Tile indices past t1 - 1 are clamped to it: the last tile is then
+  // computed again and stores the same values, which keeps the loop free of
+  // branches between loads and their use.
+  Op<PREC, NV> xr[PD + 1][NCH];
+  if (t0 >= t1) return;
+#pragma unroll
+  for (int i = 0; i < PD; ++i) load_x(min(t0 + i, t1 - 1), xr[i]);
+  for (int t = t0; t < t1; t += PD + 1) {
+#pragma unroll
+    for (int r = 0; r <= PD; ++r) {
+      load_x(min(t + r + PD, t1 - 1), xr[(r + PD) % (PD + 1)]);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(min(t + r, t1 - 1), xr[r]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
-  if (t < t1) compute(t, xa);
 }
 
 // ---------------------------------------------------------------------------
@@ -777,6 +861,12 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
           }
           sacc[gk][q0 + bb] = mom_mma1<MP>(sa[0], xt[bb][0], acc);
         }
+      }
+      // the scaling of the next row block overlaps this block's products
+#pragma unroll
+      for (int i = 0; i < NBLK; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -961,6 +1051,54 @@ DEX_DEV void merge_lse_block(const float2* __restrict__ ml, int Sk, int N, int N
   block_comp_sum<T>(v, ps, pe);
 }
 
+// Merge of many (max, sum) partials per point: four threads per point (64
+// points per 256-thread block), each folding every fourth partial in order
+// (online log-sum-exp, loads issued 8 at a time); the four results are then
+// combined in thread order. f[p] and a compensated partial sum of f over the
+// block's points (valid in thread 0).
+template <typename T>
+DEX_DEV void merge_lse_quad(const float2* __restrict__ ml, int Sk, int N, int Npad, int p0,
+                            T* __restrict__ f, T& ps, T& pe) {
+  const int p = p0 + (threadIdx.x >> 2), q = threadIdx.x & 3;
+  float M = -INFINITY, L = 0.f;
+  if (p < N) {
+    for (int s0 = q; s0 < Sk; s0 += 32) {
+      float2 e[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int sl = s0 + 4 * u;
+        e[u] = sl < Sk ? ml[(size_t)sl * Npad + p] : make_float2(-INFINITY, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (e[u].y == 0.f) continue;
+        const float d = e[u].x - M;
+        const float x = __expf(-fabsf(d));
+        L = d > 0.f ? fmaf(L, x, e[u].y) : fmaf(e[u].y, x, L);
+        M = fmaxf(M, e[u].x);
+      }
+    }
+  }
+  const int base = threadIdx.x & ~3;
+  float Mq[4], Lq[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    Mq[i] = __shfl(M, base + i, 64);
+    Lq[i] = __shfl(L, base + i, 64);
+  }
+  float Mt = fmaxf(fmaxf(Mq[0], Mq[1]), fmaxf(Mq[2], Mq[3]));
+  float Lt = 0.f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (Lq[i] > 0.f) Lt += Lq[i] * __expf(Mq[i] - Mt);
+  T v = 0;
+  if (p < N && q == 0) {
+    v = (T)(Mt + logf(Lt));
+    f[p] = v;
+  }
+  block_comp_sum<T>(v, ps, pe);
+}
+
 // F = (sum of compensated partials, fixed order) - N logsumexp(alphas); the
 // result is written by thread 0.
 template <typename T>
@@ -975,12 +1113,26 @@ DEX_DEV void finalize_F_block(const T* __restrict__ fpart, int nparts, const T* 
   }
   T s = 0, e = 0;
   block_comp_sum<T>(v + ve, s, e);
+  // logsumexp(alphas) by the whole block: max, then the sum in a fixed order
+  __shared__ T red[16];
+  T m = -INFINITY;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) m = alphas[k] > m ? alphas[k] : m;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const T om = xor_lane(m, o);
+    m = om > m ? om : m;
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  m = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = red[w] > m ? red[w] : m;
+  T z = 0;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) z += dexp<T>(alphas[k] - m);
+  T zs = 0, ze = 0;
+  block_comp_sum<T>(z, zs, ze);
   if (threadIdx.x == 0) {
-    T m = -INFINITY;
-    for (int k = 0; k < K; ++k) m = alphas[k] > m ? alphas[k] : m;
-    T z = 0;
-    for (int k = 0; k < K; ++k) z += dexp<T>(alphas[k] - m);
-    const T lse = m + dlog<T>(z);
+    const T lse = m + dlog<T>(zs + ze);
     F[0] = (s - (T)N * lse) + e;
   }
 }

@@ -18,7 +18,8 @@ struct GmmGeom {
 
 // wps: waves per SIMD to launch (0: as many as can be resident).
 struct FwdCfg {
-  int nkq, wps;  // components resident per wave (2 or 4; 4 for BF16 only), waves per SIMD
+  int nkq, wps, pd;  // components resident per wave (2 or 4; 4 for BF16 only), waves per
+                     // SIMD, x~ tiles loaded ahead (1 or 2)
 };
 struct BwdCfg {
   int gw, wps;  // components per wave, waves per SIMD

@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(256) k_prep_q(const float* __restrict__ alphas
 // (group of NKQ components, 16-point tile), group-major: a wave loads a
 // group's operands once and streams its tiles; its range covers at most a few
 // groups.
-template <int DP, int PREC, int NKQ, int CK>
+template <int DP, int PREC, int NKQ, int CK, int PD>
 __global__ void __launch_bounds__(256) k_gmm_fwd(MfmaOps ops, int Npad, int K, int64_t T, int W,
                                                  float* __restrict__ beta,
                                                  float2* __restrict__ ml) {
@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(256) k_gmm_fwd(MfmaOps ops, int Npad, int K, i
     const int64_t grp = pos / ntiles;
     const int64_t ta = pos - grp * ntiles;
     const int64_t tb = min<int64_t>(ntiles, ta + (hi - pos));
-    fwd_unit_kq<DP, PREC, NKQ, CK>(ops, Npad, K, (int)grp * NKQ, (int)ta, (int)tb, beta,
+    fwd_unit_kq<DP, PREC, NKQ, CK, PD>(ops, Npad, K, (int)grp * NKQ, (int)ta, (int)tb, beta,
                                    ml + (size_t)grp * Npad);
     pos += tb - ta;
   }
@@ -135,16 +135,16 @@ static int launch_waves(int bpc, int wps) {
   return std::min(kMaxWaves, w * num_cus());
 }
 
-template <int DP, int NKQ, int CK>
+template <int DP, int NKQ, int CK, int PD>
 static FlatSplit fwd_launch(const GmmGeom& g, const FwdCfg& c, const MfmaOps& o, float* beta,
                             float2* ml, hipStream_t st) {
-  static const int bpc = blocks_per_cu(k_gmm_fwd<DP, P, NKQ, CK>);
+  static const int bpc = blocks_per_cu(k_gmm_fwd<DP, P, NKQ, CK, PD>);
   FlatSplit sp{};
   sp.sk = (int)((g.K + NKQ - 1) / NKQ);
   sp.T = (int64_t)sp.sk * (g.Npad / 16);
   sp.W = (int)std::min<int64_t>(sp.T, launch_waves(bpc, c.wps));
-  hipLaunchKernelGGL((k_gmm_fwd<DP, P, NKQ, CK>), dim3((unsigned)((sp.W + 3) / 4)), dim3(256), 0, st,
-                     o, (int)g.Npad, (int)g.K, sp.T, sp.W, beta, ml);
+  hipLaunchKernelGGL((k_gmm_fwd<DP, P, NKQ, CK, PD>), dim3((unsigned)((sp.W + 3) / 4)), dim3(256),
+                     0, st, o, (int)g.Npad, (int)g.K, sp.T, sp.W, beta, ml);
   return sp;
 }
 
@@ -154,9 +154,12 @@ static FlatSplit fwd_dp(const GmmGeom& g, const FwdCfg& c, const MfmaOps& o, flo
                         float2* ml, hipStream_t st) {
   constexpr int CK = (P != PREC_F32 && DP >= 32) ? 32 : 16;
   if constexpr (P == PREC_BF16) {
-    if (c.nkq == 4) return fwd_launch<DP, 4, CK>(g, c, o, beta, ml, st);
+    if (c.nkq == 4)
+      return c.pd == 2 ? fwd_launch<DP, 4, CK, 2>(g, c, o, beta, ml, st)
+                       : fwd_launch<DP, 4, CK, 1>(g, c, o, beta, ml, st);
   }
-  return fwd_launch<DP, 2, CK>(g, c, o, beta, ml, st);
+  return c.pd == 2 ? fwd_launch<DP, 2, CK, 2>(g, c, o, beta, ml, st)
+                   : fwd_launch<DP, 2, CK, 1>(g, c, o, beta, ml, st);
 }
 
 template <>
