@@ -278,15 +278,17 @@ Shape shape_of(const dex_desc& d) {
 }
 
 // forward candidates: (components resident per wave, waves per SIMD (0: all
-// resident), x~ tiles loaded ahead)
-const FwdCfg kFwdBF[] = {{4, 0, 1}, {4, 0, 2}, {2, 0, 1}, {2, 0, 2}, {4, 1, 2}, {2, 2, 2}};
+// resident), x~ tiles loaded ahead); BF16 config 0 is the feature-product form
+// (D = 64 only; other D run config 1 in its place)
+const FwdCfg kFwdBF[] = {{0, 0, 0}, {4, 0, 1}, {4, 0, 2}, {2, 0, 1},
+                         {2, 0, 2}, {4, 1, 2}, {2, 2, 2}, {0, 1, 0}};
 const FwdCfg kFwdF32[] = {{2, 0, 1}, {2, 0, 2}, {2, 2, 1}, {2, 1, 2}};
 // reverse candidates: (components per wave, waves per SIMD (0: all resident))
 const BwdCfg kBwdBF[] = {{2, 0}, {1, 0}, {4, 0}, {2, 2}, {1, 2}, {1, 3}, {2, 1}, {4, 1}};
 const BwdCfg kBwdF32[] = {{2, 0}, {1, 0}, {4, 0}, {2, 2}, {1, 2}};
 constexpr int kValuS = 16;
 
-int nfwd(const Shape& s) { return s.prec == PREC_BF16 ? 6 : 4; }
+int nfwd(const Shape& s) { return s.prec == PREC_BF16 ? 8 : 4; }
 int nbwd(const Shape& s) { return s.prec == PREC_F32 ? 5 : 8; }
 size_t mom_es(const Shape& s) { return s.prec == PREC_F32 ? 4 : 2; }
 FwdCfg fwd_cfg(const Shape& s, int i) { return s.prec == PREC_BF16 ? kFwdBF[i] : kFwdF32[i]; }
@@ -294,6 +296,9 @@ BwdCfg bwd_cfg(const Shape& s, int i) { return s.prec == PREC_F32 ? kBwdF32[i] :
 
 struct CacheLayout {
   size_t xh, xl, xhT, xlT, Qh, Ql, negc, kappa, beta, total;
+  // feature-product forward (BF16, D = 64): coefficient operand, kappa',
+  // rescale factors, scaled FP16 copy of x, per-tile scale exponents
+  size_t W16, kq, isc, x16, texp;
 };
 
 CacheLayout cache_layout(const Shape& s) {
@@ -317,6 +322,14 @@ CacheLayout cache_layout(const Shape& s) {
     c.negc = take(g.K * g.DP * 4);
     c.kappa = take(g.K * 4);
     c.beta = take(beta_rows(g.K) * g.Npad * 4);
+    if (qf_eligible(g, s.prec)) {
+      const size_t Kp = (size_t)beta_rows(g.K);
+      c.W16 = take(Kp / 16 * 68 * 64 * 8 * 2);
+      c.kq = take(Kp * 4);
+      c.isc = take(Kp * 4);
+      c.x16 = take((size_t)g.Npad * 64 * 2);
+      c.texp = take((size_t)(g.Npad / 64) * 4);
+    }
   } else {
     c.beta = take(g.K * g.N * s.tsize);
   }
@@ -446,10 +459,18 @@ dex_status gmm_fwd(const dex_desc& d, int cfg, const GmmPtrs& in, void* F, void*
   FlatSplit sp{};
   switch (s.prec) {
     case PREC_BF16:
-      mfma_prep<PREC_BF16>(s.g, x, al, mu, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
-      {
+      if (c.nkq == 0 && qf_eligible(s.g, s.prec)) {
+        qf_prep(s.g, x, al, mu, qd, l, xhT, cc + cl.x16, (int*)(cc + cl.texp), cc + cl.W16,
+                (float*)(cc + cl.kq), (float*)(cc + cl.isc), st);
         ProfRange pr(DEX_PROF_GMM_FWD, st);
-        sp = mfma_fwd<PREC_BF16>(s.g, c, o, beta, ml, st);
+        sp = qf_fwd(s.g, c, cc + cl.x16, cc + cl.W16, (const float*)(cc + cl.kq),
+                    (const float*)(cc + cl.isc), (const int*)(cc + cl.texp), beta, ml, st);
+        pr.end(1);
+      } else {
+        const FwdCfg ck = c.nkq == 0 ? kFwdBF[1] : c;
+        mfma_prep<PREC_BF16>(s.g, x, al, mu, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
+        ProfRange pr(DEX_PROF_GMM_FWD, st);
+        sp = mfma_fwd<PREC_BF16>(s.g, ck, o, beta, ml, st);
         pr.end(1);
       }
       break;

@@ -377,20 +377,34 @@ struct MfmaOps {
 // ---------------------------------------------------------------------------
 // Operand preparation for 64 points starting at p0: x~ (row-major) and x~^T,
 // zero padded to DP features and Npad points.
+// Optional outputs: xh == nullptr skips x~; tmax != nullptr receives the
+// largest |x| of the tile (for the scaling of the feature-product forward).
 template <int PREC, int DP>
 DEX_DEV void prep_x_tile(const float* __restrict__ x, int N, int D, int Npad, int p0,
                          typename Store<PREC>::S* xh, typename Store<PREC>::S* xl,
                          typename MomT<MomOf<PREC>::MP>::S* xhT,
-                         typename MomT<MomOf<PREC>::MP>::S* xlT) {
+                         typename MomT<MomOf<PREC>::MP>::S* xlT, float* tmax = nullptr) {
   __shared__ float tile[64][DP + 1];
+  __shared__ float red[16];
   __syncthreads();
+  float mx = 0.f;
   for (int e = threadIdx.x; e < 64 * DP; e += blockDim.x) {
     int pp = e / DP, b = e % DP, p = p0 + pp;
-    tile[pp][b] = (p < N && b < D) ? x[(size_t)p * D + b] : 0.f;
+    const float v = (p < N && b < D) ? x[(size_t)p * D + b] : 0.f;
+    tile[pp][b] = v;
+    mx = fmaxf(mx, fabsf(v));
+  }
+  if (tmax) {
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   }
   __syncthreads();
+  if (tmax && threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mx = fmaxf(mx, red[w]);
+    tmax[p0 / 64] = mx;
+  }
   // x~: eight consecutive features of a point per store
-  for (int e = threadIdx.x; e < 8 * DP; e += blockDim.x) {
+  for (int e = threadIdx.x; xh && e < 8 * DP; e += blockDim.x) {
     const int pp = e / (DP / 8), b0 = 8 * (e % (DP / 8));
     float v[8];
 #pragma unroll
@@ -944,11 +958,51 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
     return s + err;
   };
   __shared__ float red[8];
-  // softmax weight of alpha_k, by the whole block
-  float am = -INFINITY;
-  for (int j = threadIdx.x; j < K; j += blockDim.x) am = fmaxf(am, alphas[j]);
-  am = wave_max(am);
+  __shared__ float Ps[10 * 256 + 64 + 4];  // summed slot: S blocks, u, A
+  // Every global input is loaded first, each thread's loads issued together,
+  // so the block waits for memory once instead of once per phase.
+  const int NE = NBLK * 256 + DP + 1;
+  float pv[11], qv[16], av[4];
+#pragma unroll
+  for (int i = 0; i < 11; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    pv[i] = e < NE ? comp_sum((size_t)e) : 0.f;
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    const int a = e / D, b = e - (e / D) * D;
+    float q = 0.f;
+    if (e < D * D) {
+      if (a == b)
+        q = expf(qd[(size_t)k * D + a]);
+      else if (a > b)
+        q = l[(size_t)k * L + a * (a - 1) / 2 + b];
+    }
+    qv[i] = q;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int j = threadIdx.x + 256 * i;
+    av[i] = j < K ? alphas[j] : -INFINITY;
+  }
+  const float mu_t = threadIdx.x < D ? means[(size_t)k * D + threadIdx.x] : 0.f;
   __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 11; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    if (e < NE) Ps[e] = pv[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    if (e < D * D) Qs[e / D][e % D] = qv[i];
+  }
+  if (threadIdx.x < D) mus[threadIdx.x] = mu_t;
+  for (int j = threadIdx.x + 1024; j < K; j += blockDim.x) av[3] = fmaxf(av[3], alphas[j]);
+  // softmax weight of alpha_k, by the whole block
+  float am = fmaxf(fmaxf(av[0], av[1]), fmaxf(av[2], av[3]));
+  am = wave_max(am);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = am;
   __syncthreads();
   am = red[0];
@@ -958,28 +1012,11 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
   az = wave_sum(az);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[4 + (threadIdx.x >> 6)] = az;
+  for (int e = threadIdx.x; e < D; e += blockDim.x) us[e] = Ps[NBLK * 256 + e];
+  if (threadIdx.x == 0) Ash = Ps[NBLK * 256 + DP];
   __syncthreads();
   az = 0.f;
   for (int w = 0; w < (int)(blockDim.x >> 6); ++w) az += red[4 + w];
-  __syncthreads();
-  for (int e = threadIdx.x; e <= D; e += blockDim.x) {
-    if (e < D) {
-      us[e] = comp_sum((size_t)NBLK * 256 + e);
-      mus[e] = means[(size_t)k * D + e];
-    } else {
-      Ash = comp_sum((size_t)NBLK * 256 + DP);
-    }
-  }
-  for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
-    const int a = e / D, b = e % D;
-    float q = 0.f;
-    if (a == b)
-      q = expf(qd[(size_t)k * D + a]);
-    else if (a > b)
-      q = l[(size_t)k * L + a * (a - 1) / 2 + b];
-    Qs[a][b] = q;
-  }
-  __syncthreads();
   const float A = Ash;
   for (int e = threadIdx.x; e < NBLK * 256; e += blockDim.x) {
     const int q = e >> 8, ln = (e >> 2) & 63, i = e & 3;
@@ -988,26 +1025,37 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
     const int bb = q - ab * (ab + 1) / 2;
     const int r = 16 * bb + (ln & 15), s = 16 * ab + 4 * (ln >> 4) + i;
     if (r >= D || s >= D || r > s) continue;
-    const float v = comp_sum((size_t)e) - us[r] * mus[s] - mus[r] * us[s] + A * mus[r] * mus[s];
+    const float v = Ps[e] - us[r] * mus[s] - mus[r] * us[s] + A * mus[r] * mus[s];
     C[r][s] = v;
     C[s][r] = v;
   }
   __syncthreads();
-  const int nM = D * (D + 1) / 2;
-  for (int e = threadIdx.x; e < nM; e += blockDim.x) {
-    int a = (int)((sqrtf(8.f * e + 1.f) - 1.f) * 0.5f);
-    while (a * (a + 1) / 2 > e) --a;
-    while ((a + 1) * (a + 2) / 2 <= e) ++a;
-    const int b = e - a * (a + 1) / 2;
-    float m = 0.f;
-    for (int cc = 0; cc <= a; ++cc) m = fmaf(Qs[a][cc], C[cc][b], m);
-    if (a > b) {
-      float* o = d_l + (size_t)k * L + a * (a - 1) / 2 + b;
-      *o = accumulate ? *o - m : -m;
-    } else {
-      float* o = d_qd + (size_t)k * D + a;
-      const float gq = A - Qs[a][a] * m;
-      *o = accumulate ? *o + gq : gq;
+  // M = Q C (Q lower triangular, so the sum may run over all cc < D): thread t
+  // owns column b = t % 64 and rows a = t / 64 + 4r; the 16 accumulators are
+  // independent and a wave reads each Q element as one broadcast. Called with
+  // 256 threads; rows and columns past D are computed and dropped.
+  {
+    const int b = threadIdx.x & 63, a0 = threadIdx.x >> 6;
+    float m[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) m[r] = 0.f;
+    for (int cc = 0; cc < D; ++cc) {  // entries past D are not initialised
+      const float cv = C[cc][b];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) m[r] = fmaf(Qs[a0 + 4 * r][cc], cv, m[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int a = a0 + 4 * r;
+      if (a >= D || b >= D || a < b) continue;
+      if (a > b) {
+        float* o = d_l + (size_t)k * L + a * (a - 1) / 2 + b;
+        *o = accumulate ? *o - m[r] : -m[r];
+      } else {
+        float* o = d_qd + (size_t)k * D + a;
+        const float gq = A - Qs[a][a] * m[r];
+        *o = accumulate ? *o + gq : gq;
+      }
     }
   }
   for (int a = threadIdx.x; a < D; a += blockDim.x) {

@@ -18,8 +18,9 @@ struct GmmGeom {
 
 // wps: waves per SIMD to launch (0: as many as can be resident).
 struct FwdCfg {
-  int nkq, wps, pd;  // components resident per wave (2 or 4; 4 for BF16 only), waves per
-                     // SIMD, x~ tiles loaded ahead (1 or 2)
+  int nkq, wps, pd;  // components resident per wave (2 or 4; 4 for BF16 only; 0: the
+                     // feature-product form), waves (blocks for nkq = 0) per SIMD (CU),
+                     // x~ tiles loaded ahead (1 or 2)
 };
 struct BwdCfg {
   int gw, wps;  // components per wave, waves per SIMD
@@ -44,8 +45,9 @@ constexpr int kMaxWaves = 8192;
 
 // Forward log-sum-exp partials per point: one per group of >= 2 components.
 inline int64_t fwd_max_slots(int64_t K) { return (K + 1) / 2; }
-// beta rows: K rounded up to whole groups of 4 components
-inline int64_t beta_rows(int64_t K) { return (K + 3) / 4 * 4; }
+// beta rows: K rounded up to whole passes of 32 components (the padding rows
+// take the stores of the padding components of the last group or pass)
+inline int64_t beta_rows(int64_t K) { return (K + 31) / 32 * 32; }
 // Reverse partials per component: the launch keeps W <= (slots - 1) * groups.
 inline int64_t bwd_max_slots(int64_t Npad, int64_t K) {
   return std::max<int64_t>(2, std::min<int64_t>(Npad / 32, 9600 / K));
@@ -61,6 +63,18 @@ FlatSplit mfma_fwd(const GmmGeom& g, const FwdCfg& c, const dexk::MfmaOps& o, fl
 template <int PREC>
 FlatSplit mfma_bwd(const GmmGeom& g, const BwdCfg& c, const dexk::MfmaOps& o, const float* beta,
                    const float* f, const float* ct, float* part, hipStream_t st);
+
+// Feature-product forward (BF16 variant, D = 64; defined with the BF16 kernels).
+// qf_prep: x~^T, the per-tile scaled FP16 copy of x and its exponents, the
+// coefficient operand, kappa' and rescale factors. qf_fwd: beta and the per-pass
+// log-sum-exp partials (FlatSplit::sk passes; W holds the block count).
+void qf_prep(const GmmGeom& g, const float* x, const float* alphas, const float* means,
+             const float* qd, const float* l, void* xhT, void* x16, int* tile_exp, void* W16,
+             float* kq, float* isc, hipStream_t st);
+FlatSplit qf_fwd(const GmmGeom& g, const FwdCfg& c, const void* x16, const void* W16,
+                 const float* kq, const float* isc, const int* tile_exp, float* beta, float2* ml,
+                 hipStream_t st);
+inline bool qf_eligible(const GmmGeom& g, int prec) { return prec == dexk::PREC_BF16 && g.D == 64; }
 
 template <>
 void mfma_prep<dexk::PREC_F32>(const GmmGeom&, const float*, const float*, const float*,

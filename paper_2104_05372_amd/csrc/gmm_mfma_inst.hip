@@ -2,7 +2,10 @@
 // precision, selected at compile time by DEX_PREC (0 FP32, 1 BF16, 2 split-BF16).
 #include <algorithm>
 
+#include <utility>
+
 #include "gmm_host.h"
+#include "gmm_qf.h"
 #include "internal.h"
 
 #ifndef DEX_PREC
@@ -11,24 +14,25 @@
 
 namespace dexk {
 
+// Operand preparation in one launch: blocks 0 .. K-1 prepare component k
+// (Q~, -c~, kappa), the others one 64-point tile of x~ and x~^T each.
 template <int PREC, int DP>
-__global__ void __launch_bounds__(256) k_prep_x(const float* __restrict__ x, int N, int D, int Npad,
-                                                typename Store<PREC>::S* xh,
-                                                typename Store<PREC>::S* xl,
-                                                typename MomT<MomOf<PREC>::MP>::S* xhT,
-                                                typename MomT<MomOf<PREC>::MP>::S* xlT) {
-  prep_x_tile<PREC, DP>(x, N, D, Npad, blockIdx.x * 64, xh, xl, xhT, xlT);
-}
-
-template <int PREC, int DP>
-__global__ void __launch_bounds__(256) k_prep_q(const float* __restrict__ alphas,
-                                                const float* __restrict__ means,
-                                                const float* __restrict__ qd,
-                                                const float* __restrict__ l, int D,
-                                                typename Store<PREC>::S* Qh,
-                                                typename Store<PREC>::S* Ql, float* negc,
-                                                float* kappa) {
-  prep_q_comp<PREC, DP>(alphas, means, qd, l, D, blockIdx.x, Qh, Ql, negc, kappa);
+__global__ void __launch_bounds__(256) k_prep(const float* __restrict__ x, int N, int D, int Npad,
+                                              int K, const float* __restrict__ alphas,
+                                              const float* __restrict__ means,
+                                              const float* __restrict__ qd,
+                                              const float* __restrict__ l,
+                                              typename Store<PREC>::S* xh,
+                                              typename Store<PREC>::S* xl,
+                                              typename MomT<MomOf<PREC>::MP>::S* xhT,
+                                              typename MomT<MomOf<PREC>::MP>::S* xlT,
+                                              typename Store<PREC>::S* Qh,
+                                              typename Store<PREC>::S* Ql, float* negc,
+                                              float* kappa) {
+  if ((int)blockIdx.x < K)
+    prep_q_comp<PREC, DP>(alphas, means, qd, l, D, blockIdx.x, Qh, Ql, negc, kappa);
+  else
+    prep_x_tile<PREC, DP>(x, N, D, Npad, (blockIdx.x - K) * 64, xh, xl, xhT, xlT);
 }
 
 // Both grid kernels split their work evenly over W waves (split_lo), so every
@@ -86,6 +90,321 @@ __global__ void __launch_bounds__(256) k_gmm_bwd(MfmaOps ops, int N, int Npad, i
   }
 }
 
+
+#if DEX_PREC == 1
+// ---------------------------------------------------------------------------
+// Feature-product forward (see gmm_qf.h). k_qf_x: per 64-point tile, x~^T for
+// the reverse pass and the scaled FP16 copy of x with its exponent. k_qf_w:
+// one block per component k < Kp: P = Q^T Q, the coefficient operand, kappa'
+// and the rescale factor.
+__global__ void __launch_bounds__(256) k_qf_x(const float* __restrict__ x, int N, int Npad,
+                                              _Float16* __restrict__ xhT,
+                                              _Float16* __restrict__ x16,
+                                              int* __restrict__ tile_exp) {
+  // x~^T for the reverse pass, and x scaled by the tile's 2^-ex (|x| 2^-ex <
+  // 2^7) in FP16, row-major, for the feature products
+  __shared__ float tile[64][65];
+  __shared__ float red[4];
+  const int p0 = blockIdx.x * 64, t = threadIdx.x;
+  float mx = 0.f;
+  for (int e = t; e < 64 * 64; e += 256) {
+    const int pp = e >> 6, b = e & 63, p = p0 + pp;
+    const float v = p < N ? x[(size_t)p * 64 + b] : 0.f;
+    tile[pp][b] = v;
+    mx = fmaxf(mx, fabsf(v));
+  }
+  mx = wave_max(mx);
+  if ((t & 63) == 0) red[t >> 6] = mx;
+  __syncthreads();
+  mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  // ex >= -6 keeps the linear features (x 2^-ex)(2^-ex) below 2^13 as well
+  int ex = -6;
+  if (mx > 0.f) {
+    int E;
+    frexpf(mx, &E);  // mx < 2^E
+    ex = max(-6, E - 7);
+  }
+  if (t == 0) tile_exp[blockIdx.x] = ex;
+  const float sx = ldexpf(1.f, -ex);
+  for (int e = t; e < 8 * 64; e += 256) {
+    const int pp = e >> 3, b0 = 8 * (e & 7);
+    qf::h8 h;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) h[i] = (_Float16)(tile[pp][b0 + i] * sx);
+    *reinterpret_cast<qf::h8*>(x16 + (size_t)(p0 + pp) * 64 + b0) = h;
+  }
+  for (int e = t; e < 8 * 64; e += 256) {
+    const int b = e / 8, s0 = 8 * (e % 8);
+    float v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int sp = s0 + i, st = sp & 32, q = sp & 31;
+      v[i] = tile[st + 4 * (q >> 3) + (q & 3) + 16 * ((q >> 2) & 1)][b];
+    }
+    mom_store8<MP_F16>(xhT, nullptr, (size_t)b * Npad + p0 + s0, v);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_qf_w(const float* __restrict__ alphas,
+                                              const float* __restrict__ means,
+                                              const float* __restrict__ qd,
+                                              const float* __restrict__ l, int K,
+                                              _Float16* __restrict__ W16, float* __restrict__ kq,
+                                              float* __restrict__ isc) {
+  constexpr int D = 64, L = D * (D - 1) / 2;
+  __shared__ float Qs[64][65], P[64][65];
+  __shared__ float mus[64], Pmu[64], red[8];
+  const int k = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const size_t ct = (size_t)(k >> 4), c = (size_t)(k & 15);
+  auto wpos = [&](int ch, int g, int e) {
+    return (((ct * qf::kChunks + ch) * 4 + g) * 16 + c) * 8 + e;
+  };
+  if (k >= K) {  // padding component: zero coefficients
+    for (int s = t; s < qf::kChunks * 32; s += 256)
+      W16[wpos(s / 32, (s / 8) & 3, s & 7)] = (_Float16)0.f;
+    if (t == 0) {
+      kq[k] = 0.f;
+      isc[k] = 0.f;
+    }
+    return;
+  }
+  for (int e = t; e < D * D; e += 256) {
+    const int a = e / D, b = e % D;
+    float q = 0.f;
+    if (a == b)
+      q = expf(qd[(size_t)k * D + a]);
+    else if (a > b)
+      q = l[(size_t)k * L + a * (a - 1) / 2 + b];
+    Qs[a][b] = q;
+  }
+  if (t < D) mus[t] = means[(size_t)k * D + t];
+  __syncthreads();
+  // P = Q^T Q: thread t owns column b = t % 64 and rows a = t / 64 + 4j
+  {
+    const int b = t & 63, a0 = t >> 6;
+    float acc[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+    for (int r = 0; r < D; ++r) {
+      const float qb = Qs[r][b];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j] = fmaf(Qs[r][a0 + 4 * j], qb, acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) P[a0 + 4 * j][b] = acc[j];
+  }
+  __syncthreads();
+  if (t < D) {
+    float v = 0.f;
+    for (int b = 0; b < D; ++b) v = fmaf(P[t][b], mus[b], v);
+    Pmu[t] = v;
+  }
+  __syncthreads();
+  // largest coefficient magnitude, then the scaled FP16 operand
+  float cm = 0.f, mpm = 0.f;
+  for (int s = t; s < qf::kChunks * 32; s += 256) {
+    const int ch = s / 32, g = (s / 8) & 3, e = s & 7;
+    cm = fmaxf(cm, fabsf(qf::coef(4 * ch + (e >> 1), e & 1, g, P, Pmu)));
+  }
+  if (t < D) mpm = mus[t] * Pmu[t];
+  cm = wave_max(cm);
+  mpm = wave_sum(mpm);
+  __syncthreads();
+  if (lane == 0) red[wv] = cm;
+  if (t == 0) red[4] = mpm;
+  __syncthreads();
+  cm = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  int ew = 0;
+  if (cm > 0.f) {
+    int E;
+    frexpf(cm, &E);  // cm < 2^E: cm * 2^(14-E) in [2^13, 2^14)
+    ew = 14 - E;
+  }
+  const float sw = ldexpf(1.f, ew);
+  for (int s = t; s < qf::kChunks * 32; s += 256) {
+    const int ch = s / 32, g = (s / 8) & 3, e = s & 7;
+    W16[wpos(ch, g, e)] = (_Float16)(sw * qf::coef(4 * ch + (e >> 1), e & 1, g, P, Pmu));
+  }
+  if (t == 0) {
+    float kap = alphas[k];
+    for (int d = 0; d < D; ++d) kap += qd[(size_t)k * D + d];
+    kq[k] = kap - 0.5f * red[4];
+    isc[k] = ldexpf(1.f, -ew);  // 1 / sw
+  }
+}
+
+// One wave: 4 tiles of 16 points (64 points) x one pass of 32 components
+// (two 16-wide tiles); a block's 4 waves take 256 consecutive points and
+// share the coefficient chunks, staged through LDS 4 chunks at a time.
+struct QfCtx {
+  qf::h2 (&xr)[4][32];
+  f32x4 (&acc)[4][2];
+  _Float16 one;
+  qf::h8 (*wsh)[4][2][64];  // [buffer][chunk][tile][lane]
+  const _Float16* __restrict__ wsrc;  // pass chunk 0, tile 0
+  int lane, g;
+  int4 wreg[2];
+};
+
+// Stage S: issue the loads of stage S+1, compute chunks 4S..4S+3, store the
+// loaded stage into the other buffer, barrier.
+template <int S>
+DEX_DEV void qf_stage(QfCtx& c) {
+  constexpr int NS = qf::kChunks / 4;
+  const int t = threadIdx.x;
+  if constexpr (S + 1 < NS) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int piece = t + 256 * r;  // (chunk q, tile n, lane)
+      const int q = piece >> 7, n = (piece >> 6) & 1, ln = piece & 63;
+      c.wreg[r] = *reinterpret_cast<const int4*>(
+          c.wsrc + (((size_t)n * qf::kChunks + 4 * (S + 1) + q) * 64 + ln) * 8);
+    }
+  }
+  // coefficient operands of chunk q + 1 are read from LDS while chunk q is
+  // multiplied; a chunk's four feature sets and eight products interleave
+  qf::h8 w[2][2];
+  w[0][0] = c.wsh[S & 1][0][0][c.lane];
+  w[0][1] = c.wsh[S & 1][0][1][c.lane];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    constexpr int CH0 = 4 * S;
+    if (q + 1 < 4) {
+      w[(q + 1) & 1][0] = c.wsh[S & 1][q + 1][0][c.lane];
+      w[(q + 1) & 1][1] = c.wsh[S & 1][q + 1][1][c.lane];
+    }
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      qf::h8 z;
+      if (q == 0) z = qf::features<CH0 + 0>(c.xr[tt], c.one);
+      else if (q == 1) z = qf::features<CH0 + 1>(c.xr[tt], c.one);
+      else if (q == 2) z = qf::features<CH0 + 2>(c.xr[tt], c.one);
+      else z = qf::features<CH0 + 3>(c.xr[tt], c.one);
+      c.acc[tt][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(z, w[q & 1][0], c.acc[tt][0], 0, 0, 0);
+      c.acc[tt][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(z, w[q & 1][1], c.acc[tt][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // a feature set (4 packed muls)
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // its two products
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if constexpr (S + 1 < NS) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int piece = t + 256 * r;
+      const int q = piece >> 7, n = (piece >> 6) & 1, ln = piece & 63;
+      *reinterpret_cast<int4*>(&c.wsh[(S + 1) & 1][q][n][ln]) = c.wreg[r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int... S>
+DEX_DEV void qf_stages(QfCtx& c, std::integer_sequence<int, S...>) {
+  (qf_stage<S>(c), ...);
+}
+
+// Sum / max over the 16 lanes of a row (DPP: quad swaps, half-row and row
+// mirrors); every lane of the row gets the same bits.
+template <int CTRL>
+DEX_DEV float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+DEX_DEV float row_max16(float v) {
+  v = fmaxf(v, dpp<0xB1>(v));
+  v = fmaxf(v, dpp<0x4E>(v));
+  v = fmaxf(v, dpp<0x141>(v));
+  return fmaxf(v, dpp<0x140>(v));
+}
+DEX_DEV float row_sum16(float v) {
+  v = v + dpp<0xB1>(v);
+  v = v + dpp<0x4E>(v);
+  v = v + dpp<0x141>(v);
+  return v + dpp<0x140>(v);
+}
+
+__global__ void __launch_bounds__(256) k_gmm_fwd_qf(const _Float16* __restrict__ x16, int N,
+                                                    int Npad, int K,
+                                                    const _Float16* __restrict__ W16,
+                                                    const float* __restrict__ kq,
+                                                    const float* __restrict__ isc,
+                                                    const int* __restrict__ tile_exp, int64_t T,
+                                                    float* __restrict__ beta,
+                                                    float2* __restrict__ ml) {
+  __shared__ __attribute__((aligned(16))) qf::h8 wsh[2][4][2][64];
+  const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int64_t ntb = Npad / 256;
+  qf::h2 xr[4][32];
+  f32x4 acc[4][2];
+  QfCtx ctx{xr, acc, (_Float16)1.f, wsh, nullptr, lane, g, {}};
+  const int64_t u0 = split_lo(blockIdx.x, T, gridDim.x), u1 = split_lo(blockIdx.x + 1, T, gridDim.x);
+  for (int64_t u = u0; u < u1; ++u) {
+    const int pass = (int)(u / ntb);
+    const int pb = (int)(u - (int64_t)pass * ntb) * 256 + wv * 64;  // wave's first point
+    // the wave's 64 points are one prep tile: one scale 2^-ex, and "one" = 2^-ex
+    const int ex = tile_exp[pb >> 6];
+    ctx.one = (_Float16)ldexpf(1.f, -ex);
+    // x rows, rotated by 16g (8 halves per load)
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      const _Float16* row = x16 + (size_t)(pb + 16 * tt + c) * 64;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const qf::h8 v = *reinterpret_cast<const qf::h8*>(row + ((8 * j + 16 * g) & 63));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xr[tt][4 * j + e] = qf::h2{v[2 * e], v[2 * e + 1]};
+      }
+#pragma unroll
+      for (int n = 0; n < 2; ++n) acc[tt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    // coefficient chunks of this pass: stage 0 into buffer 0
+    ctx.wsrc = W16 + (size_t)(2 * pass) * qf::kChunks * 64 * 8;
+    __syncthreads();  // previous unit's readers are done with the buffers
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int piece = t + 256 * r;
+      const int q = piece >> 7, n = (piece >> 6) & 1, ln = piece & 63;
+      *reinterpret_cast<int4*>(&wsh[0][q][n][ln]) = *reinterpret_cast<const int4*>(
+          ctx.wsrc + (((size_t)n * qf::kChunks + q) * 64 + ln) * 8);
+    }
+    __syncthreads();
+    qf_stages(ctx, std::make_integer_sequence<int, qf::kChunks / 4>{});
+    // epilogue: beta = kappa' - isc 2^(2 ex) / 2 * product; log-sum-exp over the pass
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      const int k = pass * qf::kPass + 16 * n + c;
+      const float kk = kq[k], is = ldexpf(isc[k], 2 * ex);
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[tt][n][i] = kk - 0.5f * is * acc[tt][n][i];
+        __builtin_nontemporal_store(acc[tt][n],
+                                    reinterpret_cast<f32x4*>(beta + (size_t)k * Npad + pb + 16 * tt + 4 * g));
+      }
+    }
+    const bool v0 = pass * qf::kPass + c < K, v1 = pass * qf::kPass + 16 + c < K;
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      float M[4], Ls[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float b0 = v0 ? acc[tt][0][i] : -INFINITY, b1 = v1 ? acc[tt][1][i] : -INFINITY;
+        M[i] = row_max16(fmaxf(b0, b1));
+        const float e = (v0 ? __expf(b0 - M[i]) : 0.f) + (v1 ? __expf(b1 - M[i]) : 0.f);
+        Ls[i] = row_sum16(e);
+      }
+      if (c < 4) {
+        const float mm = c == 0 ? M[0] : c == 1 ? M[1] : c == 2 ? M[2] : M[3];
+        const float ll = c == 0 ? Ls[0] : c == 1 ? Ls[1] : c == 2 ? Ls[2] : Ls[3];
+        ml[(size_t)pass * Npad + pb + 16 * tt + 4 * g + c] = make_float2(mm, ll);
+      }
+    }
+  }
+}
+#endif
 }  // namespace dexk
 
 namespace dexi {
@@ -99,10 +418,9 @@ template <int DP>
 static void prep_dp(const GmmGeom& g, const float* x, const float* alphas, const float* means,
                     const float* qd, const float* l, void* xh, void* xl, void* xhT, void* xlT,
                     void* Qh, void* Ql, float* negc, float* kappa, hipStream_t st) {
-  hipLaunchKernelGGL((k_prep_x<P, DP>), dim3((unsigned)(g.Npad / 64)), dim3(256), 0, st, x, (int)g.N,
-                     (int)g.D, (int)g.Npad, (S*)xh, (S*)xl, (SM*)xhT, (SM*)xlT);
-  hipLaunchKernelGGL((k_prep_q<P, DP>), dim3((unsigned)g.K), dim3(256), 0, st, alphas, means, qd, l,
-                     (int)g.D, (S*)Qh, (S*)Ql, negc, kappa);
+  hipLaunchKernelGGL((k_prep<P, DP>), dim3((unsigned)(g.K + g.Npad / 64)), dim3(256), 0, st, x,
+                     (int)g.N, (int)g.D, (int)g.Npad, (int)g.K, alphas, means, qd, l, (S*)xh,
+                     (S*)xl, (SM*)xhT, (SM*)xlT, (S*)Qh, (S*)Ql, negc, kappa);
 }
 
 template <>
@@ -202,5 +520,34 @@ FlatSplit mfma_bwd<P>(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const
   if (g.DP == 32) return bwd_dp<32>(g, c, o, beta, f, ct, part, st);
   return bwd_dp<64>(g, c, o, beta, f, ct, part, st);
 }
+
+
+#if DEX_PREC == 1
+void qf_prep(const GmmGeom& g, const float* x, const float* alphas, const float* means,
+             const float* qd, const float* l, void* xhT, void* x16, int* tile_exp, void* W16,
+             float* kq, float* isc, hipStream_t st) {
+  const int ntiles = (int)(g.Npad / 64);
+  const int Kp = (int)((g.K + qf::kPass - 1) / qf::kPass * qf::kPass);
+  hipLaunchKernelGGL(k_qf_x, dim3((unsigned)ntiles), dim3(256), 0, st, x, (int)g.N, (int)g.Npad,
+                     (_Float16*)xhT, (_Float16*)x16, tile_exp);
+  hipLaunchKernelGGL(k_qf_w, dim3((unsigned)Kp), dim3(256), 0, st, alphas, means, qd, l, (int)g.K,
+                     (_Float16*)W16, kq, isc);
+}
+
+FlatSplit qf_fwd(const GmmGeom& g, const FwdCfg& c, const void* x16, const void* W16,
+                 const float* kq, const float* isc, const int* tile_exp, float* beta, float2* ml,
+                 hipStream_t st) {
+  static const int bpc = blocks_per_cu(k_gmm_fwd_qf);
+  FlatSplit sp{};
+  sp.sk = (int)((g.K + qf::kPass - 1) / qf::kPass);
+  sp.T = (int64_t)sp.sk * (g.Npad / 256);
+  const int per_cu = c.wps > 0 ? std::min(bpc, c.wps) : bpc;
+  sp.W = (int)std::min<int64_t>(sp.T, (int64_t)per_cu * num_cus());  // blocks
+  hipLaunchKernelGGL(k_gmm_fwd_qf, dim3((unsigned)sp.W), dim3(256), 0, st, (const _Float16*)x16,
+                     (int)g.N, (int)g.Npad, (int)g.K, (const _Float16*)W16, kq, isc, tile_exp, sp.T,
+                     beta, ml);
+  return sp;
+}
+#endif
 
 }  // namespace dexi

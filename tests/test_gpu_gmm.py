@@ -113,6 +113,18 @@ def test_bf16_shapes(dev, variant, tol, N, D, K):
     check(got, want, tol, f"bf16 v{variant} {N},{D},{K}")
 
 
+@pytest.mark.parametrize("scale", [2.0 ** 8, 2.0 ** -6])
+def test_feature_product_forward_under_rescaling(dev, scale):
+    """x and the means scaled by s, Q by 1/s: the same distribution of
+    Mahalanobis terms at large or small |x|, which moves the FP16 scale of the
+    feature-product forward (BF16 variant, D = 64)."""
+    g = workloads.gmm_inputs(3000, 64, 9, 21, np.float32)
+    g = workloads.GMMInputs(g.alphas, (g.means * scale).astype(np.float32),
+                            (g.qd - np.log(scale)).astype(np.float32),
+                            (g.l / scale).astype(np.float32), (g.x * scale).astype(np.float32))
+    check(run_gmm(g, 2, 1), oracle_gmm(g), TOL_BF16, f"bf16 rescaled by {scale}")
+
+
 @pytest.mark.parametrize("variant", [0, 1, 2])
 def test_every_tile_configuration(dev, variant):
     from paper_2104_05372_amd import dex
