@@ -182,33 +182,35 @@ __global__ void __launch_bounds__(256) k_merge_lse_quad(const float2* __restrict
 // Fixed-order compensated sum of each component's partial moment slots (the
 // waves that owned part of its group's points), written back into slot 0, so
 // the per-component finalize reads a single slot. One thread per element.
+// Slots of component k: on each XCD x the waves that owned part of its
+// group's steps, in slots x * SX + rank; summed in (x, rank) order.
 __global__ void __launch_bounds__(256) k_mom_reduce(float* __restrict__ part, int64_t E, int K,
-                                                    int gw, int64_t nsteps, int64_t Tu,
-                                                    int64_t Wu) {
+                                                    int gw, int64_t nsteps, int Wx, int SX) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= (int64_t)K * E) return;
   const int k = (int)(i / E);
-  const int S = split_slots((int64_t)(k / gw) * nsteps, nsteps, Tu, Wu);
+  const int64_t kg = k / gw, nkg = (K + gw - 1) / gw;
   const size_t stride = (size_t)K * E;
   float s = 0.f, err = 0.f;
-  int sp = 0;
-  for (; sp + 8 <= S; sp += 8) {
-    float v[8];
+  for (int x = 0; x < 8; ++x) {
+    const int64_t nsx = (x + 1) * nsteps / 8 - x * nsteps / 8;
+    if (nsx == 0) continue;
+    const int S = split_slots(kg * nsx, nsx, nkg * nsx, min<int64_t>(Wx, nkg * nsx));
+    const float* base = part + (size_t)x * SX * stride + i;
+    for (int sp = 0; sp < S; sp += 4) {
+      float v[4];  // loads of a batch issued together; static indices keep v in registers
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)(sp + u) * stride + i];
+      for (int u = 0; u < 4; ++u) v[u] = sp + u < S ? base[(size_t)(sp + u) * stride] : 0.f;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      float ns, ne;
-      two_sum<float>(s, v[u], ns, ne);
-      s = ns;
-      err += ne;
+      for (int u = 0; u < 4; ++u) {
+        if (sp + u < S) {
+          float ns, ne;
+          two_sum<float>(s, v[u], ns, ne);
+          s = ns;
+          err += ne;
+        }
+      }
     }
-  }
-  for (; sp < S; ++sp) {
-    float ns, ne;
-    two_sum<float>(s, part[(size_t)sp * stride + i], ns, ne);
-    s = ns;
-    err += ne;
   }
   part[i] = s + err;
 }
@@ -538,7 +540,7 @@ dex_status gmm_vjp(const dex_desc& d, int cfg, const GmmPtrs& in, const void* f,
   pr.end(1);
   const int64_t E = (int64_t)mom_slot(s.g.DP);
   hipLaunchKernelGGL(k_mom_reduce, dim3((unsigned)((s.g.K * E + 255) / 256)), dim3(256), 0, st,
-                     part, E, (int)s.g.K, sp.gw, sp.nsteps, sp.T, (int64_t)sp.W);
+                     part, E, (int)s.g.K, sp.gw, sp.nsteps, sp.W, (int)sp.T);
   hipLaunchKernelGGL(k_bwd_finalize_mom, dim3((unsigned)s.g.K), dim3(256), 0, st, (const float*)part,
                      (size_t)E, 1, (int)s.g.K,
                      (int)s.g.D, s.g.DP, s.g.N, (const float*)in.alphas, (const float*)in.means,

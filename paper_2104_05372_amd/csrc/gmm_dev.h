@@ -764,7 +764,8 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
   __shared__ __attribute__((aligned(16))) WT wsh[4][2 * NP][32];
 
   f32x4 sacc[GW][NBLK];
-  float uacc[GW][NB];
+  float uacc[GW][NB];  // FP32 and split forms: u by lane dot products
+  f32x4 uq[NB];        // FP16 form: u = x~^T W, 16 dims x 16 component columns per block
   float aacc[NP];
 #pragma unroll
   for (int gk = 0; gk < GW; ++gk) {
@@ -774,12 +775,15 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
     for (int ab = 0; ab < NB; ++ab) uacc[gk][ab] = 0.f;
   }
 #pragma unroll
+  for (int ab = 0; ab < NB; ++ab) uq[ab] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
   for (int pp = 0; pp < NP; ++pp) aacc[pp] = 0.f;
 
-  // Steps of 32 points; [pbeg, pend) is a multiple of 32 long. The x~^T rows,
-  // beta and f of the next step are loaded while the current one is computed
-  // (every load in bounds: the last step reloads itself, f is clamped to N-1,
-  // components past K to K-1).
+  // Steps of 32 points; [pbeg, pend) is a multiple of 32 long. The x~^T rows
+  // of the next step are loaded while the current one is computed; beta and f,
+  // which stream from HBM, kPW steps ahead (every load in bounds: steps past
+  // the end reload the last one, f is clamped to N-1, components past K to K-1).
+  constexpr int kPW = 3;
   auto load_x = [&](int t, V8(&xt)[NB][NS]) {
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb)
@@ -797,23 +801,24 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
           &beta[(size_t)min(kw + 2 * pp + half, K - 1) * Npad + p]);
   };
   V8 xt[NB][NS];
-  float bt[NP], ft;
+  float bt[kPW][NP], ft[kPW];
   if (pbeg < pend) {
     load_x(pbeg, xt);
-    load_w(pbeg, bt, ft);
+#pragma unroll
+    for (int r = 0; r < kPW; ++r) load_w(min(pbeg + 32 * r, pend - 32), bt[r], ft[r]);
   }
   for (int t0 = pbeg; t0 < pend; t0 += 32) {
     const int tn = t0 + 32 < pend ? t0 + 32 : t0;
     V8 xn[NB][NS];
     float bn[NP], fn;
     load_x(tn, xn);
-    load_w(tn, bn, fn);
+    load_w(min(t0 + 32 * kPW, pend - 32), bn, fn);
     __builtin_amdgcn_sched_barrier(0);
     const bool vown = t0 + j < N;
 #pragma unroll
     for (int pp = 0; pp < NP; ++pp) {
       const bool vk = kw + 2 * pp + half < K && (GW > 1 || half == 0);
-      const float w = vown && vk ? __expf(bt[pp] - ft) * ctv : 0.f;
+      const float w = vown && vk ? __expf(bt[0][pp] - ft[0]) * ctv : 0.f;
       aacc[pp] += w;
       wsh[wv][2 * pp + half][mom_pos(j)] = (WT)w;
     }
@@ -824,8 +829,16 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
     W8 wq[GW];
 #pragma unroll
     for (int gk = 0; gk < GW; ++gk) wq[gk] = *reinterpret_cast<const W8*>(&wsh[wv][gk][8 * g]);
+    W8 wcol{};  // FP16 form: lane (c, g) holds component c's weights of its 8 points
+    if constexpr (MP == MP_F16) {
+      if (c < GW) wcol = *reinterpret_cast<const W8*>(&wsh[wv][c][8 * g]);
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    if constexpr (MP == MP_F16) {
+#pragma unroll
+      for (int bb = 0; bb < NB; ++bb) uq[bb] = mom_mma1<MP>(xt[bb][0], wcol, uq[bb]);
+    }
 #pragma unroll
     for (int gk = 0; gk < GW; ++gk) {
       const int k = kw + gk;
@@ -843,15 +856,6 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
           uacc[gk][ab] += ut;
         } else if constexpr (MP == MP_F16) {
           sa[0] = xt[ab][0] * wq[gk];
-          float ut = uacc[gk][ab];
-#pragma unroll
-          for (int e = 0; e < 8; e += 2) {
-            typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-            const h2 xa{xt[ab][0][e], xt[ab][0][e + 1]};
-            const h2 wa{wq[gk][e], wq[gk][e + 1]};
-            ut = __builtin_amdgcn_fdot2(xa, wa, ut, false);
-          }
-          uacc[gk][ab] = ut;
         } else {
           float ut = 0.f;
 #pragma unroll
@@ -880,7 +884,7 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
 #pragma unroll
       for (int i = 0; i < NBLK; ++i) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, MP == MP_F16 ? 2 : 3, 0);
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -889,8 +893,14 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
 #pragma unroll
       for (int s = 0; s < NS; ++s) xt[bb][s] = xn[bb][s];
 #pragma unroll
-    for (int pp = 0; pp < NP; ++pp) bt[pp] = bn[pp];
-    ft = fn;
+    for (int r = 0; r + 1 < kPW; ++r) {
+#pragma unroll
+      for (int pp = 0; pp < NP; ++pp) bt[r][pp] = bt[r + 1][pp];
+      ft[r] = ft[r + 1];
+    }
+#pragma unroll
+    for (int pp = 0; pp < NP; ++pp) bt[kPW - 1][pp] = bn[pp];
+    ft[kPW - 1] = fn;
   }
 
   // A: lanes 0-31 hold component kw + 2pp, lanes 32-63 component kw + 2pp + 1
@@ -909,12 +919,21 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
     float* P = part + (size_t)k * pstride;
 #pragma unroll
     for (int q = 0; q < NBLK; ++q) *reinterpret_cast<f32x4*>(&P[q * 256 + lane * 4]) = sacc[gk][q];
+    if constexpr (MP == MP_F16) {
+      // uq[ab] lane (c, g): u of component kw + c, dims 16 ab + 4 g + i
+      if (c == gk) {
 #pragma unroll
-    for (int ab = 0; ab < NB; ++ab) {
-      float uv = uacc[gk][ab];
-      uv += xor_lane(uv, 16);
-      uv += xor_lane(uv, 32);
-      if (g == 0) P[NBLK * 256 + 16 * ab + c] = uv;
+        for (int ab = 0; ab < NB; ++ab)
+          *reinterpret_cast<f32x4*>(&P[NBLK * 256 + 16 * ab + 4 * g]) = uq[ab];
+      }
+    } else {
+#pragma unroll
+      for (int ab = 0; ab < NB; ++ab) {
+        float uv = uacc[gk][ab];
+        uv += xor_lane(uv, 16);
+        uv += xor_lane(uv, 32);
+        if (g == 0) P[NBLK * 256 + 16 * ab + c] = uv;
+      }
     }
     if (lane == 32 * (gk & 1)) P[NBLK * 256 + DP] = asum[gk >> 1];
   }

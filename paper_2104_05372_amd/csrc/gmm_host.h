@@ -27,11 +27,12 @@ struct BwdCfg {
 };
 
 // The single-instance forward and reverse kernels split their work evenly
-// over W waves (split_lo). Forward units are (group of nkq components,
-// 16-point tile), group-major; each group leaves one log-sum-exp partial per
+// over the waves of each XCD (split_lo). Forward units are (group of nkq
+// components, 16-point tile); each group leaves one log-sum-exp partial per
 // point (sk = number of groups). Reverse units are (group of gw components,
-// 32-point step), group-major, nsteps per group; each wave writes one moment
-// partial per group it touches.
+// 32-point step); XCD x owns the x-th eighth of the steps, W waves each, and
+// a wave writes one moment partial per group it touches, in the slots
+// x * T + rank (T = slots per XCD).
 struct FlatSplit {
   int64_t T;
   int W;
@@ -48,9 +49,11 @@ inline int64_t fwd_max_slots(int64_t K) { return (K + 1) / 2; }
 // beta rows: K rounded up to whole passes of 32 components (the padding rows
 // take the stores of the padding components of the last group or pass)
 inline int64_t beta_rows(int64_t K) { return (K + 31) / 32 * 32; }
-// Reverse partials per component: the launch keeps W <= (slots - 1) * groups.
+// Reverse partial slots per component over the 8 XCDs (a multiple of 8, at
+// least 2 per XCD); the launch keeps each XCD's waves within its share.
 inline int64_t bwd_max_slots(int64_t Npad, int64_t K) {
-  return std::max<int64_t>(2, std::min<int64_t>(Npad / 32, 9600 / K));
+  (void)Npad;
+  return std::max<int64_t>(16, 9600 / K / 8 * 8);
 }
 
 template <int PREC>

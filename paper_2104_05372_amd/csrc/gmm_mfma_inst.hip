@@ -35,61 +35,77 @@ __global__ void __launch_bounds__(256) k_prep(const float* __restrict__ x, int N
     prep_x_tile<PREC, DP>(x, N, D, Npad, (blockIdx.x - K) * 64, xh, xl, xhT, xlT);
 }
 
-// Both grid kernels split their work evenly over W waves (split_lo), so every
+// The grid kernels split their work evenly over the waves (split_lo), so every
 // wave does the same amount of work whatever N, K and the CU count are, and no
-// partly filled second wave of blocks trails the launch. Forward units are
-// (group of NKQ components, 16-point tile), group-major: a wave loads a
-// group's operands once and streams its tiles; its range covers at most a few
-// groups.
+// partly filled second wave of blocks trails the launch. Workgroups are
+// dispatched to the 8 XCDs round-robin, each XCD with its own L2: XCD x
+// (blocks b with b % 8 == x) takes the x-th eighth of the point tiles for all
+// component groups, so the x~ tiles it streams (1/8 of x~) stay in its L2
+// while every group reads them. Forward units on an XCD are (group of NKQ
+// components, 16-point tile), group-major: a wave loads a group's operands
+// once and streams its tiles; its range covers at most a few groups. The grid
+// is a multiple of 8 blocks.
 template <int DP, int PREC, int NKQ, int CK, int PD>
-__global__ void __launch_bounds__(256) k_gmm_fwd(MfmaOps ops, int Npad, int K, int64_t T, int W,
+__global__ void __launch_bounds__(256) k_gmm_fwd(MfmaOps ops, int Npad, int K, int ngroups,
                                                  float* __restrict__ beta,
                                                  float2* __restrict__ ml) {
   // wave index, made explicitly uniform so the split arithmetic and the loop
   // control stay in scalar registers
-  const int w = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (w >= W) return;
+  const int xcd = blockIdx.x & 7;
+  const int wl = (blockIdx.x >> 3) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int Wx = (gridDim.x >> 3) * 4;
   const int64_t ntiles = Npad / 16;
-  int64_t pos = split_lo(w, T, W);
-  const int64_t hi = split_lo(w + 1, T, W);
+  const int64_t t0 = xcd * ntiles / 8, nix = (xcd + 1) * ntiles / 8 - t0;
+  const int64_t Tx = (int64_t)ngroups * nix;
+  int64_t pos = split_lo(wl, Tx, Wx);
+  const int64_t hi = split_lo(wl + 1, Tx, Wx);
   while (pos < hi) {
-    const int64_t grp = pos / ntiles;
-    const int64_t ta = pos - grp * ntiles;
-    const int64_t tb = min<int64_t>(ntiles, ta + (hi - pos));
-    fwd_unit_kq<DP, PREC, NKQ, CK, PD>(ops, Npad, K, (int)grp * NKQ, (int)ta, (int)tb, beta,
-                                   ml + (size_t)grp * Npad);
+    const int64_t grp = pos / nix;
+    const int64_t ta = pos - grp * nix;
+    const int64_t tb = min<int64_t>(nix, ta + (hi - pos));
+    fwd_unit_kq<DP, PREC, NKQ, CK, PD>(ops, Npad, K, (int)grp * NKQ, (int)(t0 + ta),
+                                       (int)(t0 + tb), beta, ml + (size_t)grp * Npad);
     pos += tb - ta;
   }
 }
 
-// Reverse units are (group of GW components, 32-point step), group-major; for
-// each group it touches a wave writes one partial moment slot.
+// Reverse units are (group of GW components, 32-point step); XCD x takes the
+// x-th eighth of the steps for all groups (its slice of x~^T stays in its L2),
+// group-major on the XCD. For each group it touches a wave writes one partial
+// moment slot: slot x * SX + (rank of the wave among the XCD's waves on that
+// group). Only the first min(Wx, units of the XCD) waves of an XCD take part,
+// so each of them owns at least one unit and the ranks of a group's waves are
+// contiguous (no unwritten slot between them). Waves share no LDS and meet at
+// no barrier, so the others leave at once.
 template <int DP, int PREC, int GW>
-__global__ void __launch_bounds__(256) k_gmm_bwd(MfmaOps ops, int N, int Npad, int K, int64_t T,
-                                                 int W, const float* __restrict__ beta,
+__global__ void __launch_bounds__(256) k_gmm_bwd(MfmaOps ops, int N, int Npad, int K, int SX,
+                                                 const float* __restrict__ beta,
                                                  const float* __restrict__ f,
                                                  const float* __restrict__ ct,
                                                  float* __restrict__ part) {
   // wave index, made explicitly uniform so the split arithmetic and the loop
   // control stay in scalar registers
-  const int w = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (w >= W) return;
+  const int xcd = blockIdx.x & 7;
+  const int wl = (blockIdx.x >> 3) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const size_t E = mom_slot(DP);
-  const int64_t nsteps = Npad / 32;
-  int64_t pos = split_lo(w, T, W);
-  const int64_t hi = split_lo(w + 1, T, W);
+  const int64_t nsteps = Npad / 32, nkg = (K + GW - 1) / GW;
+  const int64_t s0x = xcd * nsteps / 8, nsx = (xcd + 1) * nsteps / 8 - s0x;
+  const int64_t Tx = nkg * nsx;
+  const int64_t Wx = min<int64_t>((gridDim.x >> 3) * 4, Tx);
+  if (wl >= Wx) return;
+  int64_t pos = split_lo(wl, Tx, Wx);
+  const int64_t hi = split_lo(wl + 1, Tx, Wx);
   while (pos < hi) {
-    const int64_t kg = pos / nsteps;
-    const int64_t s0 = pos - kg * nsteps;
-    const int64_t s1 = min<int64_t>(nsteps, s0 + (hi - pos));
-    const int slot = (int)(w - split_owner(kg * nsteps, T, W));
+    const int64_t kg = pos / nsx;
+    const int64_t s0 = pos - kg * nsx;
+    const int64_t s1 = min<int64_t>(nsx, s0 + (hi - pos));
+    const int slot = xcd * SX + (int)(wl - split_owner(kg * nsx, Tx, Wx));
     bwd_mom_unit<DP, MomOf<PREC>::MP, GW>(ops.xhT, ops.xlT, N, Npad, K, (int)kg * GW,
-                                          (int)(s0 * 32), (int)(s1 * 32), beta, f, ct[0],
-                                          part + (size_t)slot * K * E, E);
+                                          (int)((s0x + s0) * 32), (int)((s0x + s1) * 32), beta,
+                                          f, ct[0], part + (size_t)slot * K * E, E);
     pos += s1 - s0;
   }
 }
-
 
 #if DEX_PREC == 1
 // ---------------------------------------------------------------------------
@@ -336,14 +352,20 @@ __global__ void __launch_bounds__(256) k_gmm_fwd_qf(const _Float16* __restrict__
   __shared__ __attribute__((aligned(16))) qf::h8 wsh[2][4][2][64];
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  // XCD x (blocks b % 8 == x) takes the x-th eighth of the 256-point block
+  // tiles for all passes, so its x copies stay in its L2 across the passes;
+  // units on an XCD are pass-major. The grid is a multiple of 8 blocks.
   const int64_t ntb = Npad / 256;
+  const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3, Gx = gridDim.x >> 3;
+  const int64_t b0 = xcd * ntb / 8, nbx = (xcd + 1) * ntb / 8 - b0;
+  const int64_t Tx = (T / ntb) * nbx;
   qf::h2 xr[4][32];
   f32x4 acc[4][2];
   QfCtx ctx{xr, acc, (_Float16)1.f, wsh, nullptr, lane, g, {}};
-  const int64_t u0 = split_lo(blockIdx.x, T, gridDim.x), u1 = split_lo(blockIdx.x + 1, T, gridDim.x);
+  const int64_t u0 = split_lo(lb, Tx, Gx), u1 = split_lo(lb + 1, Tx, Gx);
   for (int64_t u = u0; u < u1; ++u) {
-    const int pass = (int)(u / ntb);
-    const int pb = (int)(u - (int64_t)pass * ntb) * 256 + wv * 64;  // wave's first point
+    const int pass = (int)(u / nbx);
+    const int pb = (int)(b0 + (u - (int64_t)pass * nbx)) * 256 + wv * 64;  // wave's first point
     // the wave's 64 points are one prep tile: one scale 2^-ex, and "one" = 2^-ex
     const int ex = tile_exp[pb >> 6];
     ctx.one = (_Float16)ldexpf(1.f, -ex);
@@ -460,9 +482,10 @@ static FlatSplit fwd_launch(const GmmGeom& g, const FwdCfg& c, const MfmaOps& o,
   FlatSplit sp{};
   sp.sk = (int)((g.K + NKQ - 1) / NKQ);
   sp.T = (int64_t)sp.sk * (g.Npad / 16);
-  sp.W = (int)std::min<int64_t>(sp.T, launch_waves(bpc, c.wps));
-  hipLaunchKernelGGL((k_gmm_fwd<DP, P, NKQ, CK, PD>), dim3((unsigned)((sp.W + 3) / 4)), dim3(256),
-                     0, st, o, (int)g.Npad, (int)g.K, sp.T, sp.W, beta, ml);
+  const int blocks = std::max(8, launch_waves(bpc, c.wps) / 4 / 8 * 8);
+  sp.W = 4 * blocks;
+  hipLaunchKernelGGL((k_gmm_fwd<DP, P, NKQ, CK, PD>), dim3((unsigned)blocks), dim3(256), 0, st, o,
+                     (int)g.Npad, (int)g.K, sp.sk, beta, ml);
   return sp;
 }
 
@@ -495,13 +518,21 @@ static FlatSplit bwd_launch(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o,
   sp.gw = GW;
   sp.nsteps = g.Npad / 32;
   const int64_t groups = (g.K + GW - 1) / GW;
-  sp.T = groups * sp.nsteps;
-  // at most bwd_max_slots partial slots per group: W <= (slots - 1) * groups
-  const int64_t wcap = (bwd_max_slots(g.Npad, g.K) - 1) * groups;
+  // waves per XCD: as many as resident, at most (slots per XCD - 1) per group,
+  // and no more than the units of the smallest XCD slice
+  const int64_t sx_cap = bwd_max_slots(g.Npad, g.K) / 8;
   static const int bpc = blocks_per_cu(k_gmm_bwd<DP, P, GW>);
-  sp.W = (int)std::min<int64_t>(std::min<int64_t>(sp.T, wcap), launch_waves(bpc, c.wps));
-  hipLaunchKernelGGL((k_gmm_bwd<DP, P, GW>), dim3((unsigned)((sp.W + 3) / 4)), dim3(256), 0, st, o,
-                     (int)g.N, (int)g.Npad, (int)g.K, sp.T, sp.W, beta, f, ct, part);
+  int64_t wx = launch_waves(bpc, c.wps) / 8 / 4 * 4;
+  wx = std::min<int64_t>(wx, (sx_cap - 1) * groups);
+  wx = std::min<int64_t>(wx, groups * (sp.nsteps / 8)) / 4 * 4;
+  wx = std::max<int64_t>(wx, 4);
+  sp.W = (int)wx;  // waves per XCD
+  // A group's waves on one XCD are fewer than wx / groups + 2, so SX slots
+  // suffice; SX <= sx_cap since wx <= (sx_cap - 1) * groups (the floor of 4
+  // waves only applies when groups < 4, i.e. K <= 12, where sx_cap >= 100).
+  sp.T = (wx + groups - 1) / groups + 1;  // slots per XCD (SX)
+  hipLaunchKernelGGL((k_gmm_bwd<DP, P, GW>), dim3((unsigned)(2 * wx)), dim3(256), 0, st, o,
+                     (int)g.N, (int)g.Npad, (int)g.K, (int)sp.T, beta, f, ct, part);
   return sp;
 }
 
@@ -542,7 +573,7 @@ FlatSplit qf_fwd(const GmmGeom& g, const FwdCfg& c, const void* x16, const void*
   sp.sk = (int)((g.K + qf::kPass - 1) / qf::kPass);
   sp.T = (int64_t)sp.sk * (g.Npad / 256);
   const int per_cu = c.wps > 0 ? std::min(bpc, c.wps) : bpc;
-  sp.W = (int)std::min<int64_t>(sp.T, (int64_t)per_cu * num_cus());  // blocks
+  sp.W = std::max(8, per_cu * num_cus() / 8 * 8);  // blocks, a multiple of 8
   hipLaunchKernelGGL(k_gmm_fwd_qf, dim3((unsigned)sp.W), dim3(256), 0, st, (const _Float16*)x16,
                      (int)g.N, (int)g.Npad, (int)g.K, (const _Float16*)W16, kq, isc, tile_exp, sp.T,
                      beta, ml);
