@@ -492,9 +492,15 @@ dex_status gmm_fwd(const dex_desc& d, int cfg, const GmmPtrs& in, void* F, void*
         pr.end(1);
       }
   }
-  const unsigned nq = (unsigned)(s.g.Npad / 64);
-  hipLaunchKernelGGL((k_merge_lse_quad<float>), dim3(nq), dim3(256), 0, st, ml, sp.sk,
-                     (int)s.g.N, (int)s.g.Npad, (float*)f, fpart);
+  // few partials per point: one thread per point; many: four
+  const bool quad = sp.sk > 16;
+  const unsigned nq = (unsigned)(s.g.Npad / (quad ? 64 : 256));
+  if (quad)
+    hipLaunchKernelGGL((k_merge_lse_quad<float>), dim3(nq), dim3(256), 0, st, ml, sp.sk,
+                       (int)s.g.N, (int)s.g.Npad, (float*)f, fpart);
+  else
+    hipLaunchKernelGGL((k_merge_lse<float>), dim3(nq), dim3(256), 0, st, ml, sp.sk, (int)s.g.N,
+                       (int)s.g.Npad, (float*)f, fpart);
   hipLaunchKernelGGL((k_finalize_F<float>), dim3(1), dim3(256), 0, st, fpart, (int)nq, al,
                      (int)s.g.K, s.g.N, (float*)F);
   return check_hip(hipGetLastError(), "gmm_fwd (MFMA)");

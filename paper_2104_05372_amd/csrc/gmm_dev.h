@@ -838,9 +838,34 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
     if constexpr (MP == MP_F16) {
 #pragma unroll
       for (int bb = 0; bb < NB; ++bb) uq[bb] = mom_mma1<MP>(xt[bb][0], wcol, uq[bb]);
+      // scaled rows of component gk + 1 are formed while component gk's
+      // products run (two buffers); components past K have zero weights, so
+      // their products add nothing and no branch is needed
+      V8 sa[2][NB];
+#pragma unroll
+      for (int ab = 0; ab < NB; ++ab) sa[0][ab] = xt[ab][0] * wq[0];
+#pragma unroll
+      for (int gk = 0; gk < GW; ++gk) {
+        if (gk + 1 < GW) {
+#pragma unroll
+          for (int ab = 0; ab < NB; ++ab) sa[(gk + 1) & 1][ab] = xt[ab][0] * wq[gk + 1];
+        }
+#pragma unroll
+        for (int ab = 0; ab < NB; ++ab) {
+          const int q0 = ab * (ab + 1) / 2;
+#pragma unroll
+          for (int bb = 0; bb <= ab; ++bb)
+            sacc[gk][q0 + bb] = mom_mma1<MP>(sa[gk & 1][ab], xt[bb][0], sacc[gk][q0 + bb]);
+        }
+#pragma unroll
+        for (int i = 0; i < NBLK; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+        }
+      }
     }
 #pragma unroll
-    for (int gk = 0; gk < GW; ++gk) {
+    for (int gk = 0; gk < (MP == MP_F16 ? 0 : GW); ++gk) {
       const int k = kw + gk;
       if (k >= K) break;
 #pragma unroll
@@ -854,9 +879,7 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
             ut = fmaf(xt[ab][0][e], wq[gk][e], ut);
           }
           uacc[gk][ab] += ut;
-        } else if constexpr (MP == MP_F16) {
-          sa[0] = xt[ab][0] * wq[gk];
-        } else {
+        } else if constexpr (MP == MP_F16X3) {
           float ut = 0.f;
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
@@ -884,7 +907,7 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
 #pragma unroll
       for (int i = 0; i < NBLK; ++i) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x002, MP == MP_F16 ? 2 : 3, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -948,10 +971,14 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
                               const float* __restrict__ l, float ctv, float* __restrict__ d_alphas,
                               float* __restrict__ d_means, float* __restrict__ d_qd,
                               float* __restrict__ d_l, int accumulate) {
-  __shared__ float C[64][65], Qs[64][65];
-  __shared__ float us[64], mus[64], bq[64], Ash;
+  // Called with 256 threads. C is symmetric; QT holds Q transposed (row
+  // stride 68 floats keeps 16-byte rows aligned for vector reads).
+  __shared__ __attribute__((aligned(16))) float C[64][65];
+  __shared__ __attribute__((aligned(16))) float QT[64][68];
+  __shared__ float us[64], mus[64], vq[64], bq[64], Ash;
   const int NB = DP / 16, NBLK = NB * (NB + 1) / 2;
   const int L = D * (D - 1) / 2;
+  const int t = threadIdx.x;
   // slots in a fixed order; the loads of 8 slots are issued together
   auto comp_sum = [&](size_t off) {
     float s = 0.f, err = 0.f;
@@ -984,12 +1011,12 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
   float pv[11], qv[16], av[4];
 #pragma unroll
   for (int i = 0; i < 11; ++i) {
-    const int e = threadIdx.x + 256 * i;
+    const int e = t + 256 * i;
     pv[i] = e < NE ? comp_sum((size_t)e) : 0.f;
   }
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    const int e = threadIdx.x + 256 * i;
+    const int e = t + 256 * i;
     const int a = e / D, b = e - (e / D) * D;
     float q = 0.f;
     if (e < D * D) {
@@ -1002,42 +1029,42 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int j = threadIdx.x + 256 * i;
+    const int j = t + 256 * i;
     av[i] = j < K ? alphas[j] : -INFINITY;
   }
-  const float mu_t = threadIdx.x < D ? means[(size_t)k * D + threadIdx.x] : 0.f;
-  __syncthreads();
+  const float mu_t = t < D ? means[(size_t)k * D + t] : 0.f;
+  // softmax normaliser of alpha (components past 1024 read in a second pass)
+  float am = fmaxf(fmaxf(av[0], av[1]), fmaxf(av[2], av[3]));
+  for (int j = t + 1024; j < K; j += 256) am = fmaxf(am, alphas[j]);
+  am = wave_max(am);
 #pragma unroll
   for (int i = 0; i < 11; ++i) {
-    const int e = threadIdx.x + 256 * i;
+    const int e = t + 256 * i;
     if (e < NE) Ps[e] = pv[i];
   }
+  // QT: rows and columns past D stay zero
+  for (int e = t; e < 64 * 68; e += 256) (&QT[0][0])[e] = 0.f;
+  if ((t & 63) == 0) red[t >> 6] = am;
+  if (t < D) mus[t] = mu_t;
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    const int e = threadIdx.x + 256 * i;
-    if (e < D * D) Qs[e / D][e % D] = qv[i];
+    const int e = t + 256 * i;
+    if (e < D * D) QT[e % D][e / D] = qv[i];
   }
-  if (threadIdx.x < D) mus[threadIdx.x] = mu_t;
-  for (int j = threadIdx.x + 1024; j < K; j += blockDim.x) av[3] = fmaxf(av[3], alphas[j]);
-  // softmax weight of alpha_k, by the whole block
-  float am = fmaxf(fmaxf(av[0], av[1]), fmaxf(av[2], av[3]));
-  am = wave_max(am);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = am;
-  __syncthreads();
-  am = red[0];
-  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) am = fmaxf(am, red[w]);
+  am = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
   float az = 0.f;
-  for (int j = threadIdx.x; j < K; j += blockDim.x) az += expf(alphas[j] - am);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) az += av[i] > -INFINITY ? expf(av[i] - am) : 0.f;
+  for (int j = t + 1024; j < K; j += 256) az += expf(alphas[j] - am);
   az = wave_sum(az);
+  if ((t & 63) == 0) red[4 + (t >> 6)] = az;
+  if (t < D) us[t] = Ps[NBLK * 256 + t];
+  if (t == 0) Ash = Ps[NBLK * 256 + DP];
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[4 + (threadIdx.x >> 6)] = az;
-  for (int e = threadIdx.x; e < D; e += blockDim.x) us[e] = Ps[NBLK * 256 + e];
-  if (threadIdx.x == 0) Ash = Ps[NBLK * 256 + DP];
-  __syncthreads();
-  az = 0.f;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) az += red[4 + w];
+  az = red[4] + red[5] + red[6] + red[7];
   const float A = Ash;
-  for (int e = threadIdx.x; e < NBLK * 256; e += blockDim.x) {
+  for (int e = t; e < NBLK * 256; e += 256) {
     const int q = e >> 8, ln = (e >> 2) & 63, i = e & 3;
     int ab = 0;
     while ((ab + 1) * (ab + 2) / 2 <= q) ++ab;
@@ -1048,48 +1075,67 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
     C[r][s] = v;
     C[s][r] = v;
   }
+  if (t < D) vq[t] = us[t] - A * mus[t];
   __syncthreads();
-  // M = Q C (Q lower triangular, so the sum may run over all cc < D): thread t
-  // owns column b = t % 64 and rows a = t / 64 + 4r; the 16 accumulators are
-  // independent and a wave reads each Q element as one broadcast. Called with
-  // 256 threads; rows and columns past D are computed and dropped.
+  // M = Q C: thread t owns column b = t % 64 and rows a = 16 (t / 64) + r; Q is
+  // lower triangular, so the sum runs over cc <= a < 16 (t / 64) + 16. The 16
+  // Q values of a step are 4 broadcast vector reads.
   {
-    const int b = threadIdx.x & 63, a0 = threadIdx.x >> 6;
+    const int b = t & 63, a0 = 16 * (t >> 6);
+    const int ce = min(D, a0 + 16);
     float m[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) m[r] = 0.f;
-    for (int cc = 0; cc < D; ++cc) {  // entries past D are not initialised
-      const float cv = C[cc][b];
+#pragma unroll 4
+    for (int cc = 0; cc < ce; ++cc) {
+      const float cv = b < D ? C[cc][b] : 0.f;
+      const f32x4* qrow = reinterpret_cast<const f32x4*>(&QT[cc][a0]);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) m[r] = fmaf(Qs[a0 + 4 * r][cc], cv, m[r]);
+      for (int r4 = 0; r4 < 4; ++r4) {
+        const f32x4 q = qrow[r4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) m[4 * r4 + i] = fmaf(q[i], cv, m[4 * r4 + i]);
+      }
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int a = a0 + 4 * r;
+      const int a = a0 + r;
       if (a >= D || b >= D || a < b) continue;
       if (a > b) {
         float* o = d_l + (size_t)k * L + a * (a - 1) / 2 + b;
         *o = accumulate ? *o - m[r] : -m[r];
       } else {
         float* o = d_qd + (size_t)k * D + a;
-        const float gq = A - Qs[a][a] * m[r];
+        const float gq = A - QT[a][a] * m[r];
         *o = accumulate ? *o + gq : gq;
       }
     }
   }
-  for (int a = threadIdx.x; a < D; a += blockDim.x) {
+  // bq = Q (u - A mu), then d_means = Q^T bq: four threads per row, the
+  // partial sums combined over the quad
+  {
+    const int a = t >> 2, r = t & 3;
     float v = 0.f;
-    for (int cc = 0; cc <= a; ++cc) v = fmaf(Qs[a][cc], us[cc] - A * mus[cc], v);
-    bq[a] = v;
+    if (a < D)
+      for (int cc = r; cc <= a; cc += 4) v = fmaf(QT[cc][a], vq[cc], v);
+    v += xor_lane(v, 1);
+    v += xor_lane(v, 2);
+    if (a < D && r == 0) bq[a] = v;
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < D; d += blockDim.x) {
+  {
+    const int d = t >> 2, r = t & 3;
     float gm = 0.f;
-    for (int a = d; a < D; ++a) gm = fmaf(Qs[a][d], bq[a], gm);
-    float* om = d_means + (size_t)k * D + d;
-    *om = accumulate ? *om + gm : gm;
+    if (d < D)
+      for (int a = d + r; a < D; a += 4) gm = fmaf(QT[d][a], bq[a], gm);
+    gm += xor_lane(gm, 1);
+    gm += xor_lane(gm, 2);
+    if (d < D && r == 0) {
+      float* om = d_means + (size_t)k * D + d;
+      *om = accumulate ? *om + gm : gm;
+    }
   }
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     const float ga = A - ctv * (float)N * (expf(alphas[k] - am) / az);
     d_alphas[k] = accumulate ? d_alphas[k] + ga : ga;
   }
@@ -1105,12 +1151,22 @@ DEX_DEV void merge_lse_block(const float2* __restrict__ ml, int Sk, int N, int N
   const int p = p0 + threadIdx.x;
   T v = 0;
   if (p < N) {
-    float M = -INFINITY;
-    for (int s = 0; s < Sk; ++s) M = fmaxf(M, ml[(size_t)s * Npad + p].x);
-    float L = 0.f;
-    for (int s = 0; s < Sk; ++s) {
-      const float2 e = ml[(size_t)s * Npad + p];
-      if (e.y > 0.f) L += e.y * __expf(e.x - M);
+    // partials in groups of 8, each group's loads issued together, folded in
+    // order (online log-sum-exp)
+    float M = -INFINITY, L = 0.f;
+    for (int s0 = 0; s0 < Sk; s0 += 8) {
+      float2 e[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        e[u] = s0 + u < Sk ? ml[(size_t)(s0 + u) * Npad + p] : make_float2(-INFINITY, 0.f);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (e[u].y == 0.f) continue;
+        const float d = e[u].x - M;
+        const float x = __expf(-fabsf(d));
+        L = d > 0.f ? fmaf(L, x, e[u].y) : fmaf(e[u].y, x, L);
+        M = fmaxf(M, e[u].x);
+      }
     }
     v = (T)(M + logf(L));
     f[p] = v;

@@ -168,8 +168,10 @@ __global__ void __launch_bounds__(256) k_qf_w(const float* __restrict__ alphas,
                                               _Float16* __restrict__ W16, float* __restrict__ kq,
                                               float* __restrict__ isc) {
   constexpr int D = 64, L = D * (D - 1) / 2;
-  __shared__ float Qs[64][65], P[64][65];
-  __shared__ float mus[64], Pmu[64], red[8];
+  // Qs: row stride 68 floats keeps 16-byte row pieces aligned for vector reads
+  __shared__ __attribute__((aligned(16))) float Qs[64][68];
+  __shared__ float P[64][65];
+  __shared__ float mus[64], Pmu[64], red[12];
   const int k = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const size_t ct = (size_t)(k >> 4), c = (size_t)(k & 15);
   auto wpos = [&](int ch, int g, int e) {
@@ -184,50 +186,86 @@ __global__ void __launch_bounds__(256) k_qf_w(const float* __restrict__ alphas,
     }
     return;
   }
-  for (int e = t; e < D * D; e += 256) {
+  // global loads first, issued together
+  float qv[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = t + 256 * i;
     const int a = e / D, b = e % D;
     float q = 0.f;
     if (a == b)
       q = expf(qd[(size_t)k * D + a]);
     else if (a > b)
       q = l[(size_t)k * L + a * (a - 1) / 2 + b];
-    Qs[a][b] = q;
+    qv[i] = q;
   }
-  if (t < D) mus[t] = means[(size_t)k * D + t];
+  const float mu_t = t < D ? means[(size_t)k * D + t] : 0.f;
+  const float qd_t = t < D ? qd[(size_t)k * D + t] : 0.f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = t + 256 * i;
+    Qs[e / D][e % D] = qv[i];
+  }
+  if (t < D) mus[t] = mu_t;
+  const float sqd = wave_sum(qd_t);  // sum of qd_k, complete in wave 0
   __syncthreads();
-  // P = Q^T Q: thread t owns column b = t % 64 and rows a = t / 64 + 4j
+  // P = Q^T Q: thread t owns column b = t % 64 and rows a = 16 (t / 64) + j;
+  // Q[r][a] = 0 for r < a, so the sum starts at r = 16 (t / 64). The 16
+  // Q values of a step are 4 broadcast vector reads.
   {
-    const int b = t & 63, a0 = t >> 6;
+    const int b = t & 63, a0 = 16 * wv;
     float acc[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) acc[j] = 0.f;
-    for (int r = 0; r < D; ++r) {
+#pragma unroll 4
+    for (int r = a0; r < D; ++r) {
       const float qb = Qs[r][b];
+      const f32x4* qrow = reinterpret_cast<const f32x4*>(&Qs[r][a0]);
 #pragma unroll
-      for (int j = 0; j < 16; ++j) acc[j] = fmaf(Qs[r][a0 + 4 * j], qb, acc[j]);
+      for (int j4 = 0; j4 < 4; ++j4) {
+        const f32x4 q = qrow[j4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[4 * j4 + i] = fmaf(q[i], qb, acc[4 * j4 + i]);
+      }
     }
 #pragma unroll
-    for (int j = 0; j < 16; ++j) P[a0 + 4 * j][b] = acc[j];
+    for (int j = 0; j < 16; ++j) P[a0 + j][b] = acc[j];
   }
   __syncthreads();
-  if (t < D) {
+  // P mu: four threads per row, combined over the quad
+  {
+    const int a = t >> 2, r = t & 3;
     float v = 0.f;
-    for (int b = 0; b < D; ++b) v = fmaf(P[t][b], mus[b], v);
-    Pmu[t] = v;
+#pragma unroll 4
+    for (int b = r; b < D; b += 4) v = fmaf(P[a][b], mus[b], v);
+    v += xor_lane(v, 1);
+    v += xor_lane(v, 2);
+    if (r == 0) Pmu[a] = v;
   }
   __syncthreads();
-  // largest coefficient magnitude, then the scaled FP16 operand
-  float cm = 0.f, mpm = 0.f;
-  for (int s = t; s < qf::kChunks * 32; s += 256) {
-    const int ch = s / 32, g = (s / 8) & 3, e = s & 7;
-    cm = fmaxf(cm, fabsf(qf::coef(4 * ch + (e >> 1), e & 1, g, P, Pmu)));
+  // coefficients (kept in registers), their largest magnitude, then the scaled
+  // FP16 operand
+  constexpr int kPer = qf::kChunks * 32 / 256;  // 8.5 -> 9 per thread
+  float cv[kPer + 1];
+  float cm = 0.f;
+#pragma unroll
+  for (int i = 0; i <= kPer; ++i) {
+    const int s = t + 256 * i;
+    float v = 0.f;
+    if (s < qf::kChunks * 32) {
+      const int ch = s / 32, g = (s / 8) & 3, e = s & 7;
+      v = qf::coef(4 * ch + (e >> 1), e & 1, g, P, Pmu);
+    }
+    cv[i] = v;
+    cm = fmaxf(cm, fabsf(v));
   }
-  if (t < D) mpm = mus[t] * Pmu[t];
+  const float mpm = wave_sum(t < D ? mus[t] * Pmu[t] : 0.f);
   cm = wave_max(cm);
-  mpm = wave_sum(mpm);
-  __syncthreads();
   if (lane == 0) red[wv] = cm;
-  if (t == 0) red[4] = mpm;
+  if (t == 0) {
+    red[4] = mpm;
+    red[5] = sqd;
+  }
   __syncthreads();
   cm = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
   int ew = 0;
@@ -237,89 +275,18 @@ __global__ void __launch_bounds__(256) k_qf_w(const float* __restrict__ alphas,
     ew = 14 - E;
   }
   const float sw = ldexpf(1.f, ew);
-  for (int s = t; s < qf::kChunks * 32; s += 256) {
-    const int ch = s / 32, g = (s / 8) & 3, e = s & 7;
-    W16[wpos(ch, g, e)] = (_Float16)(sw * qf::coef(4 * ch + (e >> 1), e & 1, g, P, Pmu));
+#pragma unroll
+  for (int i = 0; i <= kPer; ++i) {
+    const int s = t + 256 * i;
+    if (s < qf::kChunks * 32) {
+      const int ch = s / 32, g = (s / 8) & 3, e = s & 7;
+      W16[wpos(ch, g, e)] = (_Float16)(sw * cv[i]);
+    }
   }
   if (t == 0) {
-    float kap = alphas[k];
-    for (int d = 0; d < D; ++d) kap += qd[(size_t)k * D + d];
-    kq[k] = kap - 0.5f * red[4];
+    kq[k] = alphas[k] + red[5] - 0.5f * red[4];
     isc[k] = ldexpf(1.f, -ew);  // 1 / sw
   }
-}
-
-// One wave: 4 tiles of 16 points (64 points) x one pass of 32 components
-// (two 16-wide tiles); a block's 4 waves take 256 consecutive points and
-// share the coefficient chunks, staged through LDS 4 chunks at a time.
-struct QfCtx {
-  qf::h2 (&xr)[4][32];
-  f32x4 (&acc)[4][2];
-  _Float16 one;
-  qf::h8 (*wsh)[4][2][64];  // [buffer][chunk][tile][lane]
-  const _Float16* __restrict__ wsrc;  // pass chunk 0, tile 0
-  int lane, g;
-  int4 wreg[2];
-};
-
-// Stage S: issue the loads of stage S+1, compute chunks 4S..4S+3, store the
-// loaded stage into the other buffer, barrier.
-template <int S>
-DEX_DEV void qf_stage(QfCtx& c) {
-  constexpr int NS = qf::kChunks / 4;
-  const int t = threadIdx.x;
-  if constexpr (S + 1 < NS) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int piece = t + 256 * r;  // (chunk q, tile n, lane)
-      const int q = piece >> 7, n = (piece >> 6) & 1, ln = piece & 63;
-      c.wreg[r] = *reinterpret_cast<const int4*>(
-          c.wsrc + (((size_t)n * qf::kChunks + 4 * (S + 1) + q) * 64 + ln) * 8);
-    }
-  }
-  // coefficient operands of chunk q + 1 are read from LDS while chunk q is
-  // multiplied; a chunk's four feature sets and eight products interleave
-  qf::h8 w[2][2];
-  w[0][0] = c.wsh[S & 1][0][0][c.lane];
-  w[0][1] = c.wsh[S & 1][0][1][c.lane];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    constexpr int CH0 = 4 * S;
-    if (q + 1 < 4) {
-      w[(q + 1) & 1][0] = c.wsh[S & 1][q + 1][0][c.lane];
-      w[(q + 1) & 1][1] = c.wsh[S & 1][q + 1][1][c.lane];
-    }
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-      qf::h8 z;
-      if (q == 0) z = qf::features<CH0 + 0>(c.xr[tt], c.one);
-      else if (q == 1) z = qf::features<CH0 + 1>(c.xr[tt], c.one);
-      else if (q == 2) z = qf::features<CH0 + 2>(c.xr[tt], c.one);
-      else z = qf::features<CH0 + 3>(c.xr[tt], c.one);
-      c.acc[tt][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(z, w[q & 1][0], c.acc[tt][0], 0, 0, 0);
-      c.acc[tt][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(z, w[q & 1][1], c.acc[tt][1], 0, 0, 0);
-    }
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-      __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // a feature set (4 packed muls)
-      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // its two products
-    }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  if constexpr (S + 1 < NS) {
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int piece = t + 256 * r;
-      const int q = piece >> 7, n = (piece >> 6) & 1, ln = piece & 63;
-      *reinterpret_cast<int4*>(&c.wsh[(S + 1) & 1][q][n][ln]) = c.wreg[r];
-    }
-  }
-  __syncthreads();
-}
-
-template <int... S>
-DEX_DEV void qf_stages(QfCtx& c, std::integer_sequence<int, S...>) {
-  (qf_stage<S>(c), ...);
 }
 
 // Sum / max over the 16 lanes of a row (DPP: quad swaps, half-row and row
@@ -341,89 +308,127 @@ DEX_DEV float row_sum16(float v) {
   return v + dpp<0x140>(v);
 }
 
-__global__ void __launch_bounds__(256) k_gmm_fwd_qf(const _Float16* __restrict__ x16, int N,
-                                                    int Npad, int K,
-                                                    const _Float16* __restrict__ W16,
-                                                    const float* __restrict__ kq,
-                                                    const float* __restrict__ isc,
-                                                    const int* __restrict__ tile_exp, int64_t T,
-                                                    float* __restrict__ beta,
-                                                    float2* __restrict__ ml) {
-  __shared__ __attribute__((aligned(16))) qf::h8 wsh[2][4][2][64];
+// One block per CU, 8 waves (2 per SIMD). A unit is (pass of 32 components,
+// 64-point tile); XCD x takes the x-th eighth of the tiles for all passes
+// (its x copies stay in its L2), pass-major, and a block a contiguous range
+// of the XCD's units. The block holds the coefficient operand of its current
+// pass in LDS (68 chunks x 2 component tiles x 64 lanes x 16 B = 136 KiB), so
+// the waves run their units with no barrier; the block meets only to load the
+// next pass. A wave computes its tile as 4 point tiles x 2 component tiles:
+// per chunk 4 feature sets (4 packed multiplies each) and 8 products.
+constexpr int kQfWaves = 8;
+
+template <int CH>
+DEX_DEV void qf_chunk(const qf::h2 (&xr)[4][32], _Float16 one, const qf::h8 (&w)[2],
+                      f32x4 (&acc)[4][2]) {
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) {
+    const qf::h8 z = qf::features<CH>(xr[tt], one);
+    acc[tt][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(z, w[0], acc[tt][0], 0, 0, 0);
+    acc[tt][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(z, w[1], acc[tt][1], 0, 0, 0);
+  }
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) {
+    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // a feature set (4 packed muls)
+    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // its two products
+  }
+}
+
+// chunks CH.. with the operands of chunk CH + 1 read from LDS during chunk CH
+template <int... CH>
+DEX_DEV void qf_chunks(const qf::h2 (&xr)[4][32], _Float16 one, const qf::h8 (*wsh)[2][64],
+                       int lane, f32x4 (&acc)[4][2], std::integer_sequence<int, CH...>) {
+  qf::h8 w[2][2];
+  w[0][0] = wsh[0][0][lane];
+  w[0][1] = wsh[0][1][lane];
+  (
+      [&] {
+        if constexpr (CH + 1 < qf::kChunks) {
+          w[(CH + 1) & 1][0] = wsh[CH + 1][0][lane];
+          w[(CH + 1) & 1][1] = wsh[CH + 1][1][lane];
+        }
+        qf_chunk<CH>(xr, one, w[CH & 1], acc);
+        __builtin_amdgcn_sched_barrier(0);
+      }(),
+      ...);
+}
+
+__global__ void __launch_bounds__(64 * kQfWaves) k_gmm_fwd_qf(
+    const _Float16* __restrict__ x16, int N, int Npad, int K, const _Float16* __restrict__ W16,
+    const float* __restrict__ kq, const float* __restrict__ isc, const int* __restrict__ tile_exp,
+    int npass, float* __restrict__ beta, float2* __restrict__ ml) {
+  __shared__ __attribute__((aligned(16))) qf::h8 wsh[qf::kChunks][2][64];
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-  // XCD x (blocks b % 8 == x) takes the x-th eighth of the 256-point block
-  // tiles for all passes, so its x copies stay in its L2 across the passes;
-  // units on an XCD are pass-major. The grid is a multiple of 8 blocks.
-  const int64_t ntb = Npad / 256;
+  const int64_t ntiles = Npad / 64;
   const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3, Gx = gridDim.x >> 3;
-  const int64_t b0 = xcd * ntb / 8, nbx = (xcd + 1) * ntb / 8 - b0;
-  const int64_t Tx = (T / ntb) * nbx;
+  const int64_t t0 = xcd * ntiles / 8, ntx = (xcd + 1) * ntiles / 8 - t0;
+  const int64_t Tx = (int64_t)npass * ntx;
+  const int64_t ua = split_lo(lb, Tx, Gx), ub = split_lo(lb + 1, Tx, Gx);
   qf::h2 xr[4][32];
   f32x4 acc[4][2];
-  QfCtx ctx{xr, acc, (_Float16)1.f, wsh, nullptr, lane, g, {}};
-  const int64_t u0 = split_lo(lb, Tx, Gx), u1 = split_lo(lb + 1, Tx, Gx);
-  for (int64_t u = u0; u < u1; ++u) {
-    const int pass = (int)(u / nbx);
-    const int pb = (int)(b0 + (u - (int64_t)pass * nbx)) * 256 + wv * 64;  // wave's first point
-    // the wave's 64 points are one prep tile: one scale 2^-ex, and "one" = 2^-ex
-    const int ex = tile_exp[pb >> 6];
-    ctx.one = (_Float16)ldexpf(1.f, -ex);
-    // x rows, rotated by 16g (8 halves per load)
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-      const _Float16* row = x16 + (size_t)(pb + 16 * tt + c) * 64;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const qf::h8 v = *reinterpret_cast<const qf::h8*>(row + ((8 * j + 16 * g) & 63));
-#pragma unroll
-        for (int e = 0; e < 4; ++e) xr[tt][4 * j + e] = qf::h2{v[2 * e], v[2 * e + 1]};
-      }
-#pragma unroll
-      for (int n = 0; n < 2; ++n) acc[tt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-    // coefficient chunks of this pass: stage 0 into buffer 0
-    ctx.wsrc = W16 + (size_t)(2 * pass) * qf::kChunks * 64 * 8;
-    __syncthreads();  // previous unit's readers are done with the buffers
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int piece = t + 256 * r;
-      const int q = piece >> 7, n = (piece >> 6) & 1, ln = piece & 63;
-      *reinterpret_cast<int4*>(&wsh[0][q][n][ln]) = *reinterpret_cast<const int4*>(
-          ctx.wsrc + (((size_t)n * qf::kChunks + q) * 64 + ln) * 8);
+  for (int64_t cur = ua; cur < ub;) {
+    const int pass = (int)(cur / ntx);
+    const int64_t seg = min<int64_t>(ub, (int64_t)(pass + 1) * ntx);
+    // the pass's coefficient operand into LDS (component tiles 2 pass, 2 pass + 1)
+    __syncthreads();
+    for (int e = t; e < qf::kChunks * 2 * 64; e += 64 * kQfWaves) {
+      const int ch = e >> 7, n = (e >> 6) & 1, ln = e & 63;
+      wsh[ch][n][ln] = *reinterpret_cast<const qf::h8*>(
+          W16 + ((((size_t)(2 * pass + n) * qf::kChunks + ch) * 64 + ln) * 8));
     }
     __syncthreads();
-    qf_stages(ctx, std::make_integer_sequence<int, qf::kChunks / 4>{});
-    // epilogue: beta = kappa' - isc 2^(2 ex) / 2 * product; log-sum-exp over the pass
-#pragma unroll
-    for (int n = 0; n < 2; ++n) {
-      const int k = pass * qf::kPass + 16 * n + c;
-      const float kk = kq[k], is = ldexpf(isc[k], 2 * ex);
+    for (int64_t u = cur + wv; u < seg; u += kQfWaves) {
+      const int pb = (int)(t0 + (u - (int64_t)pass * ntx)) * 64;  // the tile's first point
+      // one prep tile: one scale 2^-ex, and "one" = 2^-ex
+      const int ex = tile_exp[pb >> 6];
+      const _Float16 one = (_Float16)ldexpf(1.f, -ex);
+      // x rows, rotated by 16g (8 halves per load)
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
+        const _Float16* row = x16 + (size_t)(pb + 16 * tt + c) * 64;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) acc[tt][n][i] = kk - 0.5f * is * acc[tt][n][i];
-        __builtin_nontemporal_store(acc[tt][n],
-                                    reinterpret_cast<f32x4*>(beta + (size_t)k * Npad + pb + 16 * tt + 4 * g));
+        for (int j = 0; j < 8; ++j) {
+          const qf::h8 v = *reinterpret_cast<const qf::h8*>(row + ((8 * j + 16 * g) & 63));
+#pragma unroll
+          for (int e = 0; e < 4; ++e) xr[tt][4 * j + e] = qf::h2{v[2 * e], v[2 * e + 1]};
+        }
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[tt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      qf_chunks(xr, one, wsh, lane, acc, std::make_integer_sequence<int, qf::kChunks>{});
+      // epilogue: beta = kappa' - isc 2^(2 ex) / 2 * product; log-sum-exp over the pass
+#pragma unroll
+      for (int n = 0; n < 2; ++n) {
+        const int k = pass * qf::kPass + 16 * n + c;
+        const float kk = kq[k], is = ldexpf(isc[k], 2 * ex);
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[tt][n][i] = kk - 0.5f * is * acc[tt][n][i];
+          __builtin_nontemporal_store(
+              acc[tt][n], reinterpret_cast<f32x4*>(beta + (size_t)k * Npad + pb + 16 * tt + 4 * g));
+        }
+      }
+      const bool v0 = pass * qf::kPass + c < K, v1 = pass * qf::kPass + 16 + c < K;
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) {
+        float M[4], Ls[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float b0 = v0 ? acc[tt][0][i] : -INFINITY, b1 = v1 ? acc[tt][1][i] : -INFINITY;
+          M[i] = row_max16(fmaxf(b0, b1));
+          const float e = (v0 ? __expf(b0 - M[i]) : 0.f) + (v1 ? __expf(b1 - M[i]) : 0.f);
+          Ls[i] = row_sum16(e);
+        }
+        if (c < 4) {
+          const float mm = c == 0 ? M[0] : c == 1 ? M[1] : c == 2 ? M[2] : M[3];
+          const float ll = c == 0 ? Ls[0] : c == 1 ? Ls[1] : c == 2 ? Ls[2] : Ls[3];
+          ml[(size_t)pass * Npad + pb + 16 * tt + 4 * g + c] = make_float2(mm, ll);
+        }
       }
     }
-    const bool v0 = pass * qf::kPass + c < K, v1 = pass * qf::kPass + 16 + c < K;
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-      float M[4], Ls[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float b0 = v0 ? acc[tt][0][i] : -INFINITY, b1 = v1 ? acc[tt][1][i] : -INFINITY;
-        M[i] = row_max16(fmaxf(b0, b1));
-        const float e = (v0 ? __expf(b0 - M[i]) : 0.f) + (v1 ? __expf(b1 - M[i]) : 0.f);
-        Ls[i] = row_sum16(e);
-      }
-      if (c < 4) {
-        const float mm = c == 0 ? M[0] : c == 1 ? M[1] : c == 2 ? M[2] : M[3];
-        const float ll = c == 0 ? Ls[0] : c == 1 ? Ls[1] : c == 2 ? Ls[2] : Ls[3];
-        ml[(size_t)pass * Npad + pb + 16 * tt + 4 * g + c] = make_float2(mm, ll);
-      }
-    }
+    cur = seg;
   }
 }
 #endif
@@ -568,15 +573,14 @@ void qf_prep(const GmmGeom& g, const float* x, const float* alphas, const float*
 FlatSplit qf_fwd(const GmmGeom& g, const FwdCfg& c, const void* x16, const void* W16,
                  const float* kq, const float* isc, const int* tile_exp, float* beta, float2* ml,
                  hipStream_t st) {
-  static const int bpc = blocks_per_cu(k_gmm_fwd_qf);
+  (void)c;
   FlatSplit sp{};
   sp.sk = (int)((g.K + qf::kPass - 1) / qf::kPass);
-  sp.T = (int64_t)sp.sk * (g.Npad / 256);
-  const int per_cu = c.wps > 0 ? std::min(bpc, c.wps) : bpc;
-  sp.W = std::max(8, per_cu * num_cus() / 8 * 8);  // blocks, a multiple of 8
-  hipLaunchKernelGGL(k_gmm_fwd_qf, dim3((unsigned)sp.W), dim3(256), 0, st, (const _Float16*)x16,
-                     (int)g.N, (int)g.Npad, (int)g.K, (const _Float16*)W16, kq, isc, tile_exp, sp.T,
-                     beta, ml);
+  sp.T = (int64_t)sp.sk * (g.Npad / 64);
+  sp.W = std::max(8, num_cus() / 8 * 8);  // one block per CU, a multiple of 8
+  hipLaunchKernelGGL(k_gmm_fwd_qf, dim3((unsigned)sp.W), dim3(64 * kQfWaves), 0, st,
+                     (const _Float16*)x16, (int)g.N, (int)g.Npad, (int)g.K, (const _Float16*)W16,
+                     kq, isc, tile_exp, sp.sk, beta, ml);
   return sp;
 }
 #endif
