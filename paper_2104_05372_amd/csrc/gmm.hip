@@ -285,8 +285,9 @@ Shape shape_of(const dex_desc& d) {
 const FwdCfg kFwdBF[] = {{0, 0, 0}, {4, 0, 1}, {4, 0, 2}, {2, 0, 1},
                          {2, 0, 2}, {4, 1, 2}, {2, 2, 2}, {0, 1, 0}};
 const FwdCfg kFwdF32[] = {{2, 0, 1}, {2, 0, 2}, {2, 2, 1}, {2, 1, 2}};
-// reverse candidates: (components per wave, waves per SIMD (0: all resident))
-const BwdCfg kBwdBF[] = {{2, 0}, {1, 0}, {4, 0}, {2, 2}, {1, 2}, {1, 3}, {2, 1}, {4, 1}};
+// reverse candidates: (components per wave, waves per SIMD (0: all resident),
+// FP16 form: scaled rows double-buffered (default) or not)
+const BwdCfg kBwdBF[] = {{2, 0}, {3, 0}, {4, 0}, {2, 2}, {3, 2}, {4, 0, 0}, {2, 1}, {4, 1}};
 const BwdCfg kBwdF32[] = {{2, 0}, {1, 0}, {4, 0}, {2, 2}, {1, 2}};
 constexpr int kValuS = 16;
 

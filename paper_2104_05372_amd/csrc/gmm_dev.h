@@ -745,7 +745,7 @@ __host__ __device__ inline size_t mom_slot(int DP) {
 // weights, the B operand the unscaled row. The weights of a step are computed
 // two components at a time (lanes 0-31 one component, 32-63 the next) and
 // exchanged through LDS in the same point order (FP16 for the FP16 moments).
-template <int DP, int MP, int GW>
+template <int DP, int MP, int GW, bool DB = true>
 DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad, int K, int kw,
                           int pbeg, int pend, const float* __restrict__ beta,
                           const float* __restrict__ f, float ctv, float* __restrict__ part,
@@ -783,7 +783,7 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
   // of the next step are loaded while the current one is computed; beta and f,
   // which stream from HBM, kPW steps ahead (every load in bounds: steps past
   // the end reload the last one, f is clamped to N-1, components past K to K-1).
-  constexpr int kPW = 3;
+  constexpr int kPW = DB ? 3 : 1;
   auto load_x = [&](int t, V8(&xt)[NB][NS]) {
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb)
@@ -809,9 +809,15 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
   }
   for (int t0 = pbeg; t0 < pend; t0 += 32) {
     const int tn = t0 + 32 < pend ? t0 + 32 : t0;
-    V8 xn[NB][NS];
+    // DB: the next step's x~^T rows are loaded into registers during this
+    // step; otherwise this step's rows are loaded now (the other wave on the
+    // SIMD covers the wait)
+    V8 xn[DB ? NB : 1][NS];
     float bn[NP], fn;
-    load_x(tn, xn);
+    if constexpr (DB)
+      load_x(tn, xn);
+    else if (t0 != pbeg)
+      load_x(t0, xt);
     load_w(min(t0 + 32 * kPW, pend - 32), bn, fn);
     __builtin_amdgcn_sched_barrier(0);
     const bool vown = t0 + j < N;
@@ -826,9 +832,13 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     typedef WT W8 __attribute__((ext_vector_type(8)));
-    W8 wq[GW];
+    // (the lean FP16 form reads each component's weights where it uses them)
+    constexpr bool kWq = DB || MP != MP_F16;
+    W8 wq[kWq ? GW : 1];
+    if constexpr (kWq) {
 #pragma unroll
-    for (int gk = 0; gk < GW; ++gk) wq[gk] = *reinterpret_cast<const W8*>(&wsh[wv][gk][8 * g]);
+      for (int gk = 0; gk < GW; ++gk) wq[gk] = *reinterpret_cast<const W8*>(&wsh[wv][gk][8 * g]);
+    }
     W8 wcol{};  // FP16 form: lane (c, g) holds component c's weights of its 8 points
     if constexpr (MP == MP_F16) {
       if (c < GW) wcol = *reinterpret_cast<const W8*>(&wsh[wv][c][8 * g]);
@@ -838,24 +848,33 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
     if constexpr (MP == MP_F16) {
 #pragma unroll
       for (int bb = 0; bb < NB; ++bb) uq[bb] = mom_mma1<MP>(xt[bb][0], wcol, uq[bb]);
-      // scaled rows of component gk + 1 are formed while component gk's
-      // products run (two buffers); components past K have zero weights, so
-      // their products add nothing and no branch is needed
-      V8 sa[2][NB];
+      // DB: scaled rows of component gk + 1 are formed while component gk's
+      // products run (two buffers); otherwise each row block is scaled just
+      // before its products (fewer registers: more waves per SIMD hide the
+      // dependency). Components past K have zero weights, so their products
+      // add nothing and no branch is needed.
+      V8 sa[DB ? 2 : 1][NB];
+      if constexpr (DB) {
 #pragma unroll
-      for (int ab = 0; ab < NB; ++ab) sa[0][ab] = xt[ab][0] * wq[0];
+        for (int ab = 0; ab < NB; ++ab) sa[0][ab] = xt[ab][0] * wq[0];
+      }
 #pragma unroll
       for (int gk = 0; gk < GW; ++gk) {
-        if (gk + 1 < GW) {
+        if constexpr (DB) {
+          if (gk + 1 < GW) {
 #pragma unroll
-          for (int ab = 0; ab < NB; ++ab) sa[(gk + 1) & 1][ab] = xt[ab][0] * wq[gk + 1];
+            for (int ab = 0; ab < NB; ++ab) sa[(gk + 1) & 1][ab] = xt[ab][0] * wq[gk + 1];
+          }
         }
 #pragma unroll
         for (int ab = 0; ab < NB; ++ab) {
           const int q0 = ab * (ab + 1) / 2;
+          if constexpr (!DB)
+            sa[0][ab] = xt[ab][0] * *reinterpret_cast<const W8*>(&wsh[wv][gk][8 * g]);
 #pragma unroll
           for (int bb = 0; bb <= ab; ++bb)
-            sacc[gk][q0 + bb] = mom_mma1<MP>(sa[gk & 1][ab], xt[bb][0], sacc[gk][q0 + bb]);
+            sacc[gk][q0 + bb] =
+                mom_mma1<MP>(sa[DB ? (gk & 1) : 0][ab], xt[bb][0], sacc[gk][q0 + bb]);
         }
 #pragma unroll
         for (int i = 0; i < NBLK; ++i) {
@@ -911,10 +930,12 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
       }
     }
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (DB) {
 #pragma unroll
-    for (int bb = 0; bb < NB; ++bb)
+      for (int bb = 0; bb < NB; ++bb)
 #pragma unroll
-      for (int s = 0; s < NS; ++s) xt[bb][s] = xn[bb][s];
+        for (int s = 0; s < NS; ++s) xt[bb][s] = xn[bb][s];
+    }
 #pragma unroll
     for (int r = 0; r + 1 < kPW; ++r) {
 #pragma unroll
@@ -1009,23 +1030,50 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
   // so the block waits for memory once instead of once per phase.
   const int NE = NBLK * 256 + DP + 1;
   float pv[11], qv[16], av[4];
+  if (S == 1) {  // one slot (already reduced): plain loads, issued together
 #pragma unroll
-  for (int i = 0; i < 11; ++i) {
-    const int e = t + 256 * i;
-    pv[i] = e < NE ? comp_sum((size_t)e) : 0.f;
-  }
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int e = t + 256 * i;
-    const int a = e / D, b = e - (e / D) * D;
-    float q = 0.f;
-    if (e < D * D) {
-      if (a == b)
-        q = expf(qd[(size_t)k * D + a]);
-      else if (a > b)
-        q = l[(size_t)k * L + a * (a - 1) / 2 + b];
+    for (int i = 0; i < 11; ++i) {
+      const int e = t + 256 * i;
+      pv[i] = e < NE ? part[e] : 0.f;
     }
-    qv[i] = q;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 11; ++i) {
+      const int e = t + 256 * i;
+      pv[i] = e < NE ? comp_sum((size_t)e) : 0.f;
+    }
+  }
+  {
+    // element e = t + 256 i of Q (row-major D x D): (a, b) advanced
+    // incrementally, no division per element. Both candidate values are loaded
+    // (at clamped, valid addresses) and the diagonal exp is always evaluated,
+    // so the selection is branch-free and the 32 loads are in flight together.
+    const int q256 = 256 / D, r256 = 256 - q256 * D;
+    int a = t / D, b = t - (t / D) * D;
+    // with D = 1 there is no strict lower part (L = 0, l may be empty): the
+    // unused load then reads qd instead
+    const float* lsrc = L > 0 ? l + (size_t)k * L : qd + (size_t)k * D;
+    float dv[16], lv[16];
+    int sel[16];  // 0: zero, 1: diagonal, 2: strict lower
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int e = t + 256 * i;
+      const bool in = e < D * D;
+      sel[i] = !in ? 0 : a == b ? 1 : a > b ? 2 : 0;
+      dv[i] = qd[(size_t)k * D + min(a, D - 1)];
+      lv[i] = lsrc[sel[i] == 2 ? a * (a - 1) / 2 + b : 0];
+      a += q256;
+      b += r256;
+      if (b >= D) {
+        b -= D;
+        ++a;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const float ev = expf(dv[i]);
+      qv[i] = sel[i] == 1 ? ev : sel[i] == 2 ? lv[i] : 0.f;
+    }
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -1042,8 +1090,9 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
     const int e = t + 256 * i;
     if (e < NE) Ps[e] = pv[i];
   }
-  // QT: rows and columns past D stay zero
+  // QT and C: rows and columns past D stay zero
   for (int e = t; e < 64 * 68; e += 256) (&QT[0][0])[e] = 0.f;
+  for (int e = t; e < 64 * 65; e += 256) (&C[0][0])[e] = 0.f;
   if ((t & 63) == 0) red[t >> 6] = am;
   if (t < D) mus[t] = mu_t;
   __syncthreads();
@@ -1064,50 +1113,65 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
   __syncthreads();
   az = red[4] + red[5] + red[6] + red[7];
   const float A = Ash;
-  for (int e = t; e < NBLK * 256; e += 256) {
-    const int q = e >> 8, ln = (e >> 2) & 63, i = e & 3;
-    int ab = 0;
-    while ((ab + 1) * (ab + 2) / 2 <= q) ++ab;
-    const int bb = q - ab * (ab + 1) / 2;
-    const int r = 16 * bb + (ln & 15), s = 16 * ab + 4 * (ln >> 4) + i;
-    if (r >= D || s >= D || r > s) continue;
-    const float v = Ps[e] - us[r] * mus[s] - mus[r] * us[s] + A * mus[r] * mus[s];
-    C[r][s] = v;
-    C[s][r] = v;
+  {
+    // C = S - u mu^T - mu u^T + A mu mu^T over the stored lower blocks: the
+    // thread's entry of block q = (ab, bb) is pv[q] (element t of the block),
+    // at row r = 16 bb + (t/4 % 16) and column s = 16 ab + 4 (t/64) + t % 4
+    const int rl = (t >> 2) & 15, sl = 4 * (t >> 6) + (t & 3);
+    float ur[4], mr[4], usv[4], msv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      ur[j] = us[16 * j + rl];
+      mr[j] = mus[16 * j + rl];
+      usv[j] = us[16 * j + sl];
+      msv[j] = mus[16 * j + sl];
+    }
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      const int ab = q < 1 ? 0 : q < 3 ? 1 : q < 6 ? 2 : 3;
+      const int bb = q - ab * (ab + 1) / 2;
+      const int r = 16 * bb + rl, s2 = 16 * ab + sl;
+      if (q >= NBLK || r >= D || s2 >= D || r > s2) continue;
+      const float v = pv[q] - ur[bb] * msv[ab] - mr[bb] * usv[ab] + A * mr[bb] * msv[ab];
+      C[r][s2] = v;
+      C[s2][r] = v;
+    }
   }
   if (t < D) vq[t] = us[t] - A * mus[t];
   __syncthreads();
-  // M = Q C: thread t owns column b = t % 64 and rows a = 16 (t / 64) + r; Q is
-  // lower triangular, so the sum runs over cc <= a < 16 (t / 64) + 16. The 16
-  // Q values of a step are 4 broadcast vector reads.
+  // M = Q C on the matrix cores (FP32 products, FP32 accumulation): wave w
+  // computes rows 16w..16w+15 as four 16x16 tiles; Q is lower triangular, so
+  // the contraction runs over cc < 16w + 16, four at a time. Lane 16g + c
+  // supplies A = Q[16w + c][cc + g] and B = C[cc + g][16n + c], and holds
+  // M[16w + 4g + i][16n + c]. Entries past D are zero in QT and C.
   {
-    const int b = t & 63, a0 = 16 * (t >> 6);
-    const int ce = min(D, a0 + 16);
-    float m[16];
+    const int w = t >> 6, lane = t & 63, c = lane & 15, g = lane >> 4;
+    const int ce = min(DP, 16 * w + 16);
+    f32x4 mt[4];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) m[r] = 0.f;
+    for (int n = 0; n < 4; ++n) mt[n] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
-    for (int cc = 0; cc < ce; ++cc) {
-      const float cv = b < D ? C[cc][b] : 0.f;
-      const f32x4* qrow = reinterpret_cast<const f32x4*>(&QT[cc][a0]);
+    for (int cc = 0; cc < ce; cc += 4) {
+      const float qa = QT[cc + g][16 * w + c];
 #pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) {
-        const f32x4 q = qrow[r4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) m[4 * r4 + i] = fmaf(q[i], cv, m[4 * r4 + i]);
-      }
+      for (int n = 0; n < 4; ++n)
+        mt[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa, C[cc + g][16 * n + c], mt[n], 0, 0, 0);
     }
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int a = a0 + r;
-      if (a >= D || b >= D || a < b) continue;
-      if (a > b) {
-        float* o = d_l + (size_t)k * L + a * (a - 1) / 2 + b;
-        *o = accumulate ? *o - m[r] : -m[r];
-      } else {
-        float* o = d_qd + (size_t)k * D + a;
-        const float gq = A - QT[a][a] * m[r];
-        *o = accumulate ? *o + gq : gq;
+    for (int n = 0; n < 4; ++n) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int a = 16 * w + 4 * g + i, b = 16 * n + c;
+        if (a >= D || b >= D || a < b) continue;
+        const float mv = mt[n][i];
+        if (a > b) {
+          float* o = d_l + (size_t)k * L + a * (a - 1) / 2 + b;
+          *o = accumulate ? *o - mv : -mv;
+        } else {
+          float* o = d_qd + (size_t)k * D + a;
+          const float gq = A - QT[a][a] * mv;
+          *o = accumulate ? *o + gq : gq;
+        }
       }
     }
   }

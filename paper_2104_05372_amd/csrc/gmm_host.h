@@ -24,6 +24,7 @@ struct FwdCfg {
 };
 struct BwdCfg {
   int gw, wps;  // components per wave, waves per SIMD
+  int db = 1;   // FP16 form: scaled rows double-buffered (more registers)
 };
 
 // The single-instance forward and reverse kernels split their work evenly

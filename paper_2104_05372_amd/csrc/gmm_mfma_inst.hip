@@ -77,8 +77,9 @@ __global__ void __launch_bounds__(256) k_gmm_fwd(MfmaOps ops, int Npad, int K, i
 // so each of them owns at least one unit and the ranks of a group's waves are
 // contiguous (no unwritten slot between them). Waves share no LDS and meet at
 // no barrier, so the others leave at once.
-template <int DP, int PREC, int GW>
-__global__ void __launch_bounds__(256) k_gmm_bwd(MfmaOps ops, int N, int Npad, int K, int SX,
+template <int DP, int PREC, int GW, bool DB>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DB ? 1 : 2)))
+k_gmm_bwd(MfmaOps ops, int N, int Npad, int K, int SX,
                                                  const float* __restrict__ beta,
                                                  const float* __restrict__ f,
                                                  const float* __restrict__ ct,
@@ -100,7 +101,7 @@ __global__ void __launch_bounds__(256) k_gmm_bwd(MfmaOps ops, int N, int Npad, i
     const int64_t s0 = pos - kg * nsx;
     const int64_t s1 = min<int64_t>(nsx, s0 + (hi - pos));
     const int slot = xcd * SX + (int)(wl - split_owner(kg * nsx, Tx, Wx));
-    bwd_mom_unit<DP, MomOf<PREC>::MP, GW>(ops.xhT, ops.xlT, N, Npad, K, (int)kg * GW,
+    bwd_mom_unit<DP, MomOf<PREC>::MP, GW, DB>(ops.xhT, ops.xlT, N, Npad, K, (int)kg * GW,
                                           (int)((s0x + s0) * 32), (int)((s0x + s1) * 32), beta,
                                           f, ct[0], part + (size_t)slot * K * E, E);
     pos += s1 - s0;
@@ -109,19 +110,21 @@ __global__ void __launch_bounds__(256) k_gmm_bwd(MfmaOps ops, int N, int Npad, i
 
 #if DEX_PREC == 1
 // ---------------------------------------------------------------------------
-// Feature-product forward (see gmm_qf.h). k_qf_x: per 64-point tile, x~^T for
-// the reverse pass and the scaled FP16 copy of x with its exponent. k_qf_w:
-// one block per component k < Kp: P = Q^T Q, the coefficient operand, kappa'
-// and the rescale factor.
-__global__ void __launch_bounds__(256) k_qf_x(const float* __restrict__ x, int N, int Npad,
-                                              _Float16* __restrict__ xhT,
-                                              _Float16* __restrict__ x16,
-                                              int* __restrict__ tile_exp) {
+// Feature-product forward (see gmm_qf.h). qf_x_tile: per 64-point tile, x~^T
+// for the reverse pass and the scaled FP16 copy of x with its exponent.
+// qf_w_comp: per component k < Kp, P = Q^T Q, the coefficient operand, kappa'
+// and the rescale factor. LDS of the two parts (they share one buffer):
+constexpr size_t kQfXLds = 64 * 65 * 4 + 16;
+constexpr size_t kQfWLds = 64 * 68 * 4 + 64 * 65 * 4 + (64 + 64 + 12) * 4;
+
+DEX_DEV void qf_x_tile(int tix, char* smem, const float* __restrict__ x, int N, int Npad,
+                       _Float16* __restrict__ xhT, _Float16* __restrict__ x16,
+                       int* __restrict__ tile_exp) {
   // x~^T for the reverse pass, and x scaled by the tile's 2^-ex (|x| 2^-ex <
   // 2^7) in FP16, row-major, for the feature products
-  __shared__ float tile[64][65];
-  __shared__ float red[4];
-  const int p0 = blockIdx.x * 64, t = threadIdx.x;
+  float(*tile)[65] = reinterpret_cast<float(*)[65]>(smem);
+  float* red = reinterpret_cast<float*>(smem + 64 * 65 * 4);
+  const int p0 = tix * 64, t = threadIdx.x;
   float mx = 0.f;
   for (int e = t; e < 64 * 64; e += 256) {
     const int pp = e >> 6, b = e & 63, p = p0 + pp;
@@ -140,7 +143,7 @@ __global__ void __launch_bounds__(256) k_qf_x(const float* __restrict__ x, int N
     frexpf(mx, &E);  // mx < 2^E
     ex = max(-6, E - 7);
   }
-  if (t == 0) tile_exp[blockIdx.x] = ex;
+  if (t == 0) tile_exp[tix] = ex;
   const float sx = ldexpf(1.f, -ex);
   for (int e = t; e < 8 * 64; e += 256) {
     const int pp = e >> 3, b0 = 8 * (e & 7);
@@ -161,18 +164,18 @@ __global__ void __launch_bounds__(256) k_qf_x(const float* __restrict__ x, int N
   }
 }
 
-__global__ void __launch_bounds__(256) k_qf_w(const float* __restrict__ alphas,
-                                              const float* __restrict__ means,
-                                              const float* __restrict__ qd,
-                                              const float* __restrict__ l, int K,
-                                              _Float16* __restrict__ W16, float* __restrict__ kq,
-                                              float* __restrict__ isc) {
+DEX_DEV void qf_w_comp(int k, char* smem, const float* __restrict__ alphas,
+                       const float* __restrict__ means, const float* __restrict__ qd,
+                       const float* __restrict__ l, int K, _Float16* __restrict__ W16,
+                       float* __restrict__ kq, float* __restrict__ isc) {
   constexpr int D = 64, L = D * (D - 1) / 2;
   // Qs: row stride 68 floats keeps 16-byte row pieces aligned for vector reads
-  __shared__ __attribute__((aligned(16))) float Qs[64][68];
-  __shared__ float P[64][65];
-  __shared__ float mus[64], Pmu[64], red[12];
-  const int k = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  float(*Qs)[68] = reinterpret_cast<float(*)[68]>(smem);
+  float(*P)[65] = reinterpret_cast<float(*)[65]>(smem + 64 * 68 * 4);
+  float* mus = reinterpret_cast<float*>(smem + 64 * 68 * 4 + 64 * 65 * 4);
+  float* Pmu = mus + 64;
+  float* red = Pmu + 64;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const size_t ct = (size_t)(k >> 4), c = (size_t)(k & 15);
   auto wpos = [&](int ch, int g, int e) {
     return (((ct * qf::kChunks + ch) * 4 + g) * 16 + c) * 8 + e;
@@ -187,17 +190,22 @@ __global__ void __launch_bounds__(256) k_qf_w(const float* __restrict__ alphas,
     return;
   }
   // global loads first, issued together
-  float qv[16];
+  // branch-free (both loads issued at valid addresses), so all 32 loads are
+  // in flight together
+  float qv[16], dv[16], lv[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int e = t + 256 * i;
     const int a = e / D, b = e % D;
-    float q = 0.f;
-    if (a == b)
-      q = expf(qd[(size_t)k * D + a]);
-    else if (a > b)
-      q = l[(size_t)k * L + a * (a - 1) / 2 + b];
-    qv[i] = q;
+    dv[i] = qd[(size_t)k * D + a];
+    lv[i] = l[(size_t)k * L + (a > b ? a * (a - 1) / 2 + b : 0)];
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = t + 256 * i;
+    const int a = e / D, b = e % D;
+    const float ev = expf(dv[i]);
+    qv[i] = a == b ? ev : a > b ? lv[i] : 0.f;
   }
   const float mu_t = t < D ? means[(size_t)k * D + t] : 0.f;
   const float qd_t = t < D ? qd[(size_t)k * D + t] : 0.f;
@@ -287,6 +295,26 @@ __global__ void __launch_bounds__(256) k_qf_w(const float* __restrict__ alphas,
     kq[k] = alphas[k] + red[5] - 0.5f * red[4];
     isc[k] = ldexpf(1.f, -ew);  // 1 / sw
   }
+}
+
+// One launch for both parts of the preparation: blocks [0, Kp) build the
+// coefficient operand of one component each (latency-bound), the others one
+// 64-point x tile each (bandwidth-bound), so the two overlap.
+__global__ void __launch_bounds__(256) k_qf_prep(const float* __restrict__ x, int N, int Npad,
+                                                 _Float16* __restrict__ xhT,
+                                                 _Float16* __restrict__ x16,
+                                                 int* __restrict__ tile_exp,
+                                                 const float* __restrict__ alphas,
+                                                 const float* __restrict__ means,
+                                                 const float* __restrict__ qd,
+                                                 const float* __restrict__ l, int K, int Kp,
+                                                 _Float16* __restrict__ W16,
+                                                 float* __restrict__ kq, float* __restrict__ isc) {
+  __shared__ __attribute__((aligned(16))) char smem[kQfWLds > kQfXLds ? kQfWLds : kQfXLds];
+  if ((int)blockIdx.x < Kp)
+    qf_w_comp(blockIdx.x, smem, alphas, means, qd, l, K, W16, kq, isc);
+  else
+    qf_x_tile(blockIdx.x - Kp, smem, x, N, Npad, xhT, x16, tile_exp);
 }
 
 // Sum / max over the 16 lanes of a row (DPP: quad swaps, half-row and row
@@ -516,7 +544,7 @@ FlatSplit mfma_fwd<P>(const GmmGeom& g, const FwdCfg& c, const MfmaOps& o, float
   return fwd_dp<64>(g, c, o, beta, ml, st);
 }
 
-template <int DP, int GW>
+template <int DP, int GW, bool DB>
 static FlatSplit bwd_launch(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const float* beta,
                             const float* f, const float* ct, float* part, hipStream_t st) {
   FlatSplit sp{};
@@ -526,7 +554,7 @@ static FlatSplit bwd_launch(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o,
   // waves per XCD: as many as resident, at most (slots per XCD - 1) per group,
   // and no more than the units of the smallest XCD slice
   const int64_t sx_cap = bwd_max_slots(g.Npad, g.K) / 8;
-  static const int bpc = blocks_per_cu(k_gmm_bwd<DP, P, GW>);
+  static const int bpc = blocks_per_cu(k_gmm_bwd<DP, P, GW, DB>);
   int64_t wx = launch_waves(bpc, c.wps) / 8 / 4 * 4;
   wx = std::min<int64_t>(wx, (sx_cap - 1) * groups);
   wx = std::min<int64_t>(wx, groups * (sp.nsteps / 8)) / 4 * 4;
@@ -536,7 +564,7 @@ static FlatSplit bwd_launch(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o,
   // suffice; SX <= sx_cap since wx <= (sx_cap - 1) * groups (the floor of 4
   // waves only applies when groups < 4, i.e. K <= 12, where sx_cap >= 100).
   sp.T = (wx + groups - 1) / groups + 1;  // slots per XCD (SX)
-  hipLaunchKernelGGL((k_gmm_bwd<DP, P, GW>), dim3((unsigned)(2 * wx)), dim3(256), 0, st, o,
+  hipLaunchKernelGGL((k_gmm_bwd<DP, P, GW, DB>), dim3((unsigned)(2 * wx)), dim3(256), 0, st, o,
                      (int)g.N, (int)g.Npad, (int)g.K, (int)sp.T, beta, f, ct, part);
   return sp;
 }
@@ -544,9 +572,11 @@ static FlatSplit bwd_launch(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o,
 template <int DP>
 static FlatSplit bwd_dp(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const float* beta,
                         const float* f, const float* ct, float* part, hipStream_t st) {
-  if (c.gw == 4) return bwd_launch<DP, 4>(g, c, o, beta, f, ct, part, st);
-  if (c.gw == 2) return bwd_launch<DP, 2>(g, c, o, beta, f, ct, part, st);
-  return bwd_launch<DP, 1>(g, c, o, beta, f, ct, part, st);
+  if (c.gw == 4 && !c.db) return bwd_launch<DP, 4, false>(g, c, o, beta, f, ct, part, st);
+  if (c.gw == 4) return bwd_launch<DP, 4, true>(g, c, o, beta, f, ct, part, st);
+  if (c.gw == 3) return bwd_launch<DP, 3, true>(g, c, o, beta, f, ct, part, st);
+  if (c.gw == 2) return bwd_launch<DP, 2, true>(g, c, o, beta, f, ct, part, st);
+  return bwd_launch<DP, 1, true>(g, c, o, beta, f, ct, part, st);
 }
 
 template <>
@@ -564,10 +594,9 @@ void qf_prep(const GmmGeom& g, const float* x, const float* alphas, const float*
              float* kq, float* isc, hipStream_t st) {
   const int ntiles = (int)(g.Npad / 64);
   const int Kp = (int)((g.K + qf::kPass - 1) / qf::kPass * qf::kPass);
-  hipLaunchKernelGGL(k_qf_x, dim3((unsigned)ntiles), dim3(256), 0, st, x, (int)g.N, (int)g.Npad,
-                     (_Float16*)xhT, (_Float16*)x16, tile_exp);
-  hipLaunchKernelGGL(k_qf_w, dim3((unsigned)Kp), dim3(256), 0, st, alphas, means, qd, l, (int)g.K,
-                     (_Float16*)W16, kq, isc);
+  hipLaunchKernelGGL(k_qf_prep, dim3((unsigned)(Kp + ntiles)), dim3(256), 0, st, x, (int)g.N,
+                     (int)g.Npad, (_Float16*)xhT, (_Float16*)x16, tile_exp, alphas, means, qd, l,
+                     (int)g.K, Kp, (_Float16*)W16, kq, isc);
 }
 
 FlatSplit qf_fwd(const GmmGeom& g, const FwdCfg& c, const void* x16, const void* W16,
