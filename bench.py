@@ -31,7 +31,7 @@ METRIC = "GMM grad evals/s (N=1e5,D=64,K=200) + bwd/fwd ratio + HBM/MFMA rooflin
 PEAK = {"bf16": 2500.0, "fp32": 157.3, "hbm": 8000.0}  # TFLOP/s, TFLOP/s, GB/s
 KERNEL_SOURCES = {
     "gmm_vjp": ["gmm_dev.h", "gmm_mfma_inst.hip", "gmm_host.h"],
-    "gmm_fwd": ["gmm_dev.h", "gmm_mfma_inst.hip", "gmm_host.h"],
+    "gmm_fwd": ["gmm_dev.h", "gmm_mfma_inst.hip", "gmm_host.h", "gmm_qf.h"],
 }
 
 
