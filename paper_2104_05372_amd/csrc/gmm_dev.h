@@ -779,11 +779,14 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
 #pragma unroll
   for (int pp = 0; pp < NP; ++pp) aacc[pp] = 0.f;
 
-  // Steps of 32 points; [pbeg, pend) is a multiple of 32 long. The x~^T rows
-  // of the next step are loaded while the current one is computed; beta and f,
-  // which stream from HBM, kPW steps ahead (every load in bounds: steps past
-  // the end reload the last one, f is clamped to N-1, components past K to K-1).
-  constexpr int kPW = DB ? 3 : 1;
+  // Steps of 32 points; [pbeg, pend) is a multiple of 32 long. The loop runs
+  // two steps per iteration with two register sets, so nothing is copied
+  // between steps: DB loads the next step's x~^T rows into the other set while
+  // the current one is computed (otherwise a step loads its own rows, and the
+  // other wave on the SIMD covers the wait); beta and f, which stream from HBM,
+  // are loaded two steps ahead into the slot just consumed. Every load is in
+  // bounds: steps past the end reload the last one, f is clamped to N-1,
+  // components past K to K-1.
   auto load_x = [&](int t, V8(&xt)[NB][NS]) {
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb)
@@ -800,34 +803,21 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
       bt[pp] = __builtin_nontemporal_load(
           &beta[(size_t)min(kw + 2 * pp + half, K - 1) * Npad + p]);
   };
-  V8 xt[NB][NS];
-  float bt[kPW][NP], ft[kPW];
-  if (pbeg < pend) {
-    load_x(pbeg, xt);
-#pragma unroll
-    for (int r = 0; r < kPW; ++r) load_w(min(pbeg + 32 * r, pend - 32), bt[r], ft[r]);
-  }
-  for (int t0 = pbeg; t0 < pend; t0 += 32) {
-    const int tn = t0 + 32 < pend ? t0 + 32 : t0;
-    // DB: the next step's x~^T rows are loaded into registers during this
-    // step; otherwise this step's rows are loaded now (the other wave on the
-    // SIMD covers the wait)
-    V8 xn[DB ? NB : 1][NS];
-    float bn[NP], fn;
+  auto step = [&](int t0, V8(&xt)[NB][NS], V8(&xn)[NB][NS], float(&bc)[NP], float& fc) {
     if constexpr (DB)
-      load_x(tn, xn);
-    else if (t0 != pbeg)
+      load_x(t0 + 32 < pend ? t0 + 32 : t0, xn);
+    else
       load_x(t0, xt);
-    load_w(min(t0 + 32 * kPW, pend - 32), bn, fn);
     __builtin_amdgcn_sched_barrier(0);
     const bool vown = t0 + j < N;
 #pragma unroll
     for (int pp = 0; pp < NP; ++pp) {
       const bool vk = kw + 2 * pp + half < K && (GW > 1 || half == 0);
-      const float w = vown && vk ? __expf(bt[0][pp] - ft[0]) * ctv : 0.f;
+      const float w = vown && vk ? __expf(bc[pp] - fc) * ctv : 0.f;
       aacc[pp] += w;
       wsh[wv][2 * pp + half][mom_pos(j)] = (WT)w;
     }
+    load_w(min(t0 + 64, pend - 32), bc, fc);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -930,22 +920,20 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
       }
     }
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (DB) {
-#pragma unroll
-      for (int bb = 0; bb < NB; ++bb)
-#pragma unroll
-        for (int s = 0; s < NS; ++s) xt[bb][s] = xn[bb][s];
-    }
-#pragma unroll
-    for (int r = 0; r + 1 < kPW; ++r) {
-#pragma unroll
-      for (int pp = 0; pp < NP; ++pp) bt[r][pp] = bt[r + 1][pp];
-      ft[r] = ft[r + 1];
-    }
-#pragma unroll
-    for (int pp = 0; pp < NP; ++pp) bt[kPW - 1][pp] = bn[pp];
-    ft[kPW - 1] = fn;
+  };
+  V8 xA[NB][NS], xB[NB][NS];
+  float bA[NP], fA, bB[NP], fB;
+  if (pbeg < pend) {
+    if constexpr (DB) load_x(pbeg, xA);
+    load_w(pbeg, bA, fA);
+    load_w(min(pbeg + 32, pend - 32), bB, fB);
   }
+  int t0 = pbeg;
+  for (; t0 + 32 < pend; t0 += 64) {
+    step(t0, xA, xB, bA, fA);
+    step(t0 + 32, xB, xA, bB, fB);
+  }
+  if (t0 < pend) step(t0, xA, xB, bA, fA);
 
   // A: lanes 0-31 hold component kw + 2pp, lanes 32-63 component kw + 2pp + 1
   float asum[NP];
