@@ -329,6 +329,23 @@ DEX_DEV float row_max16(float v) {
   v = fmaxf(v, dpp<0x141>(v));
   return fmaxf(v, dpp<0x140>(v));
 }
+// Max over the 16 lanes of a row on order-preserving integer keys of the
+// floats (integer max needs no NaN canonicalisation and fuses with DPP).
+DEX_DEV int fkey(float v) {
+  const int b = __float_as_int(v);
+  return b ^ ((b >> 31) & 0x7fffffff);
+}
+DEX_DEV float funkey(int k) { return __int_as_float(k ^ ((k >> 31) & 0x7fffffff)); }
+template <int CTRL>
+DEX_DEV int dppi(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+DEX_DEV float row_max16k(int k) {
+  k = max(k, dppi<0xB1>(k));
+  k = max(k, dppi<0x4E>(k));
+  k = max(k, dppi<0x141>(k));
+  return funkey(max(k, dppi<0x140>(k)));
+}
 DEX_DEV float row_sum16(float v) {
   v = v + dpp<0xB1>(v);
   v = v + dpp<0x4E>(v);
@@ -406,6 +423,14 @@ __global__ void __launch_bounds__(64 * kQfWaves) k_gmm_fwd_qf(
           W16 + ((((size_t)(2 * pass + n) * qf::kChunks + ch) * 64 + ln) * 8));
     }
     __syncthreads();
+    // the pass's kappa' and rescale factors of the lane's two components,
+    // loaded once per pass (not after every unit's products)
+    float kqv[2], iscv[2];
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+      kqv[n] = kq[pass * qf::kPass + 16 * n + c];
+      iscv[n] = isc[pass * qf::kPass + 16 * n + c];
+    }
     for (int64_t u = cur + wv; u < seg; u += kQfWaves) {
       const int pb = (int)(t0 + (u - (int64_t)pass * ntx)) * 64;  // the tile's first point
       // one prep tile: one scale 2^-ex, and "one" = 2^-ex
@@ -429,32 +454,53 @@ __global__ void __launch_bounds__(64 * kQfWaves) k_gmm_fwd_qf(
 #pragma unroll
       for (int n = 0; n < 2; ++n) {
         const int k = pass * qf::kPass + 16 * n + c;
-        const float kk = kq[k], is = ldexpf(isc[k], 2 * ex);
+        const float kk = kqv[n], is = ldexpf(iscv[n], 2 * ex);
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) acc[tt][n][i] = kk - 0.5f * is * acc[tt][n][i];
-          __builtin_nontemporal_store(
-              acc[tt][n], reinterpret_cast<f32x4*>(beta + (size_t)k * Npad + pb + 16 * tt + 4 * g));
+          *reinterpret_cast<f32x4*>(beta + (size_t)k * Npad + pb + 16 * tt + 4 * g) = acc[tt][n];
         }
       }
-      const bool v0 = pass * qf::kPass + c < K, v1 = pass * qf::kPass + 16 + c < K;
+      // exp(b - M) as exp2(b log2 e - M log2 e); passes whose 32 components
+      // are all real skip the masks
+      auto lse = [&](auto full_t) {
+        constexpr bool FULL = decltype(full_t)::value;
+        const bool v0 = FULL || pass * qf::kPass + c < K;
+        const bool v1 = FULL || pass * qf::kPass + 16 + c < K;
+        constexpr float kL2e = 1.4426950408889634f;
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) {
-        float M[4], Ls[4];
+        for (int tt = 0; tt < 4; ++tt) {
+          float M[4], Ls[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float b0 = v0 ? acc[tt][0][i] : -INFINITY, b1 = v1 ? acc[tt][1][i] : -INFINITY;
-          M[i] = row_max16(fmaxf(b0, b1));
-          const float e = (v0 ? __expf(b0 - M[i]) : 0.f) + (v1 ? __expf(b1 - M[i]) : 0.f);
-          Ls[i] = row_sum16(e);
+          for (int i = 0; i < 4; ++i) {
+            const float b0 = acc[tt][0][i], b1 = acc[tt][1][i];
+            int key;
+            if constexpr (FULL)
+              key = max(fkey(b0), fkey(b1));
+            else
+              key = max(v0 ? fkey(b0) : fkey(-INFINITY), v1 ? fkey(b1) : fkey(-INFINITY));
+            M[i] = row_max16k(key);
+            const float m2 = M[i] * kL2e;
+            float e0 = __builtin_amdgcn_exp2f(fmaf(b0, kL2e, -m2));
+            float e1 = __builtin_amdgcn_exp2f(fmaf(b1, kL2e, -m2));
+            if constexpr (!FULL) {
+              e0 = v0 ? e0 : 0.f;
+              e1 = v1 ? e1 : 0.f;
+            }
+            Ls[i] = row_sum16(e0 + e1);
+          }
+          if (c < 4) {
+            const float mm = c == 0 ? M[0] : c == 1 ? M[1] : c == 2 ? M[2] : M[3];
+            const float ll = c == 0 ? Ls[0] : c == 1 ? Ls[1] : c == 2 ? Ls[2] : Ls[3];
+            ml[(size_t)pass * Npad + pb + 16 * tt + 4 * g + c] = make_float2(mm, ll);
+          }
         }
-        if (c < 4) {
-          const float mm = c == 0 ? M[0] : c == 1 ? M[1] : c == 2 ? M[2] : M[3];
-          const float ll = c == 0 ? Ls[0] : c == 1 ? Ls[1] : c == 2 ? Ls[2] : Ls[3];
-          ml[(size_t)pass * Npad + pb + 16 * tt + 4 * g + c] = make_float2(mm, ll);
-        }
-      }
+      };
+      if (pass * qf::kPass + qf::kPass <= K)
+        lse(std::true_type{});
+      else
+        lse(std::false_type{});
     }
     cur = seg;
   }
