@@ -179,37 +179,71 @@ __global__ void __launch_bounds__(256) k_merge_lse_quad(const float2* __restrict
   }
 }
 
+// s + err += a, compensated (two_sum)
+DEX_DEV void comp_add(float& s, float& err, float a) {
+  float ns, ne;
+  two_sum<float>(s, a, ns, ne);
+  s = ns;
+  err += ne;
+}
+
 // Fixed-order compensated sum of each component's partial moment slots (the
 // waves that owned part of its group's points), written back into slot 0, so
 // the per-component finalize reads a single slot. One thread per element.
 // Slots of component k: on each XCD x the waves that owned part of its
 // group's steps, in slots x * SX + rank; summed in (x, rank) order.
+DEX_DEV int mom_slots(int64_t kg, int x, int64_t nkg, int64_t nsteps, int Wx) {
+  const int64_t nsx = (x + 1) * nsteps / 8 - x * nsteps / 8;
+  return nsx == 0 ? 0 : split_slots(kg * nsx, nsx, nkg * nsx, min<int64_t>(Wx, nkg * nsx));
+}
+
 __global__ void __launch_bounds__(256) k_mom_reduce(float* __restrict__ part, int64_t E, int K,
                                                     int gw, int64_t nsteps, int Wx, int SX) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 256, i = i0 + threadIdx.x;
+  const int64_t nkg = (K + gw - 1) / gw;
+  // slot counts: with E >= 256 a block meets at most two components, whose
+  // counts 16 threads compute once (64-bit divisions) and share
+  __shared__ int Ssh[2][8];
+  const int k0 = (int)(i0 / E);
+  const bool shared_counts = E >= 256;
+  if (shared_counts) {
+    if (threadIdx.x < 16) {
+      const int kk = k0 + (int)(threadIdx.x >> 3);
+      Ssh[threadIdx.x >> 3][threadIdx.x & 7] =
+          kk < K ? mom_slots(kk / gw, threadIdx.x & 7, nkg, nsteps, Wx) : 0;
+    }
+    __syncthreads();
+  }
   if (i >= (int64_t)K * E) return;
   const int k = (int)(i / E);
-  const int64_t kg = k / gw, nkg = (K + gw - 1) / gw;
+  const int64_t kg = k / gw;
   const size_t stride = (size_t)K * E;
-  float s = 0.f, err = 0.f;
+  // the first 4 slots of every XCD are loaded together (one round trip for
+  // the usual case), then summed in (x, rank) order; slots past 4 follow in
+  // batches of 4
+  int S[8];
+  float v[8][4];
+#pragma unroll
   for (int x = 0; x < 8; ++x) {
-    const int64_t nsx = (x + 1) * nsteps / 8 - x * nsteps / 8;
-    if (nsx == 0) continue;
-    const int S = split_slots(kg * nsx, nsx, nkg * nsx, min<int64_t>(Wx, nkg * nsx));
+    S[x] = shared_counts ? Ssh[k - k0][x] : mom_slots(kg, x, nkg, nsteps, Wx);
     const float* base = part + (size_t)x * SX * stride + i;
-    for (int sp = 0; sp < S; sp += 4) {
-      float v[4];  // loads of a batch issued together; static indices keep v in registers
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = sp + u < S ? base[(size_t)(sp + u) * stride] : 0.f;
+    for (int u = 0; u < 4; ++u) v[x][u] = u < S[x] ? base[(size_t)u * stride] : 0.f;
+  }
+  float s = 0.f, err = 0.f;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (sp + u < S) {
-          float ns, ne;
-          two_sum<float>(s, v[u], ns, ne);
-          s = ns;
-          err += ne;
-        }
-      }
+  for (int x = 0; x < 8; ++x) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (u < S[x]) comp_add(s, err, v[x][u]);
+    const float* base = part + (size_t)x * SX * stride + i;
+    for (int sp = 4; sp < S[x]; sp += 4) {
+      float w[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) w[u] = sp + u < S[x] ? base[(size_t)(sp + u) * stride] : 0.f;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (sp + u < S[x]) comp_add(s, err, w[u]);
     }
   }
   part[i] = s + err;
