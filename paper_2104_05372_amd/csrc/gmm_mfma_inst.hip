@@ -398,6 +398,21 @@ DEX_DEV void qf_chunks(const qf::h2 (&xr)[4][32], _Float16 one, const qf::h8 (*w
       ...);
 }
 
+// x rows of the 64-point tile at pb, rotated by 16g (8 halves per load)
+DEX_DEV void qf_load_x(const _Float16* __restrict__ x16, int pb, int c, int g,
+                       qf::h2 (&xr)[4][32]) {
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) {
+    const _Float16* row = x16 + (size_t)(pb + 16 * tt + c) * 64;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const qf::h8 v = *reinterpret_cast<const qf::h8*>(row + ((8 * j + 16 * g) & 63));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) xr[tt][4 * j + e] = qf::h2{v[2 * e], v[2 * e + 1]};
+    }
+  }
+}
+
 __global__ void __launch_bounds__(64 * kQfWaves) k_gmm_fwd_qf(
     const _Float16* __restrict__ x16, int N, int Npad, int K, const _Float16* __restrict__ W16,
     const float* __restrict__ kq, const float* __restrict__ isc, const int* __restrict__ tile_exp,
@@ -436,20 +451,17 @@ __global__ void __launch_bounds__(64 * kQfWaves) k_gmm_fwd_qf(
       // one prep tile: one scale 2^-ex, and "one" = 2^-ex
       const int ex = tile_exp[pb >> 6];
       const _Float16 one = (_Float16)ldexpf(1.f, -ex);
-      // x rows, rotated by 16g (8 halves per load)
+      qf_load_x(x16, pb, c, g, xr);
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) {
-        const _Float16* row = x16 + (size_t)(pb + 16 * tt + c) * 64;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const qf::h8 v = *reinterpret_cast<const qf::h8*>(row + ((8 * j + 16 * g) & 63));
-#pragma unroll
-          for (int e = 0; e < 4; ++e) xr[tt][4 * j + e] = qf::h2{v[2 * e], v[2 * e + 1]};
-        }
+      for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
         for (int n = 0; n < 2; ++n) acc[tt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-      }
+      // the products at a higher wave priority than the loads and epilogues,
+      // so the two waves of a SIMD drift apart and one's epilogue overlaps the
+      // other's products
+      __builtin_amdgcn_s_setprio(2);
       qf_chunks(xr, one, wsh, lane, acc, std::make_integer_sequence<int, qf::kChunks>{});
+      __builtin_amdgcn_s_setprio(0);
       // epilogue: beta = kappa' - isc 2^(2 ex) / 2 * product; log-sum-exp over the pass
 #pragma unroll
       for (int n = 0; n < 2; ++n) {
