@@ -114,28 +114,42 @@ k_gmm_bwd(MfmaOps ops, int N, int Npad, int K, int SX,
 // for the reverse pass and the scaled FP16 copy of x with its exponent.
 // qf_w_comp: per component k < Kp, P = Q^T Q, the coefficient operand, kappa'
 // and the rescale factor. LDS of the two parts (they share one buffer):
-constexpr size_t kQfXLds = 64 * 65 * 4 + 16;
+constexpr size_t kQfXLds = 64 * 65 * 4 + 16;  // per tile (a block holds two)
 constexpr size_t kQfWLds = 64 * 68 * 4 + 64 * 65 * 4 + (64 + 64 + 12) * 4;
 
-DEX_DEV void qf_x_tile(int tix, char* smem, const float* __restrict__ x, int N, int Npad,
-                       _Float16* __restrict__ xhT, _Float16* __restrict__ x16,
+// Two tiles per 256-thread block, 128 threads each (x-tile blocks then fit in
+// one round of resident blocks next to the coefficient blocks); a half whose
+// tile is past the end only joins the barriers.
+DEX_DEV void qf_x_tile(int tix0, int ntiles, char* smem, const float* __restrict__ x, int N,
+                       int Npad, _Float16* __restrict__ xhT, _Float16* __restrict__ x16,
                        int* __restrict__ tile_exp) {
   // x~^T for the reverse pass, and x scaled by the tile's 2^-ex (|x| 2^-ex <
   // 2^7) in FP16, row-major, for the feature products
-  float(*tile)[65] = reinterpret_cast<float(*)[65]>(smem);
-  float* red = reinterpret_cast<float*>(smem + 64 * 65 * 4);
-  const int p0 = tix * 64, t = threadIdx.x;
+  const int hf = threadIdx.x >> 7, t = threadIdx.x & 127, tix = tix0 + hf;
+  const bool live = tix < ntiles;
+  float(*tile)[65] = reinterpret_cast<float(*)[65]>(smem + hf * kQfXLds);
+  float* red = reinterpret_cast<float*>(smem + hf * kQfXLds + 64 * 65 * 4);
+  const int p0 = tix * 64;
   float mx = 0.f;
-  for (int e = t; e < 64 * 64; e += 256) {
-    const int pp = e >> 6, b = e & 63, p = p0 + pp;
-    const float v = p < N ? x[(size_t)p * 64 + b] : 0.f;
-    tile[pp][b] = v;
-    mx = fmaxf(mx, fabsf(v));
+  if (live) {
+    float v[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      const int e = t + 128 * i, p = p0 + (e >> 6);
+      v[i] = p < N ? x[(size_t)p * 64 + (e & 63)] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      const int e = t + 128 * i;
+      tile[e >> 6][e & 63] = v[i];
+      mx = fmaxf(mx, fabsf(v[i]));
+    }
   }
   mx = wave_max(mx);
   if ((t & 63) == 0) red[t >> 6] = mx;
   __syncthreads();
-  mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  if (!live) return;  // no barrier follows
+  mx = fmaxf(red[0], red[1]);
   // ex >= -6 keeps the linear features (x 2^-ex)(2^-ex) below 2^13 as well
   int ex = -6;
   if (mx > 0.f) {
@@ -145,14 +159,14 @@ DEX_DEV void qf_x_tile(int tix, char* smem, const float* __restrict__ x, int N, 
   }
   if (t == 0) tile_exp[tix] = ex;
   const float sx = ldexpf(1.f, -ex);
-  for (int e = t; e < 8 * 64; e += 256) {
+  for (int e = t; e < 8 * 64; e += 128) {
     const int pp = e >> 3, b0 = 8 * (e & 7);
     qf::h8 h;
 #pragma unroll
     for (int i = 0; i < 8; ++i) h[i] = (_Float16)(tile[pp][b0 + i] * sx);
     *reinterpret_cast<qf::h8*>(x16 + (size_t)(p0 + pp) * 64 + b0) = h;
   }
-  for (int e = t; e < 8 * 64; e += 256) {
+  for (int e = t; e < 8 * 64; e += 128) {
     const int b = e / 8, s0 = 8 * (e % 8);
     float v[8];
 #pragma unroll
@@ -298,8 +312,8 @@ DEX_DEV void qf_w_comp(int k, char* smem, const float* __restrict__ alphas,
 }
 
 // One launch for both parts of the preparation: blocks [0, Kp) build the
-// coefficient operand of one component each (latency-bound), the others one
-// 64-point x tile each (bandwidth-bound), so the two overlap.
+// coefficient operand of one component each (latency-bound), the others two
+// 64-point x tiles each (bandwidth-bound), so the two overlap.
 __global__ void __launch_bounds__(256) k_qf_prep(const float* __restrict__ x, int N, int Npad,
                                                  _Float16* __restrict__ xhT,
                                                  _Float16* __restrict__ x16,
@@ -310,11 +324,11 @@ __global__ void __launch_bounds__(256) k_qf_prep(const float* __restrict__ x, in
                                                  const float* __restrict__ l, int K, int Kp,
                                                  _Float16* __restrict__ W16,
                                                  float* __restrict__ kq, float* __restrict__ isc) {
-  __shared__ __attribute__((aligned(16))) char smem[kQfWLds > kQfXLds ? kQfWLds : kQfXLds];
+  __shared__ __attribute__((aligned(16))) char smem[kQfWLds > 2 * kQfXLds ? kQfWLds : 2 * kQfXLds];
   if ((int)blockIdx.x < Kp)
     qf_w_comp(blockIdx.x, smem, alphas, means, qd, l, K, W16, kq, isc);
   else
-    qf_x_tile(blockIdx.x - Kp, smem, x, N, Npad, xhT, x16, tile_exp);
+    qf_x_tile(2 * (blockIdx.x - Kp), Npad / 64, smem, x, N, Npad, xhT, x16, tile_exp);
 }
 
 // Sum / max over the 16 lanes of a row (DPP: quad swaps, half-row and row
@@ -652,8 +666,8 @@ void qf_prep(const GmmGeom& g, const float* x, const float* alphas, const float*
              float* kq, float* isc, hipStream_t st) {
   const int ntiles = (int)(g.Npad / 64);
   const int Kp = (int)((g.K + qf::kPass - 1) / qf::kPass * qf::kPass);
-  hipLaunchKernelGGL(k_qf_prep, dim3((unsigned)(Kp + ntiles)), dim3(256), 0, st, x, (int)g.N,
-                     (int)g.Npad, (_Float16*)xhT, (_Float16*)x16, tile_exp, alphas, means, qd, l,
+  hipLaunchKernelGGL(k_qf_prep, dim3((unsigned)(Kp + (ntiles + 1) / 2)), dim3(256), 0, st, x,
+                     (int)g.N, (int)g.Npad, (_Float16*)xhT, (_Float16*)x16, tile_exp, alphas, means, qd, l,
                      (int)g.K, Kp, (_Float16*)W16, kq, isc);
 }
 
