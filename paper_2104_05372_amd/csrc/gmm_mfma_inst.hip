@@ -445,13 +445,19 @@ __global__ void __launch_bounds__(64 * kQfWaves) k_gmm_fwd_qf(
     const int pass = (int)(cur / ntx);
     const int64_t seg = min<int64_t>(ub, (int64_t)(pass + 1) * ntx);
     // the pass's coefficient operand into LDS (component tiles 2 pass, 2 pass + 1)
+    // by direct loads (global_load_lds_dwordx4: a wave moves one 1 KiB (chunk,
+    // tile) piece per instruction, lane i's 16 bytes to the piece's base + 16 i),
+    // all 17 of a wave in flight together and no registers used
     __syncthreads();
-    for (int e = t; e < qf::kChunks * 2 * 64; e += 64 * kQfWaves) {
-      const int ch = e >> 7, n = (e >> 6) & 1, ln = e & 63;
-      wsh[ch][n][ln] = *reinterpret_cast<const qf::h8*>(
-          W16 + ((((size_t)(2 * pass + n) * qf::kChunks + ch) * 64 + ln) * 8));
+#pragma unroll
+    for (int i = 0; i < qf::kChunks * 2 / kQfWaves; ++i) {
+      const int q = kQfWaves * i + wv, ch = q >> 1, n = q & 1;
+      __builtin_amdgcn_global_load_lds(
+          W16 + ((((size_t)(2 * pass + n) * qf::kChunks + ch) * 64 + lane) * 8),
+          (__attribute__((address_space(3))) void*)&wsh[ch][n][0], 16, 0, 0);
     }
-    __syncthreads();
+    static_assert(qf::kChunks * 2 % kQfWaves == 0, "whole pieces per wave");
+    __syncthreads();  // (waits for the loads: vmcnt(0))
     // the pass's kappa' and rescale factors of the lane's two components,
     // loaded once per pass (not after every unit's products)
     float kqv[2], iscv[2];
