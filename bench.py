@@ -193,6 +193,11 @@ def row_scatter(torch, dex, workloads, dev, steps, scatter_config=1):
     def vjp():
         dex.dex_vjp(dv, [T, idx, w], [], [g], [dT, dw], 0, wsb)
 
+    # forward mode: dT (filled by the reverse pass) and w serve as the tangents
+    # of T and w, out receives the tangent of the output
+    def jvp():
+        dex.dex_jvp(d, [T, idx, w], [dT, w], [out])
+
     fwd()
     vjp()
     torch.cuda.synchronize()
@@ -200,6 +205,7 @@ def row_scatter(torch, dex, workloads, dev, steps, scatter_config=1):
     dex.dex_profile_enable(True)
     f_ms = timed(fwd, steps, torch.cuda.synchronize) * 1e3
     b_ms = timed(vjp, steps, torch.cuda.synchronize) * 1e3
+    j_ms = timed(jvp, steps, torch.cuda.synchronize) * 1e3 if scatter_config == 1 else None
     dex.dex_profile_enable(False)
     res = {"workload": f"gather/scatter table {V}x{R} f32, {n} Zipf(1.1) indices",
            "scatter_form": {1: "block sort + run sums + atomics", 2: "radix sort, fixed-order run sums"}[
@@ -208,6 +214,9 @@ def row_scatter(torch, dex, workloads, dev, steps, scatter_config=1):
            "touched_rows": touched}
     bytes_k = {"GATHER": 2 * n * 4 + 2 * n * R * 4, "SCATTER": 2 * n * 4 + n * R * 4 + touched * R * 4,
                "GATHER_DW": 2 * n * R * 4 + 3 * n * 4}
+    if j_ms is not None:
+        res["jvp_ms"] = round(j_ms, 4)
+        bytes_k["GATHER_JVP"] = 3 * n * 4 + 3 * n * R * 4
     for k, b in bytes_k.items():
         ms, cnt = dex.dex_profile_read(k)
         a = b / (ms / max(cnt, 1) * 1e-3) / 1e9

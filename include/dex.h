@@ -88,6 +88,7 @@ typedef int32_t dex_status;
 #define DEX_WS_FWD   0 /* scratch for dex_fwd                           */
 #define DEX_WS_VJP   1 /* scratch for dex_vjp                           */
 #define DEX_WS_RESID 2 /* bytes of the second (operand-cache) residual  */
+#define DEX_WS_JVP   3 /* scratch for dex_jvp                           */
 
 /*
  * Descriptor of the function being differentiated.
@@ -212,6 +213,27 @@ dex_status dex_vjp(const dex_desc* d,
                    void* workspace, size_t ws_bytes,
                    void* hip_stream);
 
+/* Forward mode: t_out = the linear map of `linearize f in` (Sec. 5.1, the
+ * linearization rules of its figure, e.g. LinFor for the loop over j) applied
+ * to the tangents t_in, i.e. the directional derivative of f at `in` along
+ * t_in. The transpose of the same map is dex_vjp, so for every t_in and ct_out
+ * <t_out, ct_out> = <t_in, ct_in> up to rounding.
+ *   DEX_GATHER_SCALE: in = T[V*R], idx[n] (DEX_I32), w[n] (as for dex_fwd);
+ *     t_in = tT[V*R], tw[n];  t_out = tout[n*R],
+ *     tout[j, :] = tw[j] T[idx[j], :] + w[j] tT[idx[j], :]
+ *     (idx is an integer and has no tangent; rows whose index is outside [0, V)
+ *     give zeros, as in dex_fwd).
+ *   Other kinds: DEX_ERR_UNSUPPORTED.
+ * All buffers are device memory owned by the caller; t_out is overwritten.
+ * Argument errors are reported before anything is enqueued; the call enqueues
+ * on hip_stream and returns. Workspace: DEX_WS_JVP bytes (0 for the gather). */
+dex_status dex_jvp(const dex_desc* d,
+                   const dex_buf* in, int32_t n_in,
+                   const dex_buf* t_in, int32_t n_t_in,
+                   dex_buf* t_out, int32_t n_t_out,
+                   void* workspace, size_t ws_bytes,
+                   void* hip_stream);
+
 /*
  * acc!(idx[j]) += scale[j] * vals[j, :]  for j in [0, n)      (Sec. 2.3.2-2.3.3)
  *
@@ -294,7 +316,8 @@ void dex_autotune_reset(void);
 #define DEX_PROF_BGMM_VJP     7 /* batched reverse persistent kernel          */
 #define DEX_PROF_STENCIL_FWD  8 /* forward steps (one range per dex_fwd)      */
 #define DEX_PROF_STENCIL_VJP  9 /* reverse steps incl. recompute (per dex_vjp) */
-#define DEX_PROF_COUNT       10
+#define DEX_PROF_GATHER_JVP  10 /* gather-scale forward mode (dex_jvp)        */
+#define DEX_PROF_COUNT       11
 void dex_profile_enable(int32_t on);
 dex_status dex_profile_read(int32_t id, double* total_ms, int64_t* launches);
 void dex_profile_reset(void);

@@ -12,6 +12,10 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
              respect to w is dw[j] = <T[idx[j]], g[j]> (MulLeftTranspose).
   histogram  `for i. hist!(keys.i) += 1` (Sec. 2.3.3, Sec. 6.1.2): an integer
              accumulation, exact under any order.
+  gather_jvp the forward mode of `gather` (the linear map that `linearize`
+             returns, Sec. 5.1): the tangent of a product is the product rule,
+             the tangent of an indexed read reads the tangent array at the same
+             index, and the integer idx carries no tangent.
 """
 from __future__ import annotations
 
@@ -90,3 +94,22 @@ def histogram(keys, n_bins, check_bounds=False):
     np.add.at(h, keys[inside], 1)
     bad = int(keys.shape[0] - np.count_nonzero(inside))
     return (h, bad) if check_bounds else h
+
+
+def gather_jvp(T, idx, w, tT, tw, rows_out=None):
+    """Tangent of out[j] = w[j] * T[idx[j]] along (tT, tw):
+    tout[j] = tw[j] * T[idx[j]] + w[j] * tT[idx[j]], for every j or only for j in
+    rows_out. Rows whose index lies outside [0, len(T)) are zero (the library's
+    out-of-range convention)."""
+    T = np.asarray(T, dtype=np.float64)
+    tT = np.asarray(tT, dtype=np.float64)
+    idx = np.asarray(idx, dtype=np.int64)
+    w = np.asarray(w, dtype=np.float64)
+    tw = np.asarray(tw, dtype=np.float64)
+    js = np.arange(idx.shape[0]) if rows_out is None else np.asarray(rows_out)
+    out = np.zeros((js.shape[0], T.shape[1]))
+    for n, j in enumerate(js):
+        v = idx[j]
+        if 0 <= v < T.shape[0]:
+            out[n] = tw[j] * T[v] + w[j] * tT[v]
+    return out

@@ -227,6 +227,7 @@ static dex_status check_desc(const dex_desc* d) {
 }
 
 static size_t ws_bytes(const dex_desc& d, int role) {
+  if (role == DEX_WS_JVP) return 0;  // forward mode of the gather needs no scratch
   switch (d.kind) {
     case DEX_GMM:
       return gmm_ws_bytes(d, role);
@@ -283,7 +284,7 @@ dex_status dex_init(void) { return ensure_device(); }
 dex_status dex_workspace_bytes(const dex_desc* d, int32_t role, size_t* bytes) {
   DEX_TRY(check_desc(d));
   if (!bytes) return fail(DEX_ERR_INVALID_ARG, "null output");
-  if (role < DEX_WS_FWD || role > DEX_WS_RESID) return fail(DEX_ERR_INVALID_ARG, "bad role");
+  if (role < DEX_WS_FWD || role > DEX_WS_JVP) return fail(DEX_ERR_INVALID_ARG, "bad role");
   *bytes = ws_bytes(*d, role);
   return DEX_OK;
 }
@@ -395,6 +396,32 @@ dex_status dex_fwd(const dex_desc* d, const dex_buf* in, int32_t n_in, dex_buf* 
     }
   }
   return fail(DEX_ERR_INVALID_ARG, "unknown kind");
+}
+
+dex_status dex_jvp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex_buf* t_in,
+                   int32_t n_t_in, dex_buf* t_out, int32_t n_t_out, void* workspace,
+                   size_t ws_bytes_, void* hip_stream) {
+  DEX_TRY(check_desc(d));
+  if ((n_in && !in) || (n_t_in && !t_in) || (n_t_out && !t_out))
+    return fail(DEX_ERR_INVALID_ARG, "null buffer list");
+  if (d->kind != DEX_GATHER_SCALE)
+    return fail(DEX_ERR_UNSUPPORTED, "forward mode is implemented for DEX_GATHER_SCALE");
+  const int64_t V = d->dims[0], R = d->dims[1], n = d->dims[2];
+  DEX_TRY(check_count(n_in, 3, "in"));
+  DEX_TRY(want(in, 0, "in", DEX_F32, V * R));
+  DEX_TRY(want(in, 1, "in", DEX_I32, n));
+  DEX_TRY(want(in, 2, "in", DEX_F32, n));
+  DEX_TRY(check_count(n_t_in, 2, "t_in"));
+  DEX_TRY(want(t_in, 0, "t_in", DEX_F32, V * R));
+  DEX_TRY(want(t_in, 1, "t_in", DEX_F32, n));
+  DEX_TRY(check_count(n_t_out, 1, "t_out"));
+  DEX_TRY(want(t_out, 0, "t_out", DEX_F32, n * R));
+  DEX_TRY(check_ws(*d, DEX_WS_JVP, workspace, ws_bytes_));
+  DEX_TRY(ensure_device());
+  hipStream_t s = (hipStream_t)hip_stream;
+  return gather_jvp((const float*)in[0].ptr, (const float*)t_in[0].ptr, (const int32_t*)in[1].ptr,
+                    (const float*)in[2].ptr, (const float*)t_in[1].ptr, V, R, n,
+                    (float*)t_out[0].ptr, s);
 }
 
 dex_status dex_vjp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex_buf* resid,

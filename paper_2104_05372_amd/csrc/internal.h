@@ -68,6 +68,9 @@ dex_status accum_scatter(void* acc, int32_t acc_dtype, int64_t n_rows, int64_t r
                          void* ws, size_t ws_bytes, int cfg, hipStream_t s);
 dex_status gather_fwd(const float* T, const int32_t* idx, const float* w, int64_t V, int64_t R,
                       int64_t n, float* out, bool count_oob, int64_t* oob, hipStream_t s);
+dex_status gather_jvp(const float* T, const float* tT, const int32_t* idx, const float* w,
+                      const float* tw, int64_t V, int64_t R, int64_t n, float* tout,
+                      hipStream_t s);
 dex_status gather_dw(const float* T, const int32_t* idx, const float* g, int64_t V, int64_t R,
                      int64_t n, float* dw, bool accumulate, hipStream_t s);
 dex_status fill_zero(void* p, size_t bytes, hipStream_t s);

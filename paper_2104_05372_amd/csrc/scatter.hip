@@ -292,6 +292,54 @@ __global__ void __launch_bounds__(256) gather_scale_kernel(const float* __restri
   if (oob) count_oob(bad, oob);
 }
 
+// Forward mode of the gather (the linear map of its linearization, Sec. 5.1;
+// idx is an integer, so it carries no tangent):
+//   tout[j, :] = tw[j] * T[idx[j], :] + w[j] * tT[idx[j], :]
+// Same layout as the gather: half a wave per row, 4 floats per lane; rows with
+// an index outside [0, V) give zeros.
+__global__ void __launch_bounds__(256) gather_jvp_kernel(const float* __restrict__ T,
+                                                         const float* __restrict__ tT,
+                                                         const int32_t* __restrict__ idx,
+                                                         const float* __restrict__ w,
+                                                         const float* __restrict__ tw, int64_t V,
+                                                         int R, int64_t n,
+                                                         float* __restrict__ tout) {
+  const int half = threadIdx.x >> 5, hl = threadIdx.x & 31;
+  const int64_t rows_per_iter = (int64_t)gridDim.x * 8;
+  for (int64_t j = (int64_t)blockIdx.x * 8 + half; j < n; j += rows_per_iter) {
+    const int64_t v = idx[j];
+    const bool ok = v >= 0 && v < V;
+    const float a = tw[j], b = w[j];
+    for (int c = 4 * hl; c < R; c += 128) {
+      f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
+      if (ok) {
+        const f32x4 x = *reinterpret_cast<const f32x4*>(T + v * R + c);
+        const f32x4 y = *reinterpret_cast<const f32x4*>(tT + v * R + c);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) o[e] = fmaf(b, y[e], a * x[e]);
+      }
+      __builtin_nontemporal_store(o, reinterpret_cast<f32x4*>(tout + j * R + c));
+    }
+  }
+}
+
+// Scalar form for row lengths that are not a multiple of 4.
+__global__ void __launch_bounds__(256) gather_jvp_scalar(const float* __restrict__ T,
+                                                         const float* __restrict__ tT,
+                                                         const int32_t* __restrict__ idx,
+                                                         const float* __restrict__ w,
+                                                         const float* __restrict__ tw, int64_t V,
+                                                         int R, int64_t n,
+                                                         float* __restrict__ tout) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n * R) {
+    const int64_t j = t / R, c = t % R;
+    const int64_t v = idx[j];
+    const bool ok = v >= 0 && v < V;
+    tout[t] = ok ? fmaf(w[j], tT[v * R + c], tw[j] * T[v * R + c]) : 0.f;
+  }
+}
+
 // Scalar-path gather for row lengths that are not a multiple of 4.
 __global__ void __launch_bounds__(256) gather_scale_scalar(const float* __restrict__ T,
                                                            const int32_t* __restrict__ idx,
@@ -837,6 +885,25 @@ dex_status gather_fwd(const float* T, const int32_t* idx, const float* w, int64_
   }
   pr.end(1);
   return check_hip(hipGetLastError(), "gather_fwd");
+}
+
+dex_status gather_jvp(const float* T, const float* tT, const int32_t* idx, const float* w,
+                      const float* tw, int64_t V, int64_t R, int64_t n, float* tout,
+                      hipStream_t s) {
+  if (n == 0) return DEX_OK;
+  const bool vec = (R % 4) == 0 && ((uintptr_t)T & 15) == 0 && ((uintptr_t)tT & 15) == 0 &&
+                   ((uintptr_t)tout & 15) == 0;
+  ProfRange pr(DEX_PROF_GATHER_JVP, s);
+  if (vec) {
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 7) / 8, (int64_t)num_cus() * 32);
+    hipLaunchKernelGGL(gather_jvp_kernel, dim3(blocks), dim3(256), 0, s, T, tT, idx, w, tw, V,
+                       (int)R, n, tout);
+  } else {
+    hipLaunchKernelGGL(gather_jvp_scalar, dim3((unsigned)((n * R + 255) / 256)), dim3(256), 0, s,
+                       T, tT, idx, w, tw, V, (int)R, n, tout);
+  }
+  pr.end(1);
+  return check_hip(hipGetLastError(), "gather_jvp");
 }
 
 dex_status gather_dw(const float* T, const int32_t* idx, const float* g, int64_t V, int64_t R,

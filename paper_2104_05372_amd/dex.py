@@ -33,11 +33,11 @@ DEX_STENCIL_RECOMPUTE, DEX_STENCIL_LINEAR = 0, 1
 # flags
 DEX_ACCUMULATE, DEX_CHECK_BOUNDS, DEX_SYNC_CHECK, DEX_NO_DW, DEX_DETERMINISTIC = 1, 2, 4, 8, 16
 # workspace roles
-DEX_WS_FWD, DEX_WS_VJP, DEX_WS_RESID = 0, 1, 2
+DEX_WS_FWD, DEX_WS_VJP, DEX_WS_RESID, DEX_WS_JVP = 0, 1, 2, 3
 
 EXPORTS = (
     "dex_status_string", "dex_last_error", "dex_version", "dex_init", "dex_workspace_bytes",
-    "dex_num_configs", "dex_fwd", "dex_vjp", "dex_accum_scatter",
+    "dex_num_configs", "dex_fwd", "dex_vjp", "dex_jvp", "dex_accum_scatter",
     "dex_accum_scatter_workspace_bytes", "dex_gmm_batched_plan", "dex_autotune",
     "dex_autotune_reset", "dex_profile_enable", "dex_profile_read", "dex_profile_reset",
 )
@@ -85,6 +85,8 @@ def lib():
         L.dex_fwd.restype = S
         L.dex_vjp.argtypes = [DP, BP, I32, BP, I32, BP, I32, BP, I32, ctypes.c_uint32, P, SZ, P]
         L.dex_vjp.restype = S
+        L.dex_jvp.argtypes = [DP, BP, I32, BP, I32, BP, I32, P, SZ, P]
+        L.dex_jvp.restype = S
         L.dex_accum_scatter.argtypes = [P, I32, I64, I64, P, I32, P, P, I64, ctypes.c_uint32, P, P, SZ, P]
         L.dex_accum_scatter.restype = S
         L.dex_accum_scatter_workspace_bytes.argtypes = [I32, I64, I64, I64, I32, ctypes.c_uint32,
@@ -210,6 +212,17 @@ def dex_fwd(d: DexDesc, ins, outs, resid, ws: torch.Tensor | None = None, stream
     check(lib().dex_fwd(ctypes.byref(d), a, na, o, no, r, nr, wp, wb, stream_ptr(stream)))
 
 
+def dex_jvp(d: DexDesc, ins, t_in, t_out, ws: torch.Tensor | None = None, stream=None,
+            dtypes=None):
+    """Forward mode: t_out = the linearization of f at ins applied to t_in."""
+    a, na = bufs(ins, dtypes and dtypes.get("in"))
+    ti, nti = bufs(t_in)
+    to, nto = bufs(t_out)
+    wp = ctypes.c_void_p(ws.data_ptr()) if ws is not None else None
+    wb = ws.numel() if ws is not None else 0
+    check(lib().dex_jvp(ctypes.byref(d), a, na, ti, nti, to, nto, wp, wb, stream_ptr(stream)))
+
+
 def dex_vjp(d: DexDesc, ins, resid, ct_out, ct_in, flags=0, ws: torch.Tensor | None = None,
             stream=None, dtypes=None):
     a, na = bufs(ins, dtypes and dtypes.get("in"))
@@ -287,7 +300,7 @@ def dex_autotune_reset():
 
 
 DEX_PROF = dict(GMM_FWD=0, GMM_VJP=1, SCATTER=2, HIST=3, GATHER=4, GATHER_DW=5, BGMM_FWD=6,
-                BGMM_VJP=7, STENCIL_FWD=8, STENCIL_VJP=9)
+                BGMM_VJP=7, STENCIL_FWD=8, STENCIL_VJP=9, GATHER_JVP=10)
 
 
 def dex_profile_enable(on: bool = True):

@@ -66,6 +66,23 @@ def test_invalid_descriptors_rejected_on_host(dex):
         assert s in (dex.DEX_ERR_INVALID_ARG, dex.DEX_ERR_UNSUPPORTED), s
         s = _status(dex.dex_fwd, d, [], [], [], None)
         assert s in (dex.DEX_ERR_INVALID_ARG, dex.DEX_ERR_UNSUPPORTED), s
+        s = _status(dex.dex_jvp, d, [], [], [], None)
+        assert s in (dex.DEX_ERR_INVALID_ARG, dex.DEX_ERR_UNSUPPORTED), s
+
+
+def test_forward_mode_argument_checks(dex):
+    """dex_jvp: kinds without forward mode are unsupported; missing or
+    mis-sized gather buffers are rejected on the host, before any device work."""
+    assert _status(dex.dex_jvp, dex.gmm_desc(100, 4, 3), [], [], [], None) == dex.DEX_ERR_UNSUPPORTED
+    d = dex.gather_desc(10, 4, 5)
+    assert _status(dex.dex_jvp, d, [], [], [], None) == dex.DEX_ERR_INVALID_ARG
+    import torch
+    T, idx, w = torch.zeros(10, 4), torch.zeros(5, dtype=torch.int32), torch.zeros(5)
+    tT, tw, out = torch.zeros(10, 4), torch.zeros(5), torch.zeros(5, 4)
+    assert _status(dex.dex_jvp, d, [T, idx, w], [tT], [out], None) == dex.DEX_ERR_INVALID_ARG
+    assert _status(dex.dex_jvp, d, [T, idx, w], [tT, tw], [torch.zeros(5, 3)], None) \
+        == dex.DEX_ERR_INVALID_ARG
+    assert dex.dex_workspace_bytes(d, dex.DEX_WS_JVP) == 0
 
 
 def test_accum_scatter_argument_checks(dex):

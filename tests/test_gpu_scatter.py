@@ -209,3 +209,61 @@ def test_full_size_histogram(dev):
     keys = workloads.histogram_keys(c["n"], c["bins"], c["s"], c["seed"])
     h = autograd.histogram(torch.tensor(keys.view(np.int32), device=dev), c["bins"]).cpu().numpy()
     assert np.array_equal(h, osc.histogram(keys, c["bins"]))
+
+
+def gather_jvp_gpu(T, idx, w, tT, tw, dev):
+    from paper_2104_05372_amd import dex
+    V, R = T.shape
+    n = idx.shape[0]
+    d = dex.gather_desc(V, R, n)
+    out = torch.empty(n, R, device=dev)
+    print(f"  gather jvp V={V} R={R} n={n}", flush=True)
+    ws = dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_JVP), dev)
+    dex.dex_jvp(d, [torch.tensor(T, device=dev), torch.tensor(idx, device=dev),
+                    torch.tensor(w, device=dev)],
+                [torch.tensor(tT, device=dev), torch.tensor(tw, device=dev)], [out], ws)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("V,R,n,seed", [(50, 8, 1000, 0), (300, 100, 4097, 3), (7, 3, 5000, 2),
+                                        (20_000, 130, 2049, 4), (1, 64, 3000, 5), (10, 4, 0, 6)])
+def test_gather_forward_mode(dev, V, R, n, seed):
+    """dex_jvp of the gather against the oracle (several tiles, ragged row
+    lengths, n = 0), and the dot-product identity <J t, g> = <t, J^T g> against
+    dex_vjp on the same inputs."""
+    si = workloads.scatter_inputs(V, R, n, 1.1, seed)
+    rng = np.random.default_rng(seed + 100)
+    tT = rng.standard_normal((V, R)).astype(np.float32)
+    tw = rng.standard_normal(n).astype(np.float32)
+    got = gather_jvp_gpu(si.table, si.idx, si.w, tT, tw, dev)
+    if n == 0:
+        assert got.size == 0
+        return
+    assert rel(got, osc.gather_jvp(si.table, si.idx, si.w, tT, tw)) <= 1e-6
+    _, dT, dw = gather_vjp(si.table, si.idx, si.w, si.g, dev, config=1)
+    lhs = np.sum(got.astype(np.float64) * si.g)
+    rhs = np.sum(tT.astype(np.float64) * dT) + np.dot(tw.astype(np.float64), dw)
+    assert abs(lhs - rhs) <= 1e-5 * (np.linalg.norm(got) * np.linalg.norm(si.g))
+
+
+def test_gather_forward_mode_out_of_range_rows(dev):
+    T = np.arange(24, dtype=np.float32).reshape(6, 4)
+    idx = np.array([-1, 6, 2, 5, 1 << 30], dtype=np.int32)
+    w = np.array([1, 2, 3, 4, 5], dtype=np.float32)
+    tT = np.ones_like(T)
+    tw = np.full(5, 0.5, dtype=np.float32)
+    got = gather_jvp_gpu(T, idx, w, tT, tw, dev)
+    assert np.array_equal(got, osc.gather_jvp(T, idx, w, tT, tw).astype(np.float32))
+
+
+def test_full_size_gather_forward_mode_sampled(dev):
+    """The benchmarked 1e6 x 128 table with 2^22 Zipf(1.1) indices; sampled rows."""
+    c = workloads.SCATTER
+    si = workloads.scatter_inputs(c["rows"], c["row_len"], c["n"], c["s"], c["seed"])
+    rng = np.random.default_rng(1)
+    tT = rng.standard_normal(si.table.shape, dtype=np.float32)
+    tw = rng.standard_normal(si.w.shape[0], dtype=np.float32)
+    got = gather_jvp_gpu(si.table, si.idx, si.w, tT, tw, dev)
+    js = np.concatenate([[0, c["n"] - 1], rng.integers(0, c["n"], 64)])
+    assert rel(got[js], osc.gather_jvp(si.table, si.idx, si.w, tT, tw, js)) <= 1e-6

@@ -103,3 +103,49 @@ def test_zipf_statistics_of_the_table_indices():
     idx = workloads.zipf_table_indices(1 << 20, 1_000_000, 1.1, 2)
     share = np.mean(idx == 0)
     assert 0.085 < share < 0.105
+
+
+def test_gather_jvp_by_central_differences():
+    """The gather is bilinear in (T, w), so the central difference of the
+    primal along (tT, tw) equals the tangent up to rounding, for any step."""
+    si = workloads.scatter_inputs(40, 6, 300, 1.1, 5)
+    rng = np.random.default_rng(5)
+    tT = rng.standard_normal(si.table.shape)
+    tw = rng.standard_normal(si.w.shape)
+    T, w = si.table.astype(np.float64), si.w.astype(np.float64)
+    h = 0.5
+    up = scatter.gather(T + h * tT, si.idx, w + h * tw)
+    dn = scatter.gather(T - h * tT, si.idx, w - h * tw)
+    got = scatter.gather_jvp(T, si.idx, w, tT, tw)
+    assert np.allclose((up - dn) / (2 * h), got, rtol=1e-12, atol=1e-12)
+
+
+def test_gather_jvp_vjp_dot_product_identity():
+    """<J t, g> = <t, J^T g>: the forward mode against the transposed gather
+    (scatter) and the weight cotangent (scatter_dw), both pinned above."""
+    si = workloads.scatter_inputs(60, 5, 700, 1.1, 6)
+    rng = np.random.default_rng(6)
+    tT = rng.standard_normal(si.table.shape)
+    tw = rng.standard_normal(si.w.shape)
+    lhs = np.sum(scatter.gather_jvp(si.table, si.idx, si.w, tT, tw) * si.g)
+    rhs = (np.sum(tT * scatter.scatter(60, si.idx, si.w, si.g))
+           + np.dot(tw, scatter.scatter_dw(si.table, si.idx, si.g)))
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+
+
+def test_gather_jvp_special_cases():
+    """Zero tangents give zero; a tangent along T alone is the gather of tT;
+    along w alone it is tw times the gathered rows; out-of-range rows are zero."""
+    si = workloads.scatter_inputs(20, 4, 100, 1.1, 7)
+    T, w, idx = si.table.astype(np.float64), si.w.astype(np.float64), si.idx
+    z = scatter.gather_jvp(T, idx, w, np.zeros_like(T), np.zeros_like(w))
+    assert np.all(z == 0)
+    tT = np.arange(T.size, dtype=np.float64).reshape(T.shape)
+    assert np.array_equal(scatter.gather_jvp(T, idx, w, tT, np.zeros_like(w)),
+                          scatter.gather(tT, idx, w))
+    tw = np.linspace(-1, 1, w.size)
+    assert np.array_equal(scatter.gather_jvp(T, idx, w, np.zeros_like(T), tw),
+                          scatter.gather(T, idx, tw))
+    bad = np.array([-1, 20, 3], dtype=np.int64)
+    got = scatter.gather_jvp(T, bad, w[:3], tT, tw[:3])
+    assert np.all(got[:2] == 0) and np.allclose(got[2], tw[2] * T[3] + w[2] * tT[3])
