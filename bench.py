@@ -344,6 +344,22 @@ def row_stencil(torch, dex, workloads, dev, steps):
                             "frac_hbm": round(a / PEAK["hbm"], 4)}
         out[name] = r
         del ck, wsb
+    # forward mode: primal and tangent stepped together, then dL
+    d = dex.stencil_desc(H, W, T, every, 0.2, 0.0, dex.DEX_STENCIL_RECOMPUTE)
+    wsj = dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_JVP), dev)
+    du0 = torch.randn(H, W, device=dev, generator=gen)
+    tL = torch.empty(1, device=dev)
+
+    def jvp():
+        dex.dex_jvp(d, [u0, tg], [du0, tg], [tL], wsj)
+
+    jvp()
+    j_ms = timed(jvp, steps, torch.cuda.synchronize) * 1e3
+    per = j_ms / max(T, 1)
+    a = 4 * H * W * 4 / (per * 1e-3) / 1e9  # u, du read; u', du' written per step
+    out["forward_mode"] = {"jvp_ms": round(j_ms, 3), "avg_ms_per_step": round(per, 5),
+                           "GBps": round(a, 1), "frac_hbm": round(a / PEAK["hbm"], 4)}
+    del wsj
     return out
 
 

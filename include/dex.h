@@ -223,6 +223,12 @@ dex_status dex_vjp(const dex_desc* d,
  *     tout[j, :] = tw[j] T[idx[j], :] + w[j] tT[idx[j], :]
  *     (idx is an integer and has no tangent; rows whose index is outside [0, V)
  *     give zeros, as in dex_fwd).
+ *   DEX_STENCIL5: in = u0[H*W], target[H*W] (as for dex_fwd);
+ *     t_in = du0[H*W], dtarget[H*W];  t_out = dL[1]: the loop is run forward
+ *     with each state's tangent beside it (du_{t+1} = S du_t + rho cos(u_t) du_t,
+ *     S the linear diffusion step), then dL = <u_T - target, du_T - dtarget>
+ *     (summed in FP64, fixed order). Workspace: four H*W fields and the sum's
+ *     partials (DEX_WS_JVP).
  *   Other kinds: DEX_ERR_UNSUPPORTED.
  * All buffers are device memory owned by the caller; t_out is overwritten.
  * Argument errors are reported before anything is enqueued; the call enqueues

@@ -84,3 +84,28 @@ def loss_and_grad(u0: np.ndarray, target: np.ndarray, steps: int, c: float = C,
     for t in range(steps - 1, -1, -1):     # ForTranspose: t = T-1 ... 0
         lam = step_transpose(lam, c, states[t] if rho != 0.0 else None, rho)
     return L, uT, lam
+
+
+def step_tangent(du: np.ndarray, u: np.ndarray, c: float = C, rho: float = 0.0) -> np.ndarray:
+    """Tangent of `step` at u along du (the linearized step, Sec. 5.1): the
+    diffusion part is linear, so it acts on du unchanged; rho sin(u)
+    linearizes to rho cos(u) du, which reads the state u of the same step."""
+    du = np.asarray(du, dtype=np.float64)
+    nb = (np.roll(du, -1, 0) + np.roll(du, 1, 0) + np.roll(du, -1, 1) + np.roll(du, 1, 1))
+    out = du + c * (nb - 4.0 * du)
+    if rho != 0.0:
+        out = out + rho * np.cos(np.asarray(u, dtype=np.float64)) * du
+    return out
+
+
+def loss_jvp(u0: np.ndarray, target: np.ndarray, du0: np.ndarray, dtarget: np.ndarray,
+             steps: int, c: float = C, rho: float = 0.0) -> float:
+    """Forward mode of L = 1/2 ||u_T - target||^2 along (du0, dtarget): every
+    state is stepped together with its tangent, then
+    dL = <u_T - target, du_T - dtarget>."""
+    u = np.asarray(u0, dtype=np.float64)
+    du = np.asarray(du0, dtype=np.float64)
+    for _ in range(steps):
+        u, du = step(u, c, rho), step_tangent(du, u, c, rho)
+    r = u - np.asarray(target, dtype=np.float64)
+    return float(np.sum(r * (du - np.asarray(dtarget, dtype=np.float64))))

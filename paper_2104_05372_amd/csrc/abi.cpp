@@ -227,7 +227,7 @@ static dex_status check_desc(const dex_desc* d) {
 }
 
 static size_t ws_bytes(const dex_desc& d, int role) {
-  if (role == DEX_WS_JVP) return 0;  // forward mode of the gather needs no scratch
+  if (role == DEX_WS_JVP && d.kind != DEX_STENCIL5) return 0;  // (the gather needs none)
   switch (d.kind) {
     case DEX_GMM:
       return gmm_ws_bytes(d, role);
@@ -404,8 +404,25 @@ dex_status dex_jvp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex
   DEX_TRY(check_desc(d));
   if ((n_in && !in) || (n_t_in && !t_in) || (n_t_out && !t_out))
     return fail(DEX_ERR_INVALID_ARG, "null buffer list");
+  if (d->kind == DEX_STENCIL5) {
+    const int64_t n = d->dims[0] * d->dims[1];
+    DEX_TRY(check_count(n_in, 2, "in"));
+    DEX_TRY(want(in, 0, "in", DEX_F32, n));
+    DEX_TRY(want(in, 1, "in", DEX_F32, n));
+    DEX_TRY(check_count(n_t_in, 2, "t_in"));
+    DEX_TRY(want(t_in, 0, "t_in", DEX_F32, n));
+    DEX_TRY(want(t_in, 1, "t_in", DEX_F32, n));
+    DEX_TRY(check_count(n_t_out, 1, "t_out"));
+    DEX_TRY(want(t_out, 0, "t_out", DEX_F32, 1));
+    DEX_TRY(check_ws(*d, DEX_WS_JVP, workspace, ws_bytes_));
+    DEX_TRY(ensure_device());
+    return stencil_jvp(*d, (const float*)in[0].ptr, (const float*)in[1].ptr,
+                       (const float*)t_in[0].ptr, (const float*)t_in[1].ptr,
+                       (float*)t_out[0].ptr, workspace, (hipStream_t)hip_stream);
+  }
   if (d->kind != DEX_GATHER_SCALE)
-    return fail(DEX_ERR_UNSUPPORTED, "forward mode is implemented for DEX_GATHER_SCALE");
+    return fail(DEX_ERR_UNSUPPORTED,
+                "forward mode is implemented for DEX_GATHER_SCALE and DEX_STENCIL5");
   const int64_t V = d->dims[0], R = d->dims[1], n = d->dims[2];
   DEX_TRY(check_count(n_in, 3, "in"));
   DEX_TRY(want(in, 0, "in", DEX_F32, V * R));

@@ -76,6 +76,8 @@ dex_status gather_dw(const float* T, const int32_t* idx, const float* g, int64_t
 dex_status fill_zero(void* p, size_t bytes, hipStream_t s);
 
 // ----------------------------------------------------------- stencil -----
+dex_status stencil_jvp(const dex_desc& d, const float* u0, const float* target, const float* du0,
+                       const float* dtarget, float* tL, void* ws, hipStream_t st);
 size_t stencil_ws_bytes(const dex_desc& d, int role);
 int stencil_num_configs(const dex_desc& d, int role);
 dex_status stencil_fwd(const dex_desc& d, int cfg, const float* u0, const float* target,

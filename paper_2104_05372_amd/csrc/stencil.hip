@@ -218,6 +218,59 @@ __global__ void __launch_bounds__(256) stencil_adj_scatter(const float* __restri
   atomicAdd(&out[(int64_t)y * W + xl], c * gc);
 }
 
+// Forward mode, one step of the primal and its tangent together (the
+// linearized step, Sec. 5.1: the diffusion part is linear, the non-linear term
+// linearizes to rho cos(u) du, which reads the primal state of the same step):
+//   un  = u  + c (sum of the 4 neighbours of u  - 4 u ) + rho sin(u)
+//   dun = du + c (sum of the 4 neighbours of du - 4 du) + rho cos(u) du
+// One cell per thread, periodic indices.
+__global__ void __launch_bounds__(256) stencil_tan_step(const float* __restrict__ u,
+                                                        const float* __restrict__ du,
+                                                        float* __restrict__ un,
+                                                        float* __restrict__ dun, int H, int W,
+                                                        float c, float rho) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)H * W) return;
+  const int y = (int)(t / W), x = (int)(t % W);
+  const int yn = y == 0 ? H - 1 : y - 1, ys = y == H - 1 ? 0 : y + 1;
+  const int xl = x == 0 ? W - 1 : x - 1, xr = x == W - 1 ? 0 : x + 1;
+  const int64_t is = (int64_t)ys * W + x, in = (int64_t)yn * W + x;
+  const int64_t ir = (int64_t)y * W + xr, il = (int64_t)y * W + xl;
+  const float cc = u[t], dc = du[t];
+  float o = cc + c * (((u[is] + u[in]) + u[ir]) + u[il] - 4.f * cc);
+  float d = dc + c * (((du[is] + du[in]) + du[ir]) + du[il] - 4.f * dc);
+  if (rho != 0.f) {
+    o += rho * sinf(cc);
+    d += rho * cosf(cc) * dc;
+  }
+  un[t] = o;
+  dun[t] = d;
+}
+
+// Per-block partial sums of (u - target)(du - dtarget) in FP64: the tangent of
+// L = 1/2 ||u - target||^2.
+__global__ void __launch_bounds__(256) stencil_tan_loss_partial(const float* __restrict__ u,
+                                                                const float* __restrict__ tg,
+                                                                const float* __restrict__ du,
+                                                                const float* __restrict__ dtg,
+                                                                int64_t n,
+                                                                double* __restrict__ part) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    s += ((double)u[i] - (double)tg[i]) * ((double)du[i] - (double)dtg[i]);
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void stencil_sum_final(const double* __restrict__ part, int nb, float* __restrict__ out) {
+  __shared__ double sh[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += part[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[0] = (float)s;
+}
+
 // Per-block partial sums of (u - target)^2 in FP64.
 __global__ void __launch_bounds__(256) stencil_loss_partial(const float* __restrict__ u,
                                                             const float* __restrict__ tg,
@@ -328,6 +381,7 @@ size_t stencil_ws_bytes(const dex_desc& d, int role) {
   St s = st_of(d);
   const size_t fb = align256((size_t)s.n * 4);
   if (role == DEX_WS_FWD) return fb + align256(kLossBlocks * 8);
+  if (role == DEX_WS_JVP) return 4 * fb + align256(kLossBlocks * 8);  // (u, du) ping-pong
   if (role == DEX_WS_VJP) {
     size_t b = 2 * fb;  // cotangent ping-pong
     if (d.variant == DEX_STENCIL_RECOMPUTE) b += (size_t)(s.every > 1 ? s.every - 1 : 0) * fb + fb;
@@ -365,6 +419,31 @@ dex_status stencil_fwd(const dex_desc& d, int cfg, const float* u0, const float*
   hipLaunchKernelGGL(stencil_loss_partial, dim3(kLossBlocks), dim3(256), 0, st, uT, target, s.n, part);
   hipLaunchKernelGGL(stencil_loss_final, dim3(1), dim3(256), 0, st, part, kLossBlocks, L);
   return check_hip(hipGetLastError(), "stencil_fwd");
+}
+
+// Forward mode: tL = <u_T - target, du_T - dtarget>, the primal and tangent
+// states stepped together through the workspace ping-pong buffers.
+dex_status stencil_jvp(const dex_desc& d, const float* u0, const float* target, const float* du0,
+                       const float* dtarget, float* tL, void* ws, hipStream_t st) {
+  St s = st_of(d);
+  const size_t fb = align256((size_t)s.n * 4);
+  float* buf[2][2] = {{(float*)ws, (float*)((char*)ws + fb)},
+                      {(float*)((char*)ws + 2 * fb), (float*)((char*)ws + 3 * fb)}};
+  double* part = (double*)((char*)ws + 4 * fb);
+  const float *u = u0, *du = du0;
+  const unsigned nb = (unsigned)((s.n + 255) / 256);
+  for (int t = 0; t < s.T; ++t) {
+    float* un = buf[t & 1][0];
+    float* dun = buf[t & 1][1];
+    hipLaunchKernelGGL(stencil_tan_step, dim3(nb), dim3(256), 0, st, u, du, un, dun, s.H, s.W, s.c,
+                       s.rho);
+    u = un;
+    du = dun;
+  }
+  hipLaunchKernelGGL(stencil_tan_loss_partial, dim3(kLossBlocks), dim3(256), 0, st, u, target, du,
+                     dtarget, s.n, part);
+  hipLaunchKernelGGL(stencil_sum_final, dim3(1), dim3(256), 0, st, part, kLossBlocks, tL);
+  return check_hip(hipGetLastError(), "stencil_jvp");
 }
 
 // uT_in: the forward's final state (second residual).

@@ -124,3 +124,34 @@ def test_full_size_against_closed_form(dev):
           f"grad rel {rel(du, duo):.2e}", flush=True)
     assert abs(L - Lo) <= 1e-5 * Lo
     assert rel(uT, uTo) <= 1e-5 and rel(du, duo) <= 1e-5
+
+
+def run_jvp(u0, target, du0, dtarget, steps, rho=0.0, dev="cuda"):
+    from paper_2104_05372_amd import dex
+    H, W = u0.shape
+    d = dex.stencil_desc(H, W, steps, max(steps, 1), 0.2, rho, 0)
+    tL = torch.empty(1, device=dev)
+    print(f"  stencil jvp {H}x{W} steps={steps} rho={rho}", flush=True)
+    dex.dex_jvp(d, [torch.tensor(u0, device=dev), torch.tensor(target, device=dev)],
+                [torch.tensor(du0, device=dev), torch.tensor(dtarget, device=dev)], [tL],
+                dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_JVP), dev))
+    torch.cuda.synchronize()
+    return tL.item()
+
+
+@pytest.mark.parametrize("H,W,steps,rho", [(32, 24, 7, 0.0), (9, 13, 11, 0.0), (64, 256, 20, 0.05),
+                                           (40, 36, 40, -0.2), (12, 12, 0, 0.0), (128, 512, 33, 0.0)])
+def test_forward_mode(dev, H, W, steps, rho):
+    """dex_jvp of the loop against the oracle, and the dot-product identity
+    dL(du0, 0) = <grad_u0, du0> against dex_vjp on the same inputs."""
+    u0, tg = workloads.stencil_inputs(H, W, 31)
+    rng = np.random.default_rng(H * W + steps)
+    du0 = rng.standard_normal((H, W)).astype(np.float32)
+    dtg = rng.standard_normal((H, W)).astype(np.float32)
+    got = run_jvp(u0, tg, du0, dtg, steps, rho)
+    want = ost.loss_jvp(u0, tg, du0, dtg, steps, rho=rho)
+    assert abs(got - want) <= 1e-5 * max(abs(want), 1e-30)
+    g = run(u0, tg, steps, max(steps, 1), rho=rho)[2]
+    t0 = run_jvp(u0, tg, du0, np.zeros_like(dtg), steps, rho)
+    ip = float(np.sum(g.astype(np.float64) * du0))
+    assert abs(t0 - ip) <= 1e-5 * np.linalg.norm(g) * np.linalg.norm(du0)

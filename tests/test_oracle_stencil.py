@@ -95,3 +95,38 @@ def test_nonlinear_step_adjoint_identity():
     lin = stencil.step(du) + 0.2 * np.cos(u) * du
     assert np.isclose(np.sum(lin * v), np.sum(du * stencil.step_transpose(v, u=u, rho=0.2)),
                       rtol=1e-13)
+
+
+@pytest.mark.parametrize("rho", [0.0, 0.3])
+def test_loss_jvp_central_differences(rho):
+    rng = np.random.default_rng(21)
+    u0, tg = rng.standard_normal((10, 12)), rng.standard_normal((10, 12))
+    du0, dtg = rng.standard_normal((10, 12)), rng.standard_normal((10, 12))
+    h = 1e-5
+    up = stencil.loss_and_grad(u0 + h * du0, tg + h * dtg, 9, rho=rho)[0]
+    dn = stencil.loss_and_grad(u0 - h * du0, tg - h * dtg, 9, rho=rho)[0]
+    got = stencil.loss_jvp(u0, tg, du0, dtg, 9, rho=rho)
+    assert np.isclose((up - dn) / (2 * h), got, rtol=1e-7, atol=1e-9)
+
+
+@pytest.mark.parametrize("rho", [0.0, -0.2])
+def test_loss_jvp_vjp_dot_product_identity(rho):
+    """<grad_u0, du0> - <u_T - target, dtarget> = dL, against the pinned reverse pass."""
+    rng = np.random.default_rng(22)
+    u0, tg = rng.standard_normal((8, 9)), rng.standard_normal((8, 9))
+    du0, dtg = rng.standard_normal((8, 9)), rng.standard_normal((8, 9))
+    _, uT, g = stencil.loss_and_grad(u0, tg, 13, rho=rho)
+    want = float(np.sum(g * du0) - np.sum((uT - tg) * dtg))
+    assert np.isclose(stencil.loss_jvp(u0, tg, du0, dtg, 13, rho=rho), want, rtol=1e-12)
+
+
+def test_loss_jvp_linear_loop_is_the_loop_of_the_tangent():
+    """With rho = 0 the loop is linear, so the tangent state is the forward loop
+    applied to du0 (and to nothing else)."""
+    rng = np.random.default_rng(23)
+    u0, tg, du0 = (rng.standard_normal((6, 10)) for _ in range(3))
+    uT = stencil.forward(u0, 7)
+    want = float(np.sum((uT - tg) * stencil.forward(du0, 7)))
+    got = stencil.loss_jvp(u0, tg, du0, np.zeros_like(tg), 7)
+    assert np.isclose(got, want, rtol=1e-12)
+    assert stencil.loss_jvp(u0, tg, np.zeros_like(u0), np.zeros_like(tg), 7, rho=0.4) == 0.0
