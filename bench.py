@@ -452,6 +452,27 @@ def main(argv=None):
         "roofline": H["roofline"],
     }
     g = H["g"]
+    if not args.no_rows:
+        # forward mode of the objective along a tangent (the gradients buffer
+        # serves as the tangent): reverse pass with cotangent 1 + inner product
+        S = H["S"]
+        d = S["d"]
+        wsj = dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_JVP), dev)
+        dF = torch.empty(1, device=dev)
+        f = torch.empty(g.N, device=dev)
+        cache = torch.empty(dex.dex_workspace_bytes(d, dex.DEX_WS_RESID), dtype=torch.uint8,
+                            device=dev)
+        dex.dex_fwd(d, S["t"], [S["F"]], [f, cache],
+                    dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_FWD), dev))
+
+        def jvp():
+            dex.dex_jvp(d, S["t"], S["grads"], [dF], wsj, resid=[f, cache])
+
+        jvp()
+        j_ms = timed(jvp, max(3, args.steps // 2), torch.cuda.synchronize) * 1e3
+        line["forward_mode"] = {"jvp_ms": round(j_ms, 4),
+                                "form": "reverse pass with cotangent 1, then <grad F, t> in FP64"}
+        del wsj, cache, S
     del H["S"]
     torch.cuda.empty_cache()
     if args.variant != "fp32":

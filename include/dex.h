@@ -229,12 +229,21 @@ dex_status dex_vjp(const dex_desc* d,
  *     S the linear diffusion step), then dL = <u_T - target, du_T - dtarget>
  *     (summed in FP64, fixed order). Workspace: four H*W fields and the sum's
  *     partials (DEX_WS_JVP).
+ *   DEX_GMM: in = alphas, means, qd, l, x (as for dex_fwd); resid = f, cache from
+ *     dex_fwd with the same descriptor and inputs; t_in = dalphas[K], dmeans[K*D],
+ *     dqd[K*D], dl[K*L]; t_out = dF[1]. F is a scalar, so its derivative along
+ *     t is <grad F, t>: it is formed from the reverse pass (one pass of the
+ *     matrix-core moment kernels with cotangent 1, far cheaper than a second
+ *     forward-sized product over tangent coefficients) and a fixed-order
+ *     inner product with t accumulated in FP64. Workspace: DEX_WS_JVP bytes.
  *   Other kinds: DEX_ERR_UNSUPPORTED.
  * All buffers are device memory owned by the caller; t_out is overwritten.
  * Argument errors are reported before anything is enqueued; the call enqueues
- * on hip_stream and returns. Workspace: DEX_WS_JVP bytes (0 for the gather). */
+ * on hip_stream and returns. resid is empty (n_resid = 0) except for DEX_GMM.
+ * Workspace: DEX_WS_JVP bytes (0 for the gather). */
 dex_status dex_jvp(const dex_desc* d,
                    const dex_buf* in, int32_t n_in,
+                   const dex_buf* resid, int32_t n_resid,
                    const dex_buf* t_in, int32_t n_t_in,
                    dex_buf* t_out, int32_t n_t_out,
                    void* workspace, size_t ws_bytes,

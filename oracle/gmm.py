@@ -122,6 +122,37 @@ def vjp(alphas, means, qd, l, x, f=None, ct: float = 1.0):
     return d_alphas, d_means, d_qd, d_l
 
 
+def jvp(alphas, means, qd, l, x, t, f=None) -> float:
+    """Forward mode: the derivative of F along the tangent t = (dalphas, dmeans,
+    dqd, dl), written as the linearized loop (Sec. 5.1): for each component k,
+    Q = build_Q(qd.k, l.k) has tangent dQ (diagonal exp(qd) dqd, strict lower
+    part dl), y = Q r with r = x - mean.k has tangent dy = dQ r - Q dmean.k,
+    beta.k = alpha.k + sum qd.k - 1/2 y.y has tangent
+    dbeta = dalpha.k + sum dqd.k - y.dy, and the log-sum-exp over k passes on
+    the softmax weights exp(beta - f); the last term of F contributes
+    -N softmax(alphas).dalphas."""
+    alphas, means, qd, l, x = _f64(alphas, means, qd, l, x)
+    da, dm, dq, dl = (np.asarray(a, dtype=np.float64) for a in t)
+    N, D = x.shape
+    K = alphas.shape[0]
+    if f is None:
+        _, f = objective(alphas, means, qd, l, x)
+    f = np.asarray(f, dtype=np.float64)
+    dF = 0.0
+    for k in range(K):
+        Q = build_Q(qd[k], l[k])
+        # strict lower part dl (build_Q with qd = 0 puts ones on the diagonal)
+        dQ = build_Q(np.zeros(D), dl[k]) - np.eye(D) + np.diag(np.exp(qd[k]) * dq[k])
+        r = x - means[k]
+        y = r @ Q.T
+        dy = r @ dQ.T - Q @ dm[k]
+        bk = alphas[k] + qd[k].sum() - 0.5 * np.sum(y * y, axis=1)
+        dbk = da[k] + dq[k].sum() - np.sum(y * dy, axis=1)
+        dF += float(np.sum(np.exp(bk - f) * dbk))
+    sm = np.exp(alphas - logsumexp(alphas))
+    return dF - N * float(np.dot(sm, da))
+
+
 def suff_stats(alphas, means, qd, l, x, f, ct: float = 1.0, ks=None):
     """Per-component weighted sums behind the gradient, for sampled checks:
     A_k = sum_i w_ik, b_k = sum_i w_ik y_ik, M_k = sum_i w_ik y_ik r_ik^T."""

@@ -227,7 +227,7 @@ static dex_status check_desc(const dex_desc* d) {
 }
 
 static size_t ws_bytes(const dex_desc& d, int role) {
-  if (role == DEX_WS_JVP && d.kind != DEX_STENCIL5) return 0;  // (the gather needs none)
+  if (role == DEX_WS_JVP && d.kind == DEX_GATHER_SCALE) return 0;  // (the gather needs none)
   switch (d.kind) {
     case DEX_GMM:
       return gmm_ws_bytes(d, role);
@@ -398,12 +398,40 @@ dex_status dex_fwd(const dex_desc* d, const dex_buf* in, int32_t n_in, dex_buf* 
   return fail(DEX_ERR_INVALID_ARG, "unknown kind");
 }
 
-dex_status dex_jvp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex_buf* t_in,
-                   int32_t n_t_in, dex_buf* t_out, int32_t n_t_out, void* workspace,
-                   size_t ws_bytes_, void* hip_stream) {
+dex_status dex_jvp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex_buf* resid,
+                   int32_t n_resid, const dex_buf* t_in, int32_t n_t_in, dex_buf* t_out,
+                   int32_t n_t_out, void* workspace, size_t ws_bytes_, void* hip_stream) {
   DEX_TRY(check_desc(d));
-  if ((n_in && !in) || (n_t_in && !t_in) || (n_t_out && !t_out))
+  if ((n_in && !in) || (n_resid && !resid) || (n_t_in && !t_in) || (n_t_out && !t_out))
     return fail(DEX_ERR_INVALID_ARG, "null buffer list");
+  if (d->kind == DEX_GMM) {
+    const int64_t N = d->dims[0], D = d->dims[1], K = d->dims[2], L = D * (D - 1) / 2;
+    const int32_t t = d->dtype;
+    DEX_TRY(check_count(n_in, 5, "in"));
+    DEX_TRY(want(in, 0, "in", t, K));
+    DEX_TRY(want(in, 1, "in", t, K * D));
+    DEX_TRY(want(in, 2, "in", t, K * D));
+    DEX_TRY(want(in, 3, "in", t, K * L));
+    DEX_TRY(want(in, 4, "in", t, N * D));
+    DEX_TRY(check_count(n_resid, 2, "resid"));
+    DEX_TRY(want(resid, 0, "resid", t, N));
+    DEX_TRY(want(resid, 1, "resid", DEX_U8, (int64_t)gmm_cache_bytes(*d)));
+    DEX_TRY(check_count(n_t_in, 4, "t_in"));
+    DEX_TRY(want(t_in, 0, "t_in", t, K));
+    DEX_TRY(want(t_in, 1, "t_in", t, K * D));
+    DEX_TRY(want(t_in, 2, "t_in", t, K * D));
+    DEX_TRY(want(t_in, 3, "t_in", t, K * L));
+    DEX_TRY(check_count(n_t_out, 1, "t_out"));
+    DEX_TRY(want(t_out, 0, "t_out", t, 1));
+    DEX_TRY(check_ws(*d, DEX_WS_JVP, workspace, ws_bytes_));
+    DEX_TRY(ensure_device());
+    const int cfg = pick_config(*d, DEX_WS_VJP);
+    GmmPtrs p{in[0].ptr, in[1].ptr, in[2].ptr, in[3].ptr, in[4].ptr};
+    GmmGrads tg{t_in[0].ptr, t_in[1].ptr, t_in[2].ptr, t_in[3].ptr};
+    return gmm_jvp(*d, cfg, p, resid[0].ptr, resid[1].ptr, tg, t_out[0].ptr, workspace,
+                   (hipStream_t)hip_stream);
+  }
+  if (n_resid != 0) return fail(DEX_ERR_INVALID_ARG, "no residuals for this kind");
   if (d->kind == DEX_STENCIL5) {
     const int64_t n = d->dims[0] * d->dims[1];
     DEX_TRY(check_count(n_in, 2, "in"));
@@ -422,7 +450,7 @@ dex_status dex_jvp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex
   }
   if (d->kind != DEX_GATHER_SCALE)
     return fail(DEX_ERR_UNSUPPORTED,
-                "forward mode is implemented for DEX_GATHER_SCALE and DEX_STENCIL5");
+                "forward mode is implemented for DEX_GMM, DEX_GATHER_SCALE and DEX_STENCIL5");
   const int64_t V = d->dims[0], R = d->dims[1], n = d->dims[2];
   DEX_TRY(check_count(n_in, 3, "in"));
   DEX_TRY(want(in, 0, "in", DEX_F32, V * R));

@@ -250,6 +250,49 @@ __global__ void __launch_bounds__(256) k_mom_reduce(float* __restrict__ part, in
 }
 
 template <typename T>
+__global__ void k_set_one(T* __restrict__ p) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) p[0] = (T)1;
+}
+
+// Block partials (FP64, fixed grid and order) of sum_j g[j] t[j], with g the
+// concatenation of four segments and t the four separate tangent arrays.
+template <typename T>
+__global__ void __launch_bounds__(256) k_dot4_partial(const T* __restrict__ g, int64_t n0,
+                                                      int64_t n1, int64_t n2, int64_t n3,
+                                                      const T* __restrict__ t0,
+                                                      const T* __restrict__ t1,
+                                                      const T* __restrict__ t2,
+                                                      const T* __restrict__ t3,
+                                                      double* __restrict__ part) {
+  __shared__ double sh[32];
+  const int64_t n = n0 + n1 + n2 + n3;
+  double acc = 0.0;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+    T tv;
+    if (j < n0)
+      tv = t0[j];
+    else if (j < n0 + n1)
+      tv = t1[j - n0];
+    else if (j < n0 + n1 + n2)
+      tv = t2[j - n0 - n1];
+    else
+      tv = t3[j - n0 - n1 - n2];
+    acc += (double)g[j] * (double)tv;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+template <typename T>
+__global__ void k_dot_final(const double* __restrict__ part, int nb, T* __restrict__ out) {
+  __shared__ double sh[32];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[i];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[0] = (T)acc;
+}
+
+template <typename T>
 __global__ void __launch_bounds__(256) k_finalize_F(const T* __restrict__ fpart, int nparts,
                                                     const T* __restrict__ alphas, int K, int64_t N,
                                                     T* __restrict__ F) {
@@ -445,10 +488,23 @@ size_t gmm_cache_bytes(const dex_desc& d) {
   return cache_layout(s).total;
 }
 
+constexpr int kDotBlocks = 64;
+size_t gmm_ws_bytes(const dex_desc& d, int role);
+
+// Forward-mode workspace: the reverse pass's, then the gradient (alphas, means,
+// qd, l concatenated), the cotangent 1, the inner product's block partials.
+static size_t jvp_grad_offset(const dex_desc& d) { return align256(gmm_ws_bytes(d, DEX_WS_VJP)); }
+static size_t jvp_grad_bytes(const Shape& s) {
+  const size_t K = s.g.K, D = s.g.D;
+  return align256(K * (1 + 2 * D + D * (D - 1) / 2) * s.tsize);
+}
+
 size_t gmm_ws_bytes(const dex_desc& d, int role) {
   Shape s = shape_of(d);
   if (!valid_shape(s)) return 0;
   if (role == DEX_WS_RESID) return cache_layout(s).total;
+  if (role == DEX_WS_JVP)
+    return jvp_grad_offset(d) + jvp_grad_bytes(s) + 256 + align256(kDotBlocks * 8);
   const size_t nparts = (size_t)(s.g.Npad / 64);  // objective partials (one per 64 points)
   if (role == DEX_WS_FWD) {
     size_t b = align256(nparts * 2 * s.tsize);
@@ -589,6 +645,35 @@ dex_status gmm_vjp(const dex_desc& d, int cfg, const GmmPtrs& in, const void* f,
                      (float*)out.d_alphas, (float*)out.d_means, (float*)out.d_qd, (float*)out.d_l,
                      accumulate ? 1 : 0);
   return check_hip(hipGetLastError(), "gmm_vjp (MFMA)");
+}
+
+template <typename T>
+static dex_status gmm_jvp_t(const Shape& s, const dex_desc& d, int cfg, const GmmPtrs& in,
+                            const void* f, const void* cache, const GmmGrads& t, void* dF,
+                            void* ws, hipStream_t st) {
+  const int64_t K = s.g.K, D = s.g.D, L = D * (D - 1) / 2;
+  char* gb = (char*)ws + jvp_grad_offset(d);
+  T* g = (T*)gb;
+  T* ct = (T*)(gb + jvp_grad_bytes(s));
+  double* part = (double*)((char*)ct + 256);
+  hipLaunchKernelGGL((k_set_one<T>), dim3(1), dim3(64), 0, st, ct);
+  const GmmGrads gr{g, g + K, g + K + K * D, g + K + 2 * K * D};
+  const dex_status r = gmm_vjp(d, cfg, in, f, cache, ct, gr, false, ws, st);
+  if (r != DEX_OK) return r;
+  hipLaunchKernelGGL((k_dot4_partial<T>), dim3(kDotBlocks), dim3(256), 0, st, (const T*)g, K,
+                     K * D, K * D, K * L, (const T*)t.d_alphas, (const T*)t.d_means,
+                     (const T*)t.d_qd, (const T*)t.d_l, part);
+  hipLaunchKernelGGL((k_dot_final<T>), dim3(1), dim3(256), 0, st, (const double*)part, kDotBlocks,
+                     (T*)dF);
+  return check_hip(hipGetLastError(), "gmm_jvp");
+}
+
+dex_status gmm_jvp(const dex_desc& d, int cfg, const GmmPtrs& in, const void* f,
+                   const void* cache, const GmmGrads& t, void* dF, void* ws, hipStream_t st) {
+  Shape s = shape_of(d);
+  if (!valid_shape(s)) return fail(DEX_ERR_UNSUPPORTED, "GMM shape/dtype/variant not supported");
+  if (s.tsize == 8) return gmm_jvp_t<double>(s, d, cfg, in, f, cache, t, dF, ws, st);
+  return gmm_jvp_t<float>(s, d, cfg, in, f, cache, t, dF, ws, st);
 }
 
 }  // namespace dexi

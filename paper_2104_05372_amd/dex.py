@@ -85,7 +85,7 @@ def lib():
         L.dex_fwd.restype = S
         L.dex_vjp.argtypes = [DP, BP, I32, BP, I32, BP, I32, BP, I32, ctypes.c_uint32, P, SZ, P]
         L.dex_vjp.restype = S
-        L.dex_jvp.argtypes = [DP, BP, I32, BP, I32, BP, I32, P, SZ, P]
+        L.dex_jvp.argtypes = [DP, BP, I32, BP, I32, BP, I32, BP, I32, P, SZ, P]
         L.dex_jvp.restype = S
         L.dex_accum_scatter.argtypes = [P, I32, I64, I64, P, I32, P, P, I64, ctypes.c_uint32, P, P, SZ, P]
         L.dex_accum_scatter.restype = S
@@ -213,14 +213,17 @@ def dex_fwd(d: DexDesc, ins, outs, resid, ws: torch.Tensor | None = None, stream
 
 
 def dex_jvp(d: DexDesc, ins, t_in, t_out, ws: torch.Tensor | None = None, stream=None,
-            dtypes=None):
-    """Forward mode: t_out = the linearization of f at ins applied to t_in."""
+            resid=(), dtypes=None):
+    """Forward mode: t_out = the linearization of f at ins applied to t_in
+    (resid: dex_fwd's residuals, for DEX_GMM)."""
     a, na = bufs(ins, dtypes and dtypes.get("in"))
+    r, nr = bufs(list(resid), dtypes and dtypes.get("resid"))
     ti, nti = bufs(t_in)
     to, nto = bufs(t_out)
     wp = ctypes.c_void_p(ws.data_ptr()) if ws is not None else None
     wb = ws.numel() if ws is not None else 0
-    check(lib().dex_jvp(ctypes.byref(d), a, na, ti, nti, to, nto, wp, wb, stream_ptr(stream)))
+    check(lib().dex_jvp(ctypes.byref(d), a, na, r, nr, ti, nti, to, nto, wp, wb,
+                        stream_ptr(stream)))
 
 
 def dex_vjp(d: DexDesc, ins, resid, ct_out, ct_in, flags=0, ws: torch.Tensor | None = None,

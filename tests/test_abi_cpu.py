@@ -71,9 +71,10 @@ def test_invalid_descriptors_rejected_on_host(dex):
 
 
 def test_forward_mode_argument_checks(dex):
-    """dex_jvp: kinds without forward mode are unsupported; missing or
-    mis-sized gather buffers are rejected on the host, before any device work."""
-    assert _status(dex.dex_jvp, dex.gmm_desc(100, 4, 3), [], [], [], None) == dex.DEX_ERR_UNSUPPORTED
+    """dex_jvp: missing or mis-sized buffers are rejected on the host, before any
+    device work; residuals are refused where the kind has none."""
+    # the GMM form needs the forward's residuals and four tangents
+    assert _status(dex.dex_jvp, dex.gmm_desc(100, 4, 3), [], [], [], None) == dex.DEX_ERR_INVALID_ARG
     d = dex.gather_desc(10, 4, 5)
     assert _status(dex.dex_jvp, d, [], [], [], None) == dex.DEX_ERR_INVALID_ARG
     import torch
@@ -83,6 +84,10 @@ def test_forward_mode_argument_checks(dex):
     assert _status(dex.dex_jvp, d, [T, idx, w], [tT, tw], [torch.zeros(5, 3)], None) \
         == dex.DEX_ERR_INVALID_ARG
     assert dex.dex_workspace_bytes(d, dex.DEX_WS_JVP) == 0
+    assert _status(lambda: dex.dex_jvp(d, [T, idx, w], [tT, tw], [out], None, resid=[out])) \
+        == dex.DEX_ERR_INVALID_ARG
+    gd = dex.gmm_desc(100_000, 64, 200, dex.DEX_F32, dex.DEX_GMM_BF16)
+    assert dex.dex_workspace_bytes(gd, dex.DEX_WS_JVP) > dex.dex_workspace_bytes(gd, dex.DEX_WS_VJP)
 
 
 def test_accum_scatter_argument_checks(dex):

@@ -179,3 +179,53 @@ def test_full_size_bf16_and_fp32(dev):
         print(f"  full size variant {variant}: F rel {abs(got[0]-want[0])/abs(want[0]):.3e} "
               f"f rel {rel(got[1], want[1]):.3e} grads {errs}", flush=True)
         check(got, want, tol, f"full size v{variant}")
+
+
+def run_gmm_jvp(g, dtype, variant, tangent, dev="cuda"):
+    """dex_fwd, then dex_jvp along `tangent`; returns (dF, the forward's F)."""
+    from paper_2104_05372_amd import dex
+    tdt = torch.float64 if dtype == dex.DEX_F64 else torch.float32
+    t = [torch.tensor(np.ascontiguousarray(a), dtype=tdt, device=dev).contiguous()
+         for a in (g.alphas, g.means, g.qd, g.l, g.x)]
+    tt = [torch.tensor(np.ascontiguousarray(a), dtype=tdt, device=dev).reshape(-1)
+          for a in tangent]
+    N, D, K = g.N, g.D, g.K
+    d = dex.gmm_desc(N, D, K, dtype, variant)
+    F = torch.empty(1, dtype=tdt, device=dev)
+    f = torch.empty(N, dtype=tdt, device=dev)
+    cache = torch.empty(dex.dex_workspace_bytes(d, dex.DEX_WS_RESID), dtype=torch.uint8, device=dev)
+    print(f"  gmm jvp N={N} D={D} K={K} dtype={dtype} variant={variant}", flush=True)
+    dex.dex_fwd(d, t, [F], [f, cache], dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_FWD), dev))
+    dF = torch.empty(1, dtype=tdt, device=dev)
+    dex.dex_jvp(d, t, tt, [dF], dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_JVP), dev),
+                resid=[f, cache])
+    torch.cuda.synchronize()
+    return float(dF.item()), float(F.item())
+
+
+@pytest.mark.parametrize("N,D,K,variant,tol", [(3000, 8, 5, 0, 1e-5), (2500, 64, 9, 1, TOL_BF16),
+                                                (2000, 20, 7, 2, TOL_BF16X3), (1500, 64, 33, 0, 1e-5)])
+def test_forward_mode(dev, N, D, K, variant, tol):
+    """dex_jvp of the objective against the oracle's forward mode, with the error
+    measured against |grad F| |t| (the scale of <grad F, t>)."""
+    from paper_2104_05372_amd import dex
+    g = workloads.gmm_inputs(N, D, K, 40 + D, np.float32)
+    rng = np.random.default_rng(D + K)
+    tangent = [rng.standard_normal(np.shape(a)).astype(np.float32)
+               for a in (g.alphas, g.means, g.qd, g.l)]
+    got, _ = run_gmm_jvp(g, dex.DEX_F32, variant, tangent)
+    want = ogmm.jvp(*g.params(), g.x, tangent)
+    go = ogmm.vjp(*g.params(), g.x)
+    scale = np.sqrt(sum(float(np.sum(np.square(a))) for a in go)) * \
+        np.sqrt(sum(float(np.sum(np.square(b))) for b in tangent))
+    assert abs(got - want) <= tol * scale, (got, want, scale)
+
+
+def test_forward_mode_fp64(dev):
+    from paper_2104_05372_amd import dex
+    g = workloads.gmm_inputs(400, 3, 4, 9, np.float64)
+    rng = np.random.default_rng(3)
+    tangent = [rng.standard_normal(np.shape(a)) for a in (g.alphas, g.means, g.qd, g.l)]
+    got, _ = run_gmm_jvp(g, dex.DEX_F64, 0, tangent)
+    want = ogmm.jvp(*g.params(), g.x, tangent)
+    assert abs(got - want) <= 1e-10 * max(1.0, abs(want))

@@ -235,3 +235,38 @@ def test_planted_linear_diagonal_is_caught(monkeypatch):
     monkeypatch.setattr(gmm, "build_Q", bad)
     F, _ = gmm.objective(*g.params(), g.x)
     assert abs(F - scipy_objective(g)) > 1e-6 * abs(F)
+
+
+def _tangent(g, seed):
+    rng = np.random.default_rng(seed)
+    return tuple(rng.standard_normal(np.shape(a)) for a in (g.alphas, g.means, g.qd, g.l))
+
+
+@pytest.mark.parametrize("N,D,K,seed", [(40, 3, 4, 1), (25, 5, 2, 2), (30, 1, 3, 3)])
+def test_jvp_central_differences(N, D, K, seed):
+    g = workloads.gmm_inputs(N, D, K, seed, np.float64)
+    t = _tangent(g, seed)
+    h = 1e-6
+    args = (g.alphas, g.means, g.qd, g.l)
+    up = gmm.objective(*(a + h * b for a, b in zip(args, t)), g.x)[0]
+    dn = gmm.objective(*(a - h * b for a, b in zip(args, t)), g.x)[0]
+    got = gmm.jvp(*args, g.x, t)
+    assert np.isclose((up - dn) / (2 * h), got, rtol=1e-6, atol=1e-8)
+
+
+@pytest.mark.parametrize("N,D,K,seed", [(50, 4, 3, 4), (20, 6, 5, 5)])
+def test_jvp_vjp_dot_product_identity(N, D, K, seed):
+    """<J t, 1> = <t, J^T 1>: forward mode against the pinned reverse pass."""
+    g = workloads.gmm_inputs(N, D, K, seed, np.float64)
+    t = _tangent(g, seed + 10)
+    grads = gmm.vjp(g.alphas, g.means, g.qd, g.l, g.x)
+    rhs = sum(float(np.sum(np.asarray(a) * b)) for a, b in zip(grads, t))
+    assert np.isclose(gmm.jvp(g.alphas, g.means, g.qd, g.l, g.x, t), rhs, rtol=1e-10)
+
+
+def test_jvp_along_a_uniform_alpha_shift_is_zero():
+    """F is invariant under alphas -> alphas + c (the log-sum-exp terms and the
+    normaliser move together), so the derivative along (1, .., 1) vanishes."""
+    g = workloads.gmm_inputs(30, 3, 4, 6, np.float64)
+    t = (np.ones(4), np.zeros_like(g.means), np.zeros_like(g.qd), np.zeros_like(g.l))
+    assert abs(gmm.jvp(g.alphas, g.means, g.qd, g.l, g.x, t)) < 1e-9
