@@ -363,6 +363,28 @@ def row_stencil(torch, dex, workloads, dev, steps):
     return out
 
 
+def row_reduce(torch, dex, workloads, dev, steps):
+    """Regular segmented reduction (2^20 rows of 128) and complete reduction
+    (2^28 values), FP32 in, FP64 sums."""
+    gen = torch.Generator(device=dev).manual_seed(5)
+    rows, cols, n = 1 << 20, 128, 1 << 28
+    v = torch.randn(rows, cols, device=dev, generator=gen)
+    out = torch.empty(rows, device=dev)
+    seg_ms = timed(lambda: dex.dex_reduce_rows(out, v), steps, torch.cuda.synchronize) * 1e3
+    del v, out
+    w = torch.randn(n, device=dev, generator=gen)
+    o1 = torch.empty(1, device=dev)
+    ws = torch.empty(dex.DEX_REDUCE_WS_BYTES, dtype=torch.uint8, device=dev)
+    all_ms = timed(lambda: dex.dex_reduce_all(o1, w, ws), steps, torch.cuda.synchronize) * 1e3
+    del w
+    res = {"workload": f"segmented {rows}x{cols} f32 -> {rows}; complete {n} f32 -> 1"}
+    for k, ms, b in (("segmented", seg_ms, 4 * rows * cols + 4 * rows), ("complete", all_ms, 4 * n)):
+        a = b / (ms * 1e-3) / 1e9
+        res[k] = {"ms": round(ms, 4), "GBps": round(a, 1), "frac_hbm": round(a / PEAK["hbm"], 4),
+                  "bytes": b}
+    return res
+
+
 # ---------------------------------------------------------------------------
 def cpu_baseline(torch, dex, workloads, g, variant, dev):
     """The FP64 oracle on two point-subsamples of the benchmark instance (all
@@ -484,8 +506,9 @@ def main(argv=None):
     if not args.no_rows:
         rows = {}
         sel = args.rows_only.split(",") if args.rows_only else ["scatter", "scatter_det", "hist", "batched",
-                                                                "stencil"]
+                                                                "stencil", "reduce"]
         fns = {"scatter": row_scatter, "hist": row_histogram, "batched": row_batched, "stencil": row_stencil,
+               "reduce": row_reduce,
                "scatter_det": lambda *a: row_scatter(*a, scatter_config=2)}
         for name in sel:
             log("row", name)

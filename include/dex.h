@@ -249,6 +249,25 @@ dex_status dex_jvp(const dex_desc* d,
                    void* workspace, size_t ws_bytes,
                    void* hip_stream);
 
+/* Regular segmented reduction (Sec. 6.1.3: the accumulator indexed by a subset
+ * of the loop indices, `for i j. acc!i += values.i.j`):
+ *   out[i] (= or, with DEX_ACCUMULATE, +=) sum_j values[i, j],  i < rows, j < cols
+ * values: device, rows x cols FP32 row-major; out: device, rows FP32. Each row
+ * is summed by a fixed group of lanes in FP64 in a fixed order (bit-reproducible). rows = 0
+ * does nothing; cols = 0 gives zero sums. Negative sizes or null pointers with
+ * rows > 0: DEX_ERR_INVALID_ARG, before anything is enqueued. */
+dex_status dex_reduce_rows(float* out, const float* values, int64_t rows, int64_t cols,
+                           uint32_t flags, void* hip_stream);
+
+/* Complete reduction (Sec. 6.1.3: the accumulator never indexed,
+ * `for i. acc += values.i`): out[0] (= or += with DEX_ACCUMULATE) sum_i values[i].
+ * values: device, n FP32; out: device, one FP32. Per-block FP64 partial sums over
+ * a fixed grid, then one block adds them in order (bit-reproducible).
+ * workspace: device scratch of at least DEX_REDUCE_WS_BYTES bytes. */
+#define DEX_REDUCE_WS_BYTES 8192
+dex_status dex_reduce_all(float* out, const float* values, int64_t n, uint32_t flags,
+                          void* workspace, size_t ws_bytes, void* hip_stream);
+
 /*
  * acc!(idx[j]) += scale[j] * vals[j, :]  for j in [0, n)      (Sec. 2.3.2-2.3.3)
  *

@@ -31,6 +31,7 @@ UNITS = [
     ("gmm_batched.hip", [], "gmm_batched.o"),
     ("scatter.hip", [], "scatter.o"),
     ("stencil.hip", [], "stencil.o"),
+    ("reduce.hip", [], "reduce.o"),
 ]
 
 # -packed-fp32-ops: no packed FP32 instructions are generated (they are kept

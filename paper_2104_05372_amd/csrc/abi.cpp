@@ -469,6 +469,28 @@ dex_status dex_jvp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex
                     (float*)t_out[0].ptr, s);
 }
 
+dex_status dex_reduce_rows(float* out, const float* values, int64_t rows, int64_t cols,
+                           uint32_t flags, void* hip_stream) {
+  if (rows < 0 || cols < 0) return fail(DEX_ERR_INVALID_ARG, "negative size");
+  if (rows > 0 && (!out || (cols > 0 && !values))) return fail(DEX_ERR_INVALID_ARG, "null buffer");
+  if (flags & ~DEX_ACCUMULATE) return fail(DEX_ERR_INVALID_ARG, "unknown flags");
+  if (rows == 0) return DEX_OK;
+  DEX_TRY(ensure_device());
+  return reduce_rows(out, values, rows, cols, flags & DEX_ACCUMULATE, (hipStream_t)hip_stream);
+}
+
+dex_status dex_reduce_all(float* out, const float* values, int64_t n, uint32_t flags,
+                          void* workspace, size_t ws_bytes_, void* hip_stream) {
+  if (n < 0) return fail(DEX_ERR_INVALID_ARG, "negative size");
+  if (!out || (n > 0 && !values)) return fail(DEX_ERR_INVALID_ARG, "null buffer");
+  if (flags & ~DEX_ACCUMULATE) return fail(DEX_ERR_INVALID_ARG, "unknown flags");
+  static_assert(kReduceBlocks * 8 <= DEX_REDUCE_WS_BYTES, "partials fit the documented workspace");
+  if (!workspace || ws_bytes_ < DEX_REDUCE_WS_BYTES)
+    return fail(DEX_ERR_WORKSPACE, "workspace of %d bytes needed", DEX_REDUCE_WS_BYTES);
+  DEX_TRY(ensure_device());
+  return reduce_all(out, values, n, flags & DEX_ACCUMULATE, workspace, (hipStream_t)hip_stream);
+}
+
 dex_status dex_vjp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex_buf* resid,
                    int32_t n_resid, const dex_buf* ct_out, int32_t n_ct_out, dex_buf* ct_in,
                    int32_t n_ct_in, uint32_t flags, void* workspace, size_t ws_bytes_,

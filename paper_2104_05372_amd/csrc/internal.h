@@ -79,6 +79,13 @@ dex_status gather_dw(const float* T, const int32_t* idx, const float* g, int64_t
                      int64_t n, float* dw, bool accumulate, hipStream_t s);
 dex_status fill_zero(void* p, size_t bytes, hipStream_t s);
 
+// ------------------------------------------------------- reductions -----
+constexpr int kReduceBlocks = 1024;  // complete reduction: partials (FP64) per call
+dex_status reduce_rows(float* out, const float* values, int64_t rows, int64_t cols,
+                       bool accumulate, hipStream_t s);
+dex_status reduce_all(float* out, const float* values, int64_t n, bool accumulate, void* ws,
+                      hipStream_t s);
+
 // ----------------------------------------------------------- stencil -----
 dex_status stencil_jvp(const dex_desc& d, const float* u0, const float* target, const float* du0,
                        const float* dtarget, float* tL, void* ws, hipStream_t st);

@@ -37,7 +37,8 @@ DEX_WS_FWD, DEX_WS_VJP, DEX_WS_RESID, DEX_WS_JVP = 0, 1, 2, 3
 
 EXPORTS = (
     "dex_status_string", "dex_last_error", "dex_version", "dex_init", "dex_workspace_bytes",
-    "dex_num_configs", "dex_fwd", "dex_vjp", "dex_jvp", "dex_accum_scatter",
+    "dex_num_configs", "dex_fwd", "dex_vjp", "dex_jvp", "dex_reduce_rows", "dex_reduce_all",
+    "dex_accum_scatter",
     "dex_accum_scatter_workspace_bytes", "dex_gmm_batched_plan", "dex_autotune",
     "dex_autotune_reset", "dex_profile_enable", "dex_profile_read", "dex_profile_reset",
 )
@@ -87,6 +88,10 @@ def lib():
         L.dex_vjp.restype = S
         L.dex_jvp.argtypes = [DP, BP, I32, BP, I32, BP, I32, BP, I32, P, SZ, P]
         L.dex_jvp.restype = S
+        L.dex_reduce_rows.argtypes = [P, P, I64, I64, ctypes.c_uint32, P]
+        L.dex_reduce_rows.restype = S
+        L.dex_reduce_all.argtypes = [P, P, I64, ctypes.c_uint32, P, SZ, P]
+        L.dex_reduce_all.restype = S
         L.dex_accum_scatter.argtypes = [P, I32, I64, I64, P, I32, P, P, I64, ctypes.c_uint32, P, P, SZ, P]
         L.dex_accum_scatter.restype = S
         L.dex_accum_scatter_workspace_bytes.argtypes = [I32, I64, I64, I64, I32, ctypes.c_uint32,
@@ -224,6 +229,26 @@ def dex_jvp(d: DexDesc, ins, t_in, t_out, ws: torch.Tensor | None = None, stream
     wb = ws.numel() if ws is not None else 0
     check(lib().dex_jvp(ctypes.byref(d), a, na, r, nr, ti, nti, to, nto, wp, wb,
                         stream_ptr(stream)))
+
+
+DEX_REDUCE_WS_BYTES = 8192
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def dex_reduce_rows(out: torch.Tensor, values: torch.Tensor, flags=0, stream=None):
+    """out[i] (=|+=) sum_j values[i, j] for a 2-D float32 `values`."""
+    rows, cols = values.shape
+    check(lib().dex_reduce_rows(_ptr(out), _ptr(values), rows, cols, flags, stream_ptr(stream)))
+
+
+def dex_reduce_all(out: torch.Tensor, values: torch.Tensor, ws: torch.Tensor, flags=0,
+                   stream=None):
+    """out[0] (=|+=) sum of all of float32 `values`; ws: DEX_REDUCE_WS_BYTES bytes."""
+    check(lib().dex_reduce_all(_ptr(out), _ptr(values), values.numel(), flags, _ptr(ws),
+                               ws.numel() if ws is not None else 0, stream_ptr(stream)))
 
 
 def dex_vjp(d: DexDesc, ins, resid, ct_out, ct_in, flags=0, ws: torch.Tensor | None = None,

@@ -161,3 +161,17 @@ def test_package_has_no_oracle_dependency():
             if fn.endswith((".py", ".hip", ".cpp", ".h")):
                 src = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in src and "from oracle" not in src, fn
+
+
+def test_reduction_argument_checks(dex):
+    """Bad sizes, null buffers, unknown flags and a short workspace are rejected on
+    the host; an empty segmented reduction is a no-op that needs no device."""
+    L = dex.lib()
+    assert L.dex_reduce_rows(None, None, -1, 4, 0, None) == dex.DEX_ERR_INVALID_ARG
+    assert L.dex_reduce_rows(None, None, 3, 4, 0, None) == dex.DEX_ERR_INVALID_ARG
+    assert L.dex_reduce_rows(ctypes.c_void_p(16), ctypes.c_void_p(16), 3, 4, 64, None) \
+        == dex.DEX_ERR_INVALID_ARG
+    assert L.dex_reduce_rows(None, None, 0, 4, 0, None) == dex.DEX_OK
+    assert L.dex_reduce_all(None, None, 5, 0, None, 0, None) == dex.DEX_ERR_INVALID_ARG
+    assert L.dex_reduce_all(ctypes.c_void_p(16), ctypes.c_void_p(16), 5, 0, ctypes.c_void_p(16), 16,
+                            None) == dex.DEX_ERR_WORKSPACE
