@@ -351,7 +351,9 @@ void dex_autotune_reset(void);
 #define DEX_PROF_STENCIL_FWD  8 /* forward steps (one range per dex_fwd)      */
 #define DEX_PROF_STENCIL_VJP  9 /* reverse steps incl. recompute (per dex_vjp) */
 #define DEX_PROF_GATHER_JVP  10 /* gather-scale forward mode (dex_jvp)        */
-#define DEX_PROF_COUNT       11
+#define DEX_PROF_REDUCE_ROWS 11 /* regular segmented reduction                */
+#define DEX_PROF_REDUCE_ALL  12 /* complete reduction (both passes)           */
+#define DEX_PROF_COUNT       13
 void dex_profile_enable(int32_t on);
 dex_status dex_profile_read(int32_t id, double* total_ms, int64_t* launches);
 void dex_profile_reset(void);

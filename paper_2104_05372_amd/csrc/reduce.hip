@@ -96,6 +96,7 @@ dex_status reduce_rows(float* out, const float* values, int64_t rows, int64_t co
   int G = 4;  // lanes per row: about 8 values each
   while (G < 64 && 8 * G < cols) G *= 2;
   const unsigned blocks = (unsigned)((rows * G + 255) / 256);
+  ProfRange pr(DEX_PROF_REDUCE_ROWS, s);
 #define DEX_RR(g)                                                                             \
   case g:                                                                                     \
     hipLaunchKernelGGL((reduce_rows_kernel<g>), dim3(blocks), dim3(256), 0, s, values, rows, \
@@ -109,6 +110,7 @@ dex_status reduce_rows(float* out, const float* values, int64_t rows, int64_t co
     DEX_RR(64)
   }
 #undef DEX_RR
+  pr.end(1);
   return check_hip(hipGetLastError(), "reduce_rows");
 }
 
@@ -117,9 +119,11 @@ dex_status reduce_all(float* out, const float* values, int64_t n, bool accumulat
   double* part = (double*)ws;
   const int nb = kReduceBlocks;
   const bool vec = ((uintptr_t)values & 15) == 0;
+  ProfRange pr(DEX_PROF_REDUCE_ALL, s);
   hipLaunchKernelGGL(reduce_all_partial, dim3(nb), dim3(256), 0, s, values, n, vec, part);
   hipLaunchKernelGGL(reduce_all_final, dim3(1), dim3(256), 0, s, (const double*)part, nb,
                      accumulate, out);
+  pr.end(1);
   return check_hip(hipGetLastError(), "reduce_all");
 }
 
