@@ -168,13 +168,3 @@ def suff_stats(alphas, means, qd, l, x, f, ct: float = 1.0, ks=None):
         w = ct * np.exp(bk - f)
         out[k] = (w.sum(), (w[:, None] * y).sum(0), (w[:, None] * y).T @ r)
     return out
-
-
-def batched(insts, ct=None):
-    """Independent instances: objective and gradient of each, in order."""
-    res = []
-    for b, g in enumerate(insts):
-        F, f = objective(g.alphas, g.means, g.qd, g.l, g.x)
-        c = 1.0 if ct is None else float(ct[b])
-        res.append((F, f, vjp(g.alphas, g.means, g.qd, g.l, g.x, f, c)))
-    return res

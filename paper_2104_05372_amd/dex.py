@@ -130,11 +130,19 @@ def dtype_code(t: torch.Tensor) -> int:
     return _DT[t.dtype]
 
 
+def _check_device(t: torch.Tensor, name: str = "buffer"):
+    """Device buffers must live on the GPU. Without a visible GPU the library
+    itself reports the missing device (after its host-side argument checks)."""
+    if t.numel() and not t.is_cuda and torch.cuda.is_available():
+        raise ValueError(f"dex {name} must be a GPU tensor (got device {t.device})")
+
+
 def buf(t: torch.Tensor | None, dtype: int | None = None) -> DexBuf:
     if t is None:
         return DexBuf(None, 0, dtype or DEX_F32, 0)
     if not t.is_contiguous():
         raise ValueError("dex buffers must be contiguous")
+    _check_device(t)
     return DexBuf(t.data_ptr() if t.numel() else None, t.numel(),
                   dtype if dtype is not None else dtype_code(t), 0)
 
@@ -238,17 +246,44 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _f32_buffer(t, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32 (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    _check_device(t, name)
+
+
 def dex_reduce_rows(out: torch.Tensor, values: torch.Tensor, flags=0, stream=None):
-    """out[i] (=|+=) sum_j values[i, j] for a 2-D float32 `values`."""
+    """out[i] (=|+=) sum_j values[i, j] for a 2-D float32 `values`; `out` holds
+    one float32 per row."""
+    _f32_buffer(values, "values")
+    _f32_buffer(out, "out")
+    if values.dim() != 2:
+        raise ValueError(f"values must be 2-D (rows x cols), got shape {tuple(values.shape)}")
     rows, cols = values.shape
+    if out.numel() != rows:
+        raise ValueError(f"out must hold {rows} values (one per row), got {out.numel()}")
     check(lib().dex_reduce_rows(_ptr(out), _ptr(values), rows, cols, flags, stream_ptr(stream)))
 
 
 def dex_reduce_all(out: torch.Tensor, values: torch.Tensor, ws: torch.Tensor, flags=0,
                    stream=None):
-    """out[0] (=|+=) sum of all of float32 `values`; ws: DEX_REDUCE_WS_BYTES bytes."""
+    """out[0] (=|+=) sum of all of float32 `values`; ws: at least
+    DEX_REDUCE_WS_BYTES bytes of uint8 device memory."""
+    _f32_buffer(values, "values")
+    _f32_buffer(out, "out")
+    if out.numel() != 1:
+        raise ValueError(f"out must hold one value, got {out.numel()}")
+    if not isinstance(ws, torch.Tensor) or ws.dtype != torch.uint8 or not ws.is_contiguous():
+        raise ValueError("ws must be a contiguous uint8 tensor")
+    if ws.numel() < DEX_REDUCE_WS_BYTES:
+        raise ValueError(f"ws must hold at least {DEX_REDUCE_WS_BYTES} bytes, got {ws.numel()}")
+    _check_device(ws, "ws")
     check(lib().dex_reduce_all(_ptr(out), _ptr(values), values.numel(), flags, _ptr(ws),
-                               ws.numel() if ws is not None else 0, stream_ptr(stream)))
+                               ws.numel(), stream_ptr(stream)))
 
 
 def dex_vjp(d: DexDesc, ins, resid, ct_out, ct_in, flags=0, ws: torch.Tensor | None = None,
@@ -283,9 +318,11 @@ def dex_accum_scatter(acc: torch.Tensor, idx: torch.Tensor, vals: torch.Tensor |
     if ws is None:
         nb = dex_accum_scatter_workspace_bytes(acc_dt, n_rows, row_len, n, vals is not None, flags)
         ws = workspace(nb, acc.device) if nb else None
-    for t in (acc, idx, vals, scale):
-        if t is not None and not t.is_contiguous():
-            raise ValueError("dex buffers must be contiguous")
+    for t in (acc, idx, vals, scale, oob, ws):
+        if t is not None:
+            if not t.is_contiguous():
+                raise ValueError("dex buffers must be contiguous")
+            _check_device(t)
     check(lib().dex_accum_scatter(
         ctypes.c_void_p(acc.data_ptr()), acc_dt, n_rows, row_len, ctypes.c_void_p(idx.data_ptr()),
         idt, ctypes.c_void_p(vals.data_ptr()) if vals is not None else None,

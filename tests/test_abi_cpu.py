@@ -175,3 +175,36 @@ def test_reduction_argument_checks(dex):
     assert L.dex_reduce_all(None, None, 5, 0, None, 0, None) == dex.DEX_ERR_INVALID_ARG
     assert L.dex_reduce_all(ctypes.c_void_p(16), ctypes.c_void_p(16), 5, 0, ctypes.c_void_p(16), 16,
                             None) == dex.DEX_ERR_WORKSPACE
+
+
+def test_reduction_binding_rejects_bad_tensors(dex):
+    """The Python reductions check dtype, contiguity, rank, output size and the
+    workspace before any pointer reaches the library (a wrong dtype, a
+    transposed view or a short output would otherwise be read or written past
+    its end on the device)."""
+    import torch
+    v = torch.zeros(6, 4)
+    out = torch.zeros(6)
+    ws = torch.zeros(dex.DEX_REDUCE_WS_BYTES, dtype=torch.uint8)
+    bad_rows = [
+        (out, v.double()),                 # float64 values
+        (out, v.to(torch.bfloat16)),       # bf16 values
+        (out, torch.zeros(4, 6).t()),      # transposed view (not contiguous)
+        (out, torch.zeros(24)),            # not 2-D
+        (torch.zeros(5), v),               # short output
+        (out.double(), v),                 # float64 output
+    ]
+    for o, x in bad_rows:
+        with pytest.raises(ValueError):
+            dex.dex_reduce_rows(o, x)
+    one = torch.zeros(1)
+    bad_all = [
+        (one, v.double(), ws),
+        (one, torch.zeros(4, 6).t(), ws),
+        (torch.zeros(2), v, ws),
+        (one, v, ws[:100]),                                   # short workspace
+        (one, v, torch.zeros(dex.DEX_REDUCE_WS_BYTES // 4)),  # float workspace
+    ]
+    for o, x, w in bad_all:
+        with pytest.raises(ValueError):
+            dex.dex_reduce_all(o, x, w)
