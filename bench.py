@@ -2,18 +2,23 @@
 """Benchmark of the scatter-accumulate reverse-mode path on one MI355X.
 
 A step is one GMM gradient evaluation (dex_fwd + dex_vjp: F and the cotangents
-of alphas, means, qd and l) at N=100000, D=64, K=200 with BF16 matrix-core
-products and FP32 accumulation, inputs resident in HBM. Prints one JSON line.
+of alphas, means, qd and l) at N=100000, D=64, K=200 with 16-bit matrix-core
+operands (FP16 at D = 64) and FP32 accumulation, inputs resident in HBM. The
+timed steps run with nothing else enqueued between them. Prints one JSON line.
 
 The line also carries, measured in the same run:
-  roofline      the dominant kernel's algorithmic FLOP rate against the BF16
-                dense peak, its duration taken live with HIP events;
-  fp32_form     the same gradient with FP32 matrix-core products;
+  roofline      the dominant kernel's algorithmic FLOP rate against the 16-bit
+                dense peak, its duration taken with HIP events around each
+                launch in a separate pass;
+  forward_mode  the derivative of the objective along a tangent (dex_jvp);
+  bf16_resident_form, fp32_form  the same gradient with BF16 Q~(x~ - mu~)
+                products, and with FP32 matrix-core products;
   rows          the other workloads of the path (gather / scatter-accumulate,
-                histogram, batched GMM, checkpointed stencil adjoint), each with
-                its kernel time and roofline fraction;
-  cpu_baseline  the FP64 oracle timed on this host on a bounded sample, and the
-                GPU result's error against it on that sample.
+                histogram, batched GMM, checkpointed stencil adjoint,
+                reductions), each with its kernel time and roofline fraction;
+  cpu_baseline  the FP64 oracle timed on this host: one full-size evaluation on
+                all threads, and a one-thread sample; rel_l2_vs_fp64_oracle is
+                the headline's error against that full-size evaluation.
 """
 from __future__ import annotations
 
@@ -112,13 +117,16 @@ def run_headline(torch, dex, workloads, args, dev):
 
     for _ in range(args.warmup):
         step()
-    sync()
-    dex.dex_profile_reset()
-    dex.dex_profile_enable(True)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    # 1) the timed steps: nothing but the two calls (no events, profiling off)
     sync()
     t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    sync()
+    elapsed = time.perf_counter() - t0
+    # 2) forward / reverse split, with events between the calls
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     for e in ev:
         e[0].record()
         S["fwd"]()
@@ -126,10 +134,15 @@ def run_headline(torch, dex, workloads, args, dev):
         S["vjp"]()
         e[2].record()
     sync()
-    elapsed = time.perf_counter() - t0
-    dex.dex_profile_enable(False)
     fwd_ms = sum(a.elapsed_time(b) for a, b, _ in ev) / len(ev)
     vjp_ms = sum(b.elapsed_time(c) for _, b, c in ev) / len(ev)
+    # 3) the main kernels' own durations (HIP events around each launch)
+    dex.dex_profile_reset()
+    dex.dex_profile_enable(True)
+    for _ in range(args.steps):
+        step()
+    sync()
+    dex.dex_profile_enable(False)
     kf_ms, kf_n = dex.dex_profile_read("GMM_FWD")
     kb_ms, kb_n = dex.dex_profile_read("GMM_VJP")
     tri = D * (D + 1) * N * K        # forward: y = Q r, triangular, 2 flops per multiply-add
@@ -148,10 +161,31 @@ def run_headline(torch, dex, workloads, args, dev):
             "kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "tflops": round(v["tflops"], 2),
                             "frac": round(v["tflops"] / peak, 4)} for k, v in kern.items()},
             "flop_count": "forward D(D+1)NK (triangular y = Q r); reverse D(D+3)NK (symmetric "
-                          "weighted moment sum_i w x x^T and sum_i w x per component)"}
+                          "weighted moment sum_i w x x^T and sum_i w x per component)",
+            "timing": "kernel durations from HIP events around each launch, in a pass of their "
+                      "own after the timed steps"}
     res = dict(value=args.steps / elapsed, ms=elapsed / args.steps * 1e3, fwd_ms=fwd_ms, vjp_ms=vjp_ms,
                roofline=roof, cfg=S["cfg"], g=g, S=S)
     return res
+
+
+def headline_vs_oracle(torch, dex, g, S, threads):
+    """One FP64 oracle evaluation (objective + gradient) of the whole benchmark
+    instance on the host, timed: the CPU baseline at full size, and the
+    reference for the GPU result's error (the GPU state holds the last step)."""
+    import numpy as np
+    from oracle import gmm as ogmm
+    torch.cuda.synchronize()
+    got = [x.cpu().numpy().astype(np.float64) for x in S["grads"]]
+    Fg = float(S["F"].item())
+    t0 = time.perf_counter()
+    Fo, fo = ogmm.objective(*g.params(), g.x)
+    go = ogmm.vjp(*g.params(), g.x, fo)
+    secs = time.perf_counter() - t0
+    errs = {n: float(np.linalg.norm(a.ravel() - o.ravel()) / np.linalg.norm(o))
+            for n, a, o in zip(("alphas", "means", "qd", "l"), got, go)}
+    errs["F"] = abs(Fg - Fo) / abs(Fo)
+    return secs, errs
 
 
 def run_fp32_form(torch, dex, g, dev, steps):
@@ -399,43 +433,46 @@ def row_reduce(torch, dex, workloads, dev, steps):
 
 
 # ---------------------------------------------------------------------------
-def cpu_baseline(torch, dex, workloads, g, variant, dev):
-    """The FP64 oracle on two point-subsamples of the benchmark instance (all
-    200 components), fitted as a + b N and evaluated at N = 1e5; plus the GPU
-    gradient's error against the oracle on the larger subsample."""
-    import numpy as np
-    from oracle import gmm as ogmm
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
-        cores = os.cpu_count() or 1
-    times = {}
-    sub = {}
-    for n in (1000, 5000):
-        h = workloads.GMMInputs(g.alphas, g.means, g.qd, g.l, g.x[:n].copy())
-        t0 = time.perf_counter()
-        F, f = ogmm.objective(*h.params(), h.x)
-        go = ogmm.vjp(*h.params(), h.x, f)
-        times[n] = time.perf_counter() - t0
-        sub[n] = (h, F, go)
-    b = (times[5000] - times[1000]) / 4000
-    a = times[1000] - b * 1000
-    t_full = a + b * g.N
-    h, Fo, go = sub[5000]
-    S = gmm_setup(torch, dex, h, variant, dev)
-    S["fwd"]()
-    S["vjp"]()
-    torch.cuda.synchronize()
-    errs = {}
-    for name, x, o in zip(("alphas", "means", "qd", "l"), S["grads"], go):
-        xx = x.cpu().numpy().astype(np.float64).ravel()
-        errs[name] = float(np.linalg.norm(xx - o.ravel()) / np.linalg.norm(o))
-    errs["F"] = abs(S["F"].item() - Fo) / abs(Fo)
-    return {"value": round(1.0 / t_full, 6), "unit": "grad evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle on the first 1000 and 5000 of the 100000 points (all 200 "
-                      f"components, D=64), {times[1000]:.2f}s and {times[5000]:.2f}s, fitted a+bN "
-                      f"and evaluated at N=100000 ({t_full:.1f}s per grad eval)"}, errs
+        return os.cpu_count() or 1
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_single_thread(g, n_sample=5000):
+    """The FP64 oracle on one thread over the first n_sample points (all
+    components); its cost is linear in N, so the full-size time is the sample
+    time times N / n_sample."""
+    from oracle import gmm as ogmm
+    import workloads
+    h = workloads.GMMInputs(g.alphas, g.means, g.qd, g.l, g.x[:n_sample].copy())
+    try:
+        from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(1)
+    except Exception:
+        ctx = None
+    t0 = time.perf_counter()
+    try:
+        _, f = ogmm.objective(*h.params(), h.x)
+        ogmm.vjp(*h.params(), h.x, f)
+    finally:
+        if ctx is not None:
+            ctx.unregister() if hasattr(ctx, "unregister") else ctx.__exit__(None, None, None)
+    t = time.perf_counter() - t0
+    return t, t * g.N / n_sample
 
 
 def main(argv=None):
@@ -477,10 +514,12 @@ def main(argv=None):
         "metric": METRIC, "value": round(H["value"], 3), "unit": "grad evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(H["ms"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"bf16": "bf16", "bf16x3": "bf16x3", "fp32": "f32"}[args.variant], "data": "synthetic",
+        "dtype": {"bf16": "fp16", "bf16x3": "bf16x3", "fp32": "f32"}[args.variant], "data": "synthetic",
         "config": {"workload": "gmm_grad_N100000_D64_K200", "N": 100000, "D": 64, "K": 200,
-                   "products": {"bf16": "BF16 MFMA, FP32 accumulate", "bf16x3": "split-BF16 MFMA",
-                                "fp32": "FP32 MFMA"}[args.variant],
+                   "products": {"bf16": "16-bit variant: forward one FP16 matrix-core product over "
+                                        "second-order features (per-tile power-of-two scaling), "
+                                        "reverse FP16 weighted moments, FP32 accumulation",
+                                "bf16x3": "split-BF16 MFMA", "fp32": "FP32 MFMA"}[args.variant],
                    "tile_configs": {"fwd": H["cfg"][0], "vjp": H["cfg"][1]}},
         "bwd_fwd_ratio": round(H["vjp_ms"] / H["fwd_ms"], 3),
         "fwd_ms": round(H["fwd_ms"], 4), "vjp_ms": round(H["vjp_ms"], 4),
@@ -489,7 +528,7 @@ def main(argv=None):
     g = H["g"]
     if not args.no_rows:
         # forward mode of the objective along a tangent (the gradients buffer
-        # serves as the tangent): reverse pass with cotangent 1 + inner product
+        # serves as the tangent): the linearized loop run forward
         S = H["S"]
         d = S["d"]
         wsj = dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_JVP), dev)
@@ -504,10 +543,42 @@ def main(argv=None):
             dex.dex_jvp(d, S["t"], S["grads"], [dF], wsj, resid=[f, cache])
 
         jvp()
-        j_ms = timed(jvp, max(3, args.steps // 2), torch.cuda.synchronize) * 1e3
-        line["forward_mode"] = {"jvp_ms": round(j_ms, 4),
-                                "form": "reverse pass with cotangent 1, then <grad F, t> in FP64"}
+        nj = max(3, args.steps // 2)
+        j_ms = timed(jvp, nj, torch.cuda.synchronize) * 1e3
+        dex.dex_profile_reset()
+        dex.dex_profile_enable(True)
+        for _ in range(nj):
+            jvp()
+        torch.cuda.synchronize()
+        dex.dex_profile_enable(False)
+        kms, kn = dex.dex_profile_read("GMM_JVP")
+        tri = g.D * (g.D + 1) * g.N * g.K
+        kt = tri / (kms / max(kn, 1) * 1e-3) / 1e12
+        line["forward_mode"] = {
+            "jvp_ms": round(j_ms, 4),
+            "tangent_kernel": {"avg_ms": round(kms / max(kn, 1), 4), "tflops": round(kt, 2),
+                               "frac": round(kt / PEAK["bf16"], 4)},
+            "form": "linearized loop run forward: tangent coefficients (dP = dQ^T Q + Q^T dQ), one "
+                    "FP16 matrix-core product over the forward's second-order features, weighted "
+                    "by exp(beta - f) from the forward's residuals; no reverse pass"}
         del wsj, cache, S
+        # the BF16 products the workload names (Q~ (x~ - mu~), the resident-component
+        # forward, tile configuration 2) in place of the feature-product forward
+        try:
+            SB = gmm_setup(torch, dex, g, dex.DEX_GMM_BF16, dev, (2, H["cfg"][1]))
+            for _ in range(2):
+                SB["fwd"]()
+                SB["vjp"]()
+            ms = timed(lambda: (SB["fwd"](), SB["vjp"]()), max(3, args.steps // 2),
+                       torch.cuda.synchronize) * 1e3
+            line["bf16_resident_form"] = {
+                "grad_evals_per_s": round(1e3 / ms, 2), "ms_per_step": round(ms, 4),
+                "products": "forward BF16 Q~(x~ - mu~) (4 components resident per wave), "
+                            "reverse FP16 weighted moments"}
+            del SB
+        except Exception as e:
+            line["bf16_resident_form"] = {"error": repr(e)}
+    H["S_keep"] = {"F": H["S"]["F"], "grads": H["S"]["grads"]}  # the headline's result
     del H["S"]
     torch.cuda.empty_cache()
     if args.variant != "fp32":
@@ -532,12 +603,24 @@ def main(argv=None):
             torch.cuda.empty_cache()
         line["rows"] = rows
     if not args.no_cpu_baseline:
+        # one full-size FP64 oracle evaluation on all host threads (the CPU
+        # baseline, and the reference for the headline's error), plus a
+        # single-thread sample
         log("cpu baseline")
-        variant = {"bf16": dex.DEX_GMM_BF16, "bf16x3": dex.DEX_GMM_BF16X3, "fp32": dex.DEX_GMM_PLAIN}[args.variant]
         try:
-            cb, errs = cpu_baseline(torch, dex, workloads, g, variant, dev)
-            line["cpu_baseline"] = cb
+            secs, errs = headline_vs_oracle(torch, dex, g, H["S_keep"], blas_threads())
+            t1, t1_full = cpu_single_thread(g)
+            line["cpu_baseline"] = {
+                "value": round(1.0 / secs, 6), "unit": "grad evals/s", "cores": blas_threads(),
+                "kind": "oracle",
+                "sample": f"one FP64 oracle evaluation (objective + gradient) of the whole "
+                          f"N=100000, D=64, K=200 instance on {blas_threads()} host threads, "
+                          f"{secs:.1f} s; host CPU {cpu_model()}, {os.cpu_count()} logical CPUs",
+                "single_thread": {"value": round(1.0 / t1_full, 6), "unit": "grad evals/s",
+                                  "sample": f"first 5000 points, one thread, {t1:.2f} s, times "
+                                            f"N/5000 (the cost is linear in N)"}}
             line["rel_l2_vs_fp64_oracle"] = {k: float(f"{v:.3e}") for k, v in errs.items()}
+            line["rel_l2_vs_fp64_oracle"]["at"] = "full size, the last timed step's result"
         except Exception as e:
             line["cpu_baseline"] = {"error": repr(e)}
     print(json.dumps(line), flush=True)

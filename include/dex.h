@@ -66,8 +66,15 @@ typedef int32_t dex_status;
 
 /* GMM arithmetic variants (dex_desc.variant) */
 #define DEX_GMM_PLAIN  0 /* every product and sum in the descriptor dtype            */
-#define DEX_GMM_BF16   1 /* Q_k (x_i - mu_k) and the weighted outer products as BF16
-                            MFMA with FP32 accumulation; FP32 storage only          */
+#define DEX_GMM_BF16   1 /* 16-bit matrix-core operands, FP32 accumulation, FP32
+                            storage only. Forward at D = 64: one FP16 product over
+                            the second-order features of x (||Q_k r||^2 expanded
+                            through P_k = Q_k^T Q_k, per-tile power-of-two scaling);
+                            forward at other D: BF16 Q_k (x_i - mu_k) products;
+                            reverse (weighted moments) FP16 at every D. All operands
+                            are taken about the mean of the component means, which
+                            changes no result (only x - mu enters) but keeps the
+                            16-bit values small for data far from the origin.     */
 #define DEX_GMM_BF16X3 2 /* split-BF16 operands, hi*hi + hi*lo + lo*hi per product   */
 
 /* stencil variants */
@@ -231,11 +238,16 @@ dex_status dex_vjp(const dex_desc* d,
  *     partials (DEX_WS_JVP).
  *   DEX_GMM: in = alphas, means, qd, l, x (as for dex_fwd); resid = f, cache from
  *     dex_fwd with the same descriptor and inputs; t_in = dalphas[K], dmeans[K*D],
- *     dqd[K*D], dl[K*L]; t_out = dF[1]. F is a scalar, so its derivative along
- *     t is <grad F, t>: it is formed from the reverse pass (one pass of the
- *     matrix-core moment kernels with cotangent 1, far cheaper than a second
- *     forward-sized product over tangent coefficients) and a fixed-order
- *     inner product with t accumulated in FP64. Workspace: DEX_WS_JVP bytes.
+ *     dqd[K*D], dl[K*L]; t_out = dF[1]. The linearized loop is run forward: per
+ *     point i and component k, dy = dQ_k r_ik - Q_k dmu_k (dQ_k: diagonal
+ *     exp(qd) dqd, strict lower dl), dbeta = dalpha_k + sum_d dqd_kd - y.dy,
+ *     dF = sum_i sum_k exp(beta_ik - f_i) dbeta_ik - N softmax(alphas).dalphas.
+ *     16-bit variant at D = 64: dbeta comes from one FP16 matrix-core product
+ *     of the forward's second-order features with tangent coefficients (built
+ *     from dP = dQ^T Q + Q^T dQ), weighted by the forward's beta residual.
+ *     Every other form: one vector-ALU pass in the descriptor dtype (FP32 forms
+ *     compute in FP32). The per-block sums and the final sum are FP64 in a
+ *     fixed order. Workspace: DEX_WS_JVP bytes.
  *   Other kinds: DEX_ERR_UNSUPPORTED.
  * All buffers are device memory owned by the caller; t_out is overwritten.
  * Argument errors are reported before anything is enqueued; the call enqueues
@@ -353,7 +365,8 @@ void dex_autotune_reset(void);
 #define DEX_PROF_GATHER_JVP  10 /* gather-scale forward mode (dex_jvp)        */
 #define DEX_PROF_REDUCE_ROWS 11 /* regular segmented reduction                */
 #define DEX_PROF_REDUCE_ALL  12 /* complete reduction (both passes)           */
-#define DEX_PROF_COUNT       13
+#define DEX_PROF_GMM_JVP     13 /* GMM forward-mode tangent kernel (dex_jvp)   */
+#define DEX_PROF_COUNT       14
 void dex_profile_enable(int32_t on);
 dex_status dex_profile_read(int32_t id, double* total_ms, int64_t* launches);
 void dex_profile_reset(void);

@@ -317,7 +317,8 @@ dex_status dex_fwd(const dex_desc* d, const dex_buf* in, int32_t n_in, dex_buf* 
   DEX_TRY(check_desc(d));
   if ((n_in && !in) || (n_out && !out) || (n_resid && !resid))
     return fail(DEX_ERR_INVALID_ARG, "null buffer list");
-  DEX_TRY(ensure_device());
+  // every argument is checked on the host first; the device is set up (and
+  // checked to be gfx950) only before the launches
   hipStream_t s = (hipStream_t)hip_stream;
   const int cfg = pick_config(*d, DEX_WS_FWD);
   int32_t nc = 1;
@@ -340,6 +341,7 @@ dex_status dex_fwd(const dex_desc* d, const dex_buf* in, int32_t n_in, dex_buf* 
       DEX_TRY(want(resid, 0, "resid", t, N));
       DEX_TRY(want(resid, 1, "resid", DEX_U8, (int64_t)gmm_cache_bytes(*d)));
       GmmPtrs p{in[0].ptr, in[1].ptr, in[2].ptr, in[3].ptr, in[4].ptr};
+      DEX_TRY(ensure_device());
       return gmm_fwd(*d, cfg, p, out[0].ptr, resid[0].ptr, resid[1].ptr, workspace, s);
     }
     case DEX_GMM_BATCHED: {
@@ -358,6 +360,7 @@ dex_status dex_fwd(const dex_desc* d, const dex_buf* in, int32_t n_in, dex_buf* 
       DEX_TRY(want(resid, 0, "resid", DEX_F32, sumN));
       DEX_TRY(want(resid, 1, "resid", DEX_U8, d->dims[7]));
       GmmPtrs p{in[1].ptr, in[2].ptr, in[3].ptr, in[4].ptr, in[5].ptr};
+      DEX_TRY(ensure_device());
       return gmm_batched_fwd(*d, cfg, in[0].ptr, p, out[0].ptr, resid[0].ptr, resid[1].ptr,
                              workspace, s);
     }
@@ -369,6 +372,7 @@ dex_status dex_fwd(const dex_desc* d, const dex_buf* in, int32_t n_in, dex_buf* 
       DEX_TRY(want(in, 2, "in", DEX_F32, n));
       DEX_TRY(check_count(n_out, 1, "out"));
       DEX_TRY(want(out, 0, "out", DEX_F32, n * R));
+      DEX_TRY(ensure_device());
       return gather_fwd((const float*)in[0].ptr, (const int32_t*)in[1].ptr, (const float*)in[2].ptr,
                         V, R, n, (float*)out[0].ptr, false, nullptr, s);
     }
@@ -385,6 +389,7 @@ dex_status dex_fwd(const dex_desc* d, const dex_buf* in, int32_t n_in, dex_buf* 
       DEX_TRY(want(resid, 0, "resid", DEX_F32, nck * n));
       DEX_TRY(want(resid, 1, "resid", DEX_F32, n));
       if (out[1].ptr == in[0].ptr) return fail(DEX_ERR_INVALID_ARG, "uT must not alias u0");
+      DEX_TRY(ensure_device());
       DEX_TRY(stencil_fwd(*d, cfg, (const float*)in[0].ptr, (const float*)in[1].ptr,
                           (float*)out[0].ptr, (float*)out[1].ptr, (float*)resid[0].ptr, workspace, s));
       if (resid[1].ptr != out[1].ptr) {
@@ -498,7 +503,8 @@ dex_status dex_vjp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex
   DEX_TRY(check_desc(d));
   if ((n_in && !in) || (n_resid && !resid) || (n_ct_out && !ct_out) || (n_ct_in && !ct_in))
     return fail(DEX_ERR_INVALID_ARG, "null buffer list");
-  DEX_TRY(ensure_device());
+  // every argument is checked on the host first; the device is set up (and
+  // checked to be gfx950) only before the launches
   hipStream_t s = (hipStream_t)hip_stream;
   const bool acc = flags & DEX_ACCUMULATE;
   const int cfg = pick_config(*d, DEX_WS_VJP);
@@ -528,6 +534,7 @@ dex_status dex_vjp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex
       DEX_TRY(want(ct_in, 3, "ct_in", t, K * L));
       GmmPtrs p{in[0].ptr, in[1].ptr, in[2].ptr, in[3].ptr, in[4].ptr};
       GmmGrads g{ct_in[0].ptr, ct_in[1].ptr, ct_in[2].ptr, ct_in[3].ptr};
+      DEX_TRY(ensure_device());
       return gmm_vjp(*d, cfg, p, resid[0].ptr, resid[1].ptr, ct_out[0].ptr, g, acc, workspace, s);
     }
     case DEX_GMM_BATCHED: {
@@ -552,6 +559,7 @@ dex_status dex_vjp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex
       DEX_TRY(want(ct_in, 3, "ct_in", DEX_F32, sumKL));
       GmmPtrs p{in[1].ptr, in[2].ptr, in[3].ptr, in[4].ptr, in[5].ptr};
       GmmGrads g{ct_in[0].ptr, ct_in[1].ptr, ct_in[2].ptr, ct_in[3].ptr};
+      DEX_TRY(ensure_device());
       return gmm_batched_vjp(*d, cfg, in[0].ptr, p, resid[0].ptr, resid[1].ptr, ct_out[0].ptr, g,
                              acc, workspace, s);
     }
@@ -568,6 +576,7 @@ dex_status dex_vjp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex
       DEX_TRY(want(ct_in, 0, "ct_in", DEX_F32, V * R));
       const bool with_dw = !(flags & DEX_NO_DW);
       DEX_TRY(want(ct_in, 1, "ct_in", DEX_F32, with_dw ? n : 0));
+      DEX_TRY(ensure_device());
       if (!acc) DEX_TRY(fill_zero(ct_in[0].ptr, (size_t)(V * R) * 4, s));
       DEX_TRY(accum_scatter(ct_in[0].ptr, DEX_F32, V, R, in[1].ptr, DEX_I32, ct_out[0].ptr,
                             (const float*)in[2].ptr, n, false, nullptr, workspace, ws_bytes_, cfg, s));
@@ -589,6 +598,7 @@ dex_status dex_vjp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex
       DEX_TRY(want(ct_out, 0, "ct_out", DEX_F32, 1));
       DEX_TRY(check_count(n_ct_in, 1, "ct_in"));
       DEX_TRY(want(ct_in, 0, "ct_in", DEX_F32, n));
+      DEX_TRY(ensure_device());
       return stencil_vjp(*d, cfg, (const float*)in[0].ptr, (const float*)in[1].ptr,
                          (const float*)resid[0].ptr, (const float*)resid[1].ptr,
                          (const float*)ct_out[0].ptr, (float*)ct_in[0].ptr, acc, workspace, s);
@@ -622,6 +632,15 @@ dex_status dex_accum_scatter(void* acc, int32_t acc_dtype, int64_t n_rows, int64
   if (acc_dtype == DEX_I32 && scale) return fail(DEX_ERR_INVALID_ARG, "integer accumulation takes no scale");
   const bool check = flags & DEX_CHECK_BOUNDS;
   if (check && !oob_count_dev) return fail(DEX_ERR_INVALID_ARG, "DEX_CHECK_BOUNDS needs oob_count_dev");
+  if ((flags & DEX_DETERMINISTIC) && acc_dtype != DEX_F32)
+    return fail(DEX_ERR_INVALID_ARG, "DEX_DETERMINISTIC applies to float accumulation");
+  {
+    const size_t need = scatter_ws_bytes(acc_dtype, n_rows, row_len, n, vals != nullptr,
+                                         (flags & DEX_DETERMINISTIC) != 0);
+    if (need && (!workspace || ws_bytes_ < need))
+      return fail(DEX_ERR_WORKSPACE, "this accumulation needs %zu workspace bytes, got %zu", need,
+                  workspace ? ws_bytes_ : (size_t)0);
+  }
   DEX_TRY(ensure_device());
   hipStream_t s = (hipStream_t)hip_stream;
   long long before = 0, after = 0;

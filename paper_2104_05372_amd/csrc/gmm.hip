@@ -249,47 +249,131 @@ __global__ void __launch_bounds__(256) k_mom_reduce(float* __restrict__ part, in
   part[i] = s + err;
 }
 
-template <typename T>
-__global__ void k_set_one(T* __restrict__ p) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) p[0] = (T)1;
-}
+// Forward mode of the objective on the vector ALU (every D <= 64; FP64, or
+// FP32 with x - mu formed exactly in FP64 and rounded once). Block
+// (256 points, chunk of kJvpKC components); the components of the chunk are
+// staged in LDS in turn. For point i and component k, with r = x_i - mu_k,
+//   y = Q_k r, dy = dQ_k r - Q_k dmu_k (dQ: diagonal exp(qd) dqd, strict lower
+//   dl), beta = kappa_k - |y|^2 / 2, dbeta = dalpha_k + sum_d dqd_kd - y . dy,
+// and the tangent of f_i = LSE_k beta_ik is sum_k exp(beta_ik - f_i) dbeta_ik.
+// Each block writes its FP64 sum of these to part[blockIdx.y * gridDim.x +
+// blockIdx.x].
+constexpr int kJvpKC = 8;
 
-// Block partials (FP64, fixed grid and order) of sum_j g[j] t[j], with g the
-// concatenation of four segments and t the four separate tangent arrays.
-template <typename T>
-__global__ void __launch_bounds__(256) k_dot4_partial(const T* __restrict__ g, int64_t n0,
-                                                      int64_t n1, int64_t n2, int64_t n3,
-                                                      const T* __restrict__ t0,
-                                                      const T* __restrict__ t1,
-                                                      const T* __restrict__ t2,
-                                                      const T* __restrict__ t3,
-                                                      double* __restrict__ part) {
+template <typename T, int DB>
+__global__ void __launch_bounds__(256) gmm_jvp_valu(
+    const T* __restrict__ alphas, const T* __restrict__ means, const T* __restrict__ qd,
+    const T* __restrict__ l, const T* __restrict__ x, const T* __restrict__ f, int N, int D, int K,
+    const T* __restrict__ da, const T* __restrict__ dm, const T* __restrict__ dq,
+    const T* __restrict__ dl, double* __restrict__ part) {
+  __shared__ T Qs[DB][DB + 1], dQs[DB][DB + 1];
+  __shared__ T mus[DB], qdm[DB], kap[2];
   __shared__ double sh[32];
-  const int64_t n = n0 + n1 + n2 + n3;
+  const int t = threadIdx.x, p = blockIdx.x * 256 + t;
+  const bool valid = p < N;
+  const int L = D * (D - 1) / 2;
+  T xr[DB];
+#pragma unroll
+  for (int b = 0; b < DB; ++b) xr[b] = (valid && b < D) ? x[(size_t)p * D + b] : T(0);
+  const T fp = valid ? f[p] : T(0);
   double acc = 0.0;
-  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
-    T tv;
-    if (j < n0)
-      tv = t0[j];
-    else if (j < n0 + n1)
-      tv = t1[j - n0];
-    else if (j < n0 + n1 + n2)
-      tv = t2[j - n0 - n1];
-    else
-      tv = t3[j - n0 - n1 - n2];
-    acc += (double)g[j] * (double)tv;
+  const int k0 = blockIdx.y * kJvpKC, k1 = min(K, k0 + kJvpKC);
+  for (int k = k0; k < k1; ++k) {
+    __syncthreads();
+    for (int e = t; e < DB * DB; e += 256) {
+      const int a = e / DB, b = e % DB;
+      T q = 0, dqv = 0;
+      if (a < D && b < D) {
+        if (a == b) {
+          const T ev = dexp<T>(qd[(size_t)k * D + a]);
+          q = ev;
+          dqv = ev * dq[(size_t)k * D + a];
+        } else if (a > b) {
+          const size_t li = (size_t)k * L + a * (a - 1) / 2 + b;
+          q = l[li];
+          dqv = dl[li];
+        }
+      }
+      Qs[a][b] = q;
+      dQs[a][b] = dqv;
+    }
+    if (t < DB) mus[t] = t < D ? means[(size_t)k * D + t] : T(0);
+    if (t < 64) {
+      T s = 0, ds = 0;
+      for (int d = t; d < D; d += 64) {
+        s += qd[(size_t)k * D + d];
+        ds += dq[(size_t)k * D + d];
+      }
+      s = wave_sum(s);
+      ds = wave_sum(ds);
+      if (t == 0) {
+        kap[0] = alphas[k] + s;
+        kap[1] = da[k] + ds;
+      }
+    }
+    __syncthreads();
+    if (t < DB) {  // Q_k dmu_k
+      T v = 0;
+      for (int b = 0; b <= t && b < D; ++b) v += Qs[t][b] * dm[(size_t)k * D + b];
+      qdm[t] = v;
+    }
+    __syncthreads();
+    T r[DB];
+#pragma unroll
+    for (int b = 0; b < DB; ++b) r[b] = b < D ? (T)((double)xr[b] - (double)mus[b]) : T(0);
+    T s = 0, sd = 0;
+#pragma unroll
+    for (int a = 0; a < DB; ++a) {
+      if (a < D) {
+        T y = 0, dy = -qdm[a];
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+          y += Qs[a][b] * r[b];
+          dy += dQs[a][b] * r[b];
+        }
+        s += y * y;
+        sd += y * dy;
+      }
+    }
+    if (valid) acc += (double)(dexp<T>(kap[0] - T(0.5) * s - fp) * (kap[1] - sd));
   }
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+  if (t == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
 }
 
+// dF = (sum of the partials, fixed order) - N sum_k softmax(alpha)_k dalpha_k,
+// in FP64.
 template <typename T>
-__global__ void k_dot_final(const double* __restrict__ part, int nb, T* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_jvp_final(const double* __restrict__ part, int64_t np,
+                                                   const T* __restrict__ alphas,
+                                                   const T* __restrict__ da, int K, int64_t N,
+                                                   T* __restrict__ out) {
   __shared__ double sh[32];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[i];
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) out[0] = (T)acc;
+  double s = 0.0, am = -INFINITY;
+  for (int64_t i = threadIdx.x; i < np; i += 256) s += part[i];
+  for (int k = threadIdx.x; k < K; k += 256) am = fmax(am, (double)alphas[k]);
+  s = block_sum(s, sh);
+  // max over the block (every thread's am), through the same LDS slots
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = -INFINITY;
+  __syncthreads();
+  {
+    double m = am;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  }
+  __syncthreads();
+  am = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  double z = 0.0, zd = 0.0;
+  for (int k = threadIdx.x; k < K; k += 256) {
+    const double e = exp((double)alphas[k] - am);
+    z += e;
+    zd += e * (double)da[k];
+  }
+  z = block_sum(z, sh);
+  zd = block_sum(zd, sh);
+  if (threadIdx.x == 0) out[0] = (T)(s - (double)N * zd / z);
 }
 
 template <typename T>
@@ -315,15 +399,44 @@ __global__ void __launch_bounds__(256) k_bwd_finalize(const TP* __restrict__ par
                            means, ct[0], d_alphas, d_means, d_qd, d_l, accumulate);
 }
 
-// Component k's moment partials, already summed into slot 0 (S = 1).
+// Component k's moment partials, already summed into slot 0 (S = 1); the
+// moments were taken about the origin `shift`.
 __global__ void __launch_bounds__(256) k_bwd_finalize_mom(
     const float* __restrict__ part, size_t E, int S, int K, int D, int DP, int64_t N,
     const float* __restrict__ alphas, const float* __restrict__ means, const float* __restrict__ qd,
     const float* __restrict__ l, const float* __restrict__ ct, float* __restrict__ d_alphas,
-    float* __restrict__ d_means, float* __restrict__ d_qd, float* __restrict__ d_l, int accumulate) {
+    float* __restrict__ d_means, float* __restrict__ d_qd, float* __restrict__ d_l, int accumulate,
+    const float* __restrict__ shift) {
   const int k = blockIdx.x;
   bwd_finalize_mom(part + (size_t)k * E, (size_t)K * E, S, k, K, D, DP, N, alphas, means, qd, l,
-                   ct[0], d_alphas, d_means, d_qd, d_l, accumulate);
+                   ct[0], d_alphas, d_means, d_qd, d_l, accumulate, shift);
+}
+
+// The origin about which the matrix-core forms take their operands: the mean
+// of the component means, c[d] = (1/K) sum_k means[k][d] (FP64, fixed order),
+// zero for d >= D. Every term of the objective and of its gradient depends on
+// x_i and mu_k only through x_i - mu_k = (x_i - c) - (mu_k - c), so moving the
+// origin changes no result; it keeps the 16-bit operands, and the expansion
+// ||Q(x - mu)||^2 = x^T P x - 2 (P mu)^T x + mu^T P mu of the feature-product
+// form, free of the cancellation that data far from the origin would cause.
+// One block of 1024 threads: 16 slices of the components per coordinate.
+__global__ void __launch_bounds__(1024) k_shift(const float* __restrict__ means, int K, int D,
+                                                float* __restrict__ shift) {
+  __shared__ double part[16][64];
+  const int d = threadIdx.x & 63, q = threadIdx.x >> 6;
+  double s = 0.0;
+  if (d < D) {
+#pragma unroll 8
+    for (int k = q; k < K; k += 16) s += (double)means[(size_t)k * D + d];
+  }
+  part[q][d] = s;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) t += part[j][d];
+    shift[d] = d < D ? (float)(t / K) : 0.f;
+  }
 }
 
 }  // namespace dexk
@@ -375,7 +488,7 @@ FwdCfg fwd_cfg(const Shape& s, int i) { return s.prec == PREC_BF16 ? kFwdBF[i] :
 BwdCfg bwd_cfg(const Shape& s, int i) { return s.prec == PREC_F32 ? kBwdF32[i] : kBwdBF[i]; }
 
 struct CacheLayout {
-  size_t xh, xl, xhT, xlT, Qh, Ql, negc, kappa, beta, total;
+  size_t xh, xl, xhT, xlT, Qh, Ql, negc, kappa, beta, shift, total;
   // feature-product forward (BF16, D = 64): coefficient operand, kappa',
   // rescale factors, scaled FP16 copy of x, per-tile scale exponents
   size_t W16, kq, isc, x16, texp;
@@ -401,6 +514,7 @@ CacheLayout cache_layout(const Shape& s) {
     c.Ql = lo ? take(g.K * g.DP * g.DP * es) : 0;
     c.negc = take(g.K * g.DP * 4);
     c.kappa = take(g.K * 4);
+    c.shift = take(64 * 4);
     c.beta = take(beta_rows(g.K) * g.Npad * 4);
     if (qf_eligible(g, s.prec)) {
       const size_t Kp = (size_t)beta_rows(g.K);
@@ -488,23 +602,43 @@ size_t gmm_cache_bytes(const dex_desc& d) {
   return cache_layout(s).total;
 }
 
-constexpr int kDotBlocks = 64;
-size_t gmm_ws_bytes(const dex_desc& d, int role);
-
-// Forward-mode workspace: the reverse pass's, then the gradient (alphas, means,
-// qd, l concatenated), the cotangent 1, the inner product's block partials.
-static size_t jvp_grad_offset(const dex_desc& d) { return align256(gmm_ws_bytes(d, DEX_WS_VJP)); }
-static size_t jvp_grad_bytes(const Shape& s) {
-  const size_t K = s.g.K, D = s.g.D;
-  return align256(K * (1 + 2 * D + D * (D - 1) / 2) * s.tsize);
+// Forward-mode workspace. Feature-product form (16-bit variant, D = 64): the
+// scaled FP16 x~ and its tile exponents, the tangent coefficient operand,
+// dkq' and rescale factors, one FP64 partial per (pass, tile). Vector-ALU
+// form: one FP64 partial per (point block, component chunk).
+struct JvpLayout {
+  size_t x16, texp, dW16, dkq, disc, part, total;
+  int64_t nparts;
+};
+static JvpLayout jvp_layout(const Shape& s) {
+  JvpLayout j{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  if (s.mfma && qf_eligible(s.g, s.prec)) {
+    const size_t Kp = (size_t)beta_rows(s.g.K);
+    j.x16 = take((size_t)s.g.Npad * 64 * 2);
+    j.texp = take((size_t)(s.g.Npad / 64) * 4);
+    j.dW16 = take(Kp / 16 * 68 * 64 * 8 * 2);
+    j.dkq = take(Kp * 4);
+    j.disc = take(Kp * 4);
+    j.nparts = qf_tan_parts(s.g);
+  } else {
+    j.nparts = ((s.g.N + 255) / 256) * ((s.g.K + kJvpKC - 1) / kJvpKC);
+  }
+  j.part = take((size_t)j.nparts * 8);
+  j.total = o;
+  return j;
 }
 
 size_t gmm_ws_bytes(const dex_desc& d, int role) {
   Shape s = shape_of(d);
   if (!valid_shape(s)) return 0;
   if (role == DEX_WS_RESID) return cache_layout(s).total;
-  if (role == DEX_WS_JVP)
-    return jvp_grad_offset(d) + jvp_grad_bytes(s) + 256 + align256(kDotBlocks * 8);
+  if (role == DEX_WS_JVP) return jvp_layout(s).total;
   const size_t nparts = (size_t)(s.g.Npad / 64);  // objective partials (one per 64 points)
   if (role == DEX_WS_FWD) {
     size_t b = align256(nparts * 2 * s.tsize);
@@ -549,26 +683,30 @@ dex_status gmm_fwd(const dex_desc& d, int cfg, const GmmPtrs& in, void* F, void*
   void *xh = cc + cl.xh, *xl = cc + cl.xl, *xhT = cc + cl.xhT, *xlT = cc + cl.xlT, *Qh = cc + cl.Qh,
        *Ql = cc + cl.Ql;
   float *negc = (float*)(cc + cl.negc), *kappa = (float*)(cc + cl.kappa);
+  float* shift = (float*)(cc + cl.shift);
+  hipLaunchKernelGGL(k_shift, dim3(1), dim3(1024), 0, st, mu, (int)s.g.K, (int)s.g.D, shift);
   FlatSplit sp{};
   switch (s.prec) {
     case PREC_BF16:
       if (c.nkq == 0 && qf_eligible(s.g, s.prec)) {
         qf_prep(s.g, x, al, mu, qd, l, xhT, cc + cl.x16, (int*)(cc + cl.texp), cc + cl.W16,
-                (float*)(cc + cl.kq), (float*)(cc + cl.isc), st);
+                (float*)(cc + cl.kq), (float*)(cc + cl.isc), shift, st);
         ProfRange pr(DEX_PROF_GMM_FWD, st);
         sp = qf_fwd(s.g, c, cc + cl.x16, cc + cl.W16, (const float*)(cc + cl.kq),
                     (const float*)(cc + cl.isc), (const int*)(cc + cl.texp), beta, ml, st);
         pr.end(1);
       } else {
         const FwdCfg ck = c.nkq == 0 ? kFwdBF[1] : c;
-        mfma_prep<PREC_BF16>(s.g, x, al, mu, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
+        mfma_prep<PREC_BF16>(s.g, x, al, mu, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, shift,
+                             st);
         ProfRange pr(DEX_PROF_GMM_FWD, st);
         sp = mfma_fwd<PREC_BF16>(s.g, ck, o, beta, ml, st);
         pr.end(1);
       }
       break;
     case PREC_BF16X3:
-      mfma_prep<PREC_BF16X3>(s.g, x, al, mu, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
+      mfma_prep<PREC_BF16X3>(s.g, x, al, mu, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, shift,
+                             st);
       {
         ProfRange pr(DEX_PROF_GMM_FWD, st);
         sp = mfma_fwd<PREC_BF16X3>(s.g, c, o, beta, ml, st);
@@ -576,7 +714,8 @@ dex_status gmm_fwd(const dex_desc& d, int cfg, const GmmPtrs& in, void* F, void*
       }
       break;
     default:
-      mfma_prep<PREC_F32>(s.g, x, al, mu, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
+      mfma_prep<PREC_F32>(s.g, x, al, mu, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, shift,
+                          st);
       {
         ProfRange pr(DEX_PROF_GMM_FWD, st);
         sp = mfma_fwd<PREC_F32>(s.g, c, o, beta, ml, st);
@@ -643,37 +782,70 @@ dex_status gmm_vjp(const dex_desc& d, int cfg, const GmmPtrs& in, const void* f,
                      (int)s.g.D, s.g.DP, s.g.N, (const float*)in.alphas, (const float*)in.means,
                      (const float*)in.qd, (const float*)in.l, (const float*)ct,
                      (float*)out.d_alphas, (float*)out.d_means, (float*)out.d_qd, (float*)out.d_l,
-                     accumulate ? 1 : 0);
+                     accumulate ? 1 : 0, (const float*)(cc + cl.shift));
   return check_hip(hipGetLastError(), "gmm_vjp (MFMA)");
 }
 
 template <typename T>
-static dex_status gmm_jvp_t(const Shape& s, const dex_desc& d, int cfg, const GmmPtrs& in,
-                            const void* f, const void* cache, const GmmGrads& t, void* dF,
-                            void* ws, hipStream_t st) {
-  const int64_t K = s.g.K, D = s.g.D, L = D * (D - 1) / 2;
-  char* gb = (char*)ws + jvp_grad_offset(d);
-  T* g = (T*)gb;
-  T* ct = (T*)(gb + jvp_grad_bytes(s));
-  double* part = (double*)((char*)ct + 256);
-  hipLaunchKernelGGL((k_set_one<T>), dim3(1), dim3(64), 0, st, ct);
-  const GmmGrads gr{g, g + K, g + K + K * D, g + K + 2 * K * D};
-  const dex_status r = gmm_vjp(d, cfg, in, f, cache, ct, gr, false, ws, st);
-  if (r != DEX_OK) return r;
-  hipLaunchKernelGGL((k_dot4_partial<T>), dim3(kDotBlocks), dim3(256), 0, st, (const T*)g, K,
-                     K * D, K * D, K * L, (const T*)t.d_alphas, (const T*)t.d_means,
-                     (const T*)t.d_qd, (const T*)t.d_l, part);
-  hipLaunchKernelGGL((k_dot_final<T>), dim3(1), dim3(256), 0, st, (const double*)part, kDotBlocks,
-                     (T*)dF);
-  return check_hip(hipGetLastError(), "gmm_jvp");
+static void launch_jvp_valu(const Shape& s, const GmmPtrs& in, const void* f, const GmmGrads& t,
+                            double* part, hipStream_t st) {
+  dim3 grid((unsigned)((s.g.N + 255) / 256), (unsigned)((s.g.K + kJvpKC - 1) / kJvpKC));
+#define DEX_JV(DB)                                                                            \
+  hipLaunchKernelGGL((gmm_jvp_valu<T, DB>), grid, dim3(256), 0, st, (const T*)in.alphas,     \
+                     (const T*)in.means, (const T*)in.qd, (const T*)in.l, (const T*)in.x,     \
+                     (const T*)f, (int)s.g.N, (int)s.g.D, (int)s.g.K, (const T*)t.d_alphas,   \
+                     (const T*)t.d_means, (const T*)t.d_qd, (const T*)t.d_l, part)
+  if (s.g.D <= 4)
+    DEX_JV(4);
+  else if (s.g.D <= 8)
+    DEX_JV(8);
+  else if (s.g.D <= 16)
+    DEX_JV(16);
+  else if (s.g.D <= 32)
+    DEX_JV(32);
+  else
+    DEX_JV(64);
+#undef DEX_JV
 }
 
 dex_status gmm_jvp(const dex_desc& d, int cfg, const GmmPtrs& in, const void* f,
                    const void* cache, const GmmGrads& t, void* dF, void* ws, hipStream_t st) {
+  (void)cfg;
   Shape s = shape_of(d);
   if (!valid_shape(s)) return fail(DEX_ERR_UNSUPPORTED, "GMM shape/dtype/variant not supported");
-  if (s.tsize == 8) return gmm_jvp_t<double>(s, d, cfg, in, f, cache, t, dF, ws, st);
-  return gmm_jvp_t<float>(s, d, cfg, in, f, cache, t, dF, ws, st);
+  const JvpLayout jl = jvp_layout(s);
+  char* w = (char*)ws;
+  double* part = (double*)(w + jl.part);
+  if (s.mfma && qf_eligible(s.g, s.prec)) {
+    // tangent products over the same second-order features as the forward
+    const CacheLayout cl = cache_layout(s);
+    const char* cc = (const char*)cache;
+    const float* shift = (const float*)(cc + cl.shift);
+    qf_tan_prep(s.g, (const float*)in.x, (const float*)in.means, (const float*)in.qd,
+                (const float*)in.l, (const float*)t.d_alphas, (const float*)t.d_means,
+                (const float*)t.d_qd, (const float*)t.d_l, shift, w + jl.x16, (int*)(w + jl.texp),
+                w + jl.dW16, (float*)(w + jl.dkq), (float*)(w + jl.disc), st);
+    ProfRange pr(DEX_PROF_GMM_JVP, st);
+    qf_jvp(s.g, w + jl.x16, w + jl.dW16, (const float*)(w + jl.dkq), (const float*)(w + jl.disc),
+           (const int*)(w + jl.texp), (const float*)(cc + cl.beta), (const float*)f, part, st);
+    pr.end(1);
+  } else {
+    ProfRange pr(DEX_PROF_GMM_JVP, st);
+    if (s.tsize == 8)
+      launch_jvp_valu<double>(s, in, f, t, part, st);
+    else
+      launch_jvp_valu<float>(s, in, f, t, part, st);
+    pr.end(1);
+  }
+  if (s.tsize == 8)
+    hipLaunchKernelGGL((k_jvp_final<double>), dim3(1), dim3(256), 0, st, (const double*)part,
+                       jl.nparts, (const double*)in.alphas, (const double*)t.d_alphas, (int)s.g.K,
+                       s.g.N, (double*)dF);
+  else
+    hipLaunchKernelGGL((k_jvp_final<float>), dim3(1), dim3(256), 0, st, (const double*)part,
+                       jl.nparts, (const float*)in.alphas, (const float*)t.d_alphas, (int)s.g.K,
+                       s.g.N, (float*)dF);
+  return check_hip(hipGetLastError(), "gmm_jvp");
 }
 
 }  // namespace dexi

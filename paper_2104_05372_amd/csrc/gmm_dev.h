@@ -379,18 +379,23 @@ struct MfmaOps {
 // zero padded to DP features and Npad points.
 // Optional outputs: xh == nullptr skips x~; tmax != nullptr receives the
 // largest |x| of the tile (for the scaling of the feature-product forward).
+// shift != nullptr: every coordinate of a real point has shift[b] subtracted
+// (the origin moved to the centre of the means, so 16-bit operands carry
+// x - c, not x; every quadratic form in x - mu is unchanged).
 template <int PREC, int DP>
 DEX_DEV void prep_x_tile(const float* __restrict__ x, int N, int D, int Npad, int p0,
                          typename Store<PREC>::S* xh, typename Store<PREC>::S* xl,
                          typename MomT<MomOf<PREC>::MP>::S* xhT,
-                         typename MomT<MomOf<PREC>::MP>::S* xlT, float* tmax = nullptr) {
+                         typename MomT<MomOf<PREC>::MP>::S* xlT, float* tmax = nullptr,
+                         const float* __restrict__ shift = nullptr) {
   __shared__ float tile[64][DP + 1];
   __shared__ float red[16];
   __syncthreads();
   float mx = 0.f;
   for (int e = threadIdx.x; e < 64 * DP; e += blockDim.x) {
     int pp = e / DP, b = e % DP, p = p0 + pp;
-    const float v = (p < N && b < D) ? x[(size_t)p * D + b] : 0.f;
+    const bool in = p < N && b < D;
+    const float v = in ? x[(size_t)p * D + b] - (shift ? shift[b] : 0.f) : 0.f;
     tile[pp][b] = v;
     mx = fmaxf(mx, fabsf(v));
   }
@@ -427,19 +432,20 @@ DEX_DEV void prep_x_tile(const float* __restrict__ x, int N, int D, int Npad, in
 }
 
 // Q~_k (dense DP x DP, zero above the diagonal and in the padding), -c~_k and
-// kappa_k for one component k.
+// kappa_k for one component k (means shifted by shift[] when it is given, as
+// the points are in prep_x_tile).
 template <int PREC, int DP>
 DEX_DEV void prep_q_comp(const float* __restrict__ alphas, const float* __restrict__ means,
                          const float* __restrict__ qd, const float* __restrict__ l, int D, int k,
                          typename Store<PREC>::S* Qh, typename Store<PREC>::S* Ql, float* negc,
-                         float* kappa) {
+                         float* kappa, const float* __restrict__ shift = nullptr) {
   __shared__ float qs[DP][DP + 1];
   __shared__ float mus[DP], qds[DP];
   const int L = D * (D - 1) / 2;
   __syncthreads();
   if (threadIdx.x < DP) {
     const int a = threadIdx.x;
-    mus[a] = a < D ? means[(size_t)k * D + a] : 0.f;
+    mus[a] = a < D ? means[(size_t)k * D + a] - (shift ? shift[a] : 0.f) : 0.f;
     qds[a] = a < D ? qd[(size_t)k * D + a] : 0.f;
   }
   __syncthreads();
@@ -763,7 +769,16 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
   const S* xl = (const S*)xT_lo;
   __shared__ __attribute__((aligned(16))) WT wsh[4][2 * NP][32];
 
+  // FP32 form with few blocks: the products of 8 steps go into a tile of their
+  // own (sinn), which is then added to sacc, so no FP32 sum runs through more
+  // than 16 matrix-core additions plus one per 8 steps (instead of two per
+  // step over the whole point range): the rounding error of the weighted
+  // moments drops several-fold, which matters where the gradient cancels
+  // (dqd = A - exp(qd) M_dd).
+  constexpr bool kBlk = MP == MP_F32 && NBLK <= 3;
   f32x4 sacc[GW][NBLK];
+  f32x4 sinn[kBlk ? GW : 1][kBlk ? NBLK : 1];
+  int nstep = 0;
   float uacc[GW][NB];  // FP32 and split forms: u by lane dot products
   f32x4 uq[NB];        // FP16 form: u = x~^T W, 16 dims x 16 component columns per block
   float aacc[NP];
@@ -773,6 +788,23 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
     for (int q = 0; q < NBLK; ++q) sacc[gk][q] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ab = 0; ab < NB; ++ab) uacc[gk][ab] = 0.f;
+  }
+  auto fold = [&] {
+    if constexpr (kBlk) {
+#pragma unroll
+      for (int gk = 0; gk < GW; ++gk)
+#pragma unroll
+        for (int q = 0; q < NBLK; ++q) {
+          sacc[gk][q] += sinn[gk][q];
+          sinn[gk][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  };
+  if constexpr (kBlk) {
+#pragma unroll
+    for (int gk = 0; gk < GW; ++gk)
+#pragma unroll
+      for (int q = 0; q < NBLK; ++q) sinn[gk][q] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
 #pragma unroll
   for (int ab = 0; ab < NB; ++ab) uq[ab] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -904,12 +936,16 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
         const int q0 = ab * (ab + 1) / 2;
 #pragma unroll
         for (int bb = 0; bb <= ab; ++bb) {
-          f32x4 acc = sacc[gk][q0 + bb];
-          if constexpr (MP == MP_F16X3) {
-            acc = mom_mma1<MP>(sa[1], xt[bb][0], acc);
-            acc = mom_mma1<MP>(sa[0], xt[bb][1], acc);
+          if constexpr (kBlk) {
+            sinn[gk][q0 + bb] = mom_mma1<MP>(sa[0], xt[bb][0], sinn[gk][q0 + bb]);
+          } else {
+            f32x4 acc = sacc[gk][q0 + bb];
+            if constexpr (MP == MP_F16X3) {
+              acc = mom_mma1<MP>(sa[1], xt[bb][0], acc);
+              acc = mom_mma1<MP>(sa[0], xt[bb][1], acc);
+            }
+            sacc[gk][q0 + bb] = mom_mma1<MP>(sa[0], xt[bb][0], acc);
           }
-          sacc[gk][q0 + bb] = mom_mma1<MP>(sa[0], xt[bb][0], acc);
         }
       }
       // the scaling of the next row block overlaps this block's products
@@ -920,6 +956,9 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
       }
     }
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (kBlk) {
+      if ((++nstep & 7) == 0) fold();
+    }
   };
   V8 xA[NB][NS], xB[NB][NS];
   float bA[NP], fA, bB[NP], fB;
@@ -934,6 +973,7 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
     step(t0 + 32, xB, xA, bB, fB);
   }
   if (t0 < pend) step(t0, xA, xB, bA, fA);
+  fold();
 
   // A: lanes 0-31 hold component kw + 2pp, lanes 32-63 component kw + 2pp + 1
   float asum[NP];
@@ -973,13 +1013,15 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
 
 // Final step of the moment form for component k: fixed-order compensated sums
 // over the S partial slots, C_k, then M_k = Q_k C_k and the gradient assembly
-// (FP32 Q_k from qd and l).
+// (FP32 Q_k from qd and l). shift: the origin the moments were taken about
+// (nullptr: zero), subtracted from the means here as from the points.
 DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, int S, int k, int K,
                               int D, int DP, int64_t N, const float* __restrict__ alphas,
                               const float* __restrict__ means, const float* __restrict__ qd,
                               const float* __restrict__ l, float ctv, float* __restrict__ d_alphas,
                               float* __restrict__ d_means, float* __restrict__ d_qd,
-                              float* __restrict__ d_l, int accumulate) {
+                              float* __restrict__ d_l, int accumulate,
+                              const float* __restrict__ shift = nullptr) {
   // Called with 256 threads. C is symmetric; QT holds Q transposed (row
   // stride 68 floats keeps 16-byte rows aligned for vector reads).
   __shared__ __attribute__((aligned(16))) float C[64][65];
@@ -1068,7 +1110,7 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
     const int j = t + 256 * i;
     av[i] = j < K ? alphas[j] : -INFINITY;
   }
-  const float mu_t = t < D ? means[(size_t)k * D + t] : 0.f;
+  const float mu_t = t < D ? means[(size_t)k * D + t] - (shift ? shift[t] : 0.f) : 0.f;
   // softmax normaliser of alpha (components past 1024 read in a second pass)
   float am = fmaxf(fmaxf(av[0], av[1]), fmaxf(av[2], av[3]));
   for (int j = t + 1024; j < K; j += 256) am = fmaxf(am, alphas[j]);

@@ -60,7 +60,7 @@ inline int64_t bwd_max_slots(int64_t Npad, int64_t K) {
 template <int PREC>
 void mfma_prep(const GmmGeom& g, const float* x, const float* alphas, const float* means,
                const float* qd, const float* l, void* xh, void* xl, void* xhT, void* xlT, void* Qh,
-               void* Ql, float* negc, float* kappa, hipStream_t st);
+               void* Ql, float* negc, float* kappa, const float* shift, hipStream_t st);
 template <int PREC>
 FlatSplit mfma_fwd(const GmmGeom& g, const FwdCfg& c, const dexk::MfmaOps& o, float* beta,
                    float2* ml, hipStream_t st);
@@ -74,24 +74,37 @@ FlatSplit mfma_bwd(const GmmGeom& g, const BwdCfg& c, const dexk::MfmaOps& o, co
 // log-sum-exp partials (FlatSplit::sk passes; W holds the block count).
 void qf_prep(const GmmGeom& g, const float* x, const float* alphas, const float* means,
              const float* qd, const float* l, void* xhT, void* x16, int* tile_exp, void* W16,
-             float* kq, float* isc, hipStream_t st);
+             float* kq, float* isc, const float* shift, hipStream_t st);
 FlatSplit qf_fwd(const GmmGeom& g, const FwdCfg& c, const void* x16, const void* W16,
                  const float* kq, const float* isc, const int* tile_exp, float* beta, float2* ml,
                  hipStream_t st);
 inline bool qf_eligible(const GmmGeom& g, int prec) { return prec == dexk::PREC_BF16 && g.D == 64; }
+// Forward mode of the feature-product form: qf_tan_prep writes the scaled FP16
+// copy of x~ (about the forward's origin `shift`), its tile exponents and the
+// tangent coefficient operand with dkq' and its rescale factors; qf_jvp writes
+// one FP64 partial of sum_{i,k} exp(beta_ik - f_i) dbeta_ik per (pass, 64-point
+// tile), qf_tan_parts(g) of them.
+void qf_tan_prep(const GmmGeom& g, const float* x, const float* means, const float* qd,
+                 const float* l, const float* da, const float* dm, const float* dq,
+                 const float* dl, const float* shift, void* x16, int* tile_exp, void* dW16,
+                 float* dkq, float* disc, hipStream_t st);
+int64_t qf_tan_parts(const GmmGeom& g);
+void qf_jvp(const GmmGeom& g, const void* x16, const void* dW16, const float* dkq,
+            const float* disc, const int* tile_exp, const float* beta, const float* f,
+            double* part, hipStream_t st);
 
 template <>
 void mfma_prep<dexk::PREC_F32>(const GmmGeom&, const float*, const float*, const float*,
                                const float*, const float*, void*, void*, void*, void*, void*,
-                               void*, float*, float*, hipStream_t);
+                               void*, float*, float*, const float*, hipStream_t);
 template <>
 void mfma_prep<dexk::PREC_BF16>(const GmmGeom&, const float*, const float*, const float*,
                                 const float*, const float*, void*, void*, void*, void*, void*,
-                                void*, float*, float*, hipStream_t);
+                                void*, float*, float*, const float*, hipStream_t);
 template <>
 void mfma_prep<dexk::PREC_BF16X3>(const GmmGeom&, const float*, const float*, const float*,
                                   const float*, const float*, void*, void*, void*, void*, void*,
-                                  void*, float*, float*, hipStream_t);
+                                  void*, float*, float*, const float*, hipStream_t);
 template <>
 FlatSplit mfma_fwd<dexk::PREC_F32>(const GmmGeom&, const FwdCfg&, const dexk::MfmaOps&, float*,
                               float2*, hipStream_t);

@@ -28,11 +28,12 @@ __global__ void __launch_bounds__(256) k_prep(const float* __restrict__ x, int N
                                               typename MomT<MomOf<PREC>::MP>::S* xlT,
                                               typename Store<PREC>::S* Qh,
                                               typename Store<PREC>::S* Ql, float* negc,
-                                              float* kappa) {
+                                              float* kappa, const float* __restrict__ shift) {
   if ((int)blockIdx.x < K)
-    prep_q_comp<PREC, DP>(alphas, means, qd, l, D, blockIdx.x, Qh, Ql, negc, kappa);
+    prep_q_comp<PREC, DP>(alphas, means, qd, l, D, blockIdx.x, Qh, Ql, negc, kappa, shift);
   else
-    prep_x_tile<PREC, DP>(x, N, D, Npad, (blockIdx.x - K) * 64, xh, xl, xhT, xlT);
+    prep_x_tile<PREC, DP>(x, N, D, Npad, (blockIdx.x - K) * 64, xh, xl, xhT, xlT, nullptr,
+                          shift);
 }
 
 // The grid kernels split their work evenly over the waves (split_lo), so every
@@ -122,7 +123,7 @@ constexpr size_t kQfWLds = 64 * 68 * 4 + 64 * 65 * 4 + (64 + 64 + 12) * 4;
 // tile is past the end only joins the barriers.
 DEX_DEV void qf_x_tile(int tix0, int ntiles, char* smem, const float* __restrict__ x, int N,
                        int Npad, _Float16* __restrict__ xhT, _Float16* __restrict__ x16,
-                       int* __restrict__ tile_exp) {
+                       int* __restrict__ tile_exp, const float* __restrict__ shift) {
   // x~^T for the reverse pass, and x scaled by the tile's 2^-ex (|x| 2^-ex <
   // 2^7) in FP16, row-major, for the feature products
   const int hf = threadIdx.x >> 7, t = threadIdx.x & 127, tix = tix0 + hf;
@@ -132,11 +133,13 @@ DEX_DEV void qf_x_tile(int tix0, int ntiles, char* smem, const float* __restrict
   const int p0 = tix * 64;
   float mx = 0.f;
   if (live) {
+    // x - c: thread t always meets coordinate t & 63
+    const float cs = shift[t & 63];
     float v[32];
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
       const int e = t + 128 * i, p = p0 + (e >> 6);
-      v[i] = p < N ? x[(size_t)p * 64 + (e & 63)] : 0.f;
+      v[i] = p < N ? x[(size_t)p * 64 + (e & 63)] - cs : 0.f;
     }
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
@@ -166,7 +169,7 @@ DEX_DEV void qf_x_tile(int tix0, int ntiles, char* smem, const float* __restrict
     for (int i = 0; i < 8; ++i) h[i] = (_Float16)(tile[pp][b0 + i] * sx);
     *reinterpret_cast<qf::h8*>(x16 + (size_t)(p0 + pp) * 64 + b0) = h;
   }
-  for (int e = t; e < 8 * 64; e += 128) {
+  for (int e = t; xhT && e < 8 * 64; e += 128) {  // (xhT == nullptr: no reverse operand)
     const int b = e / 8, s0 = 8 * (e % 8);
     float v[8];
 #pragma unroll
@@ -181,7 +184,8 @@ DEX_DEV void qf_x_tile(int tix0, int ntiles, char* smem, const float* __restrict
 DEX_DEV void qf_w_comp(int k, char* smem, const float* __restrict__ alphas,
                        const float* __restrict__ means, const float* __restrict__ qd,
                        const float* __restrict__ l, int K, _Float16* __restrict__ W16,
-                       float* __restrict__ kq, float* __restrict__ isc) {
+                       float* __restrict__ kq, float* __restrict__ isc,
+                       const float* __restrict__ shift) {
   constexpr int D = 64, L = D * (D - 1) / 2;
   // Qs: row stride 68 floats keeps 16-byte row pieces aligned for vector reads
   float(*Qs)[68] = reinterpret_cast<float(*)[68]>(smem);
@@ -221,7 +225,7 @@ DEX_DEV void qf_w_comp(int k, char* smem, const float* __restrict__ alphas,
     const float ev = expf(dv[i]);
     qv[i] = a == b ? ev : a > b ? lv[i] : 0.f;
   }
-  const float mu_t = t < D ? means[(size_t)k * D + t] : 0.f;
+  const float mu_t = t < D ? means[(size_t)k * D + t] - shift[t] : 0.f;
   const float qd_t = t < D ? qd[(size_t)k * D + t] : 0.f;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
@@ -311,6 +315,196 @@ DEX_DEV void qf_w_comp(int k, char* smem, const float* __restrict__ alphas,
   }
 }
 
+// Tangent coefficients of component k for forward mode (the slot layout and
+// the power-of-two scaling of qf_w_comp). dQ, the tangent of Q, has diagonal
+// exp(qd) dqd and strict lower part dl; the tangent of P = Q^T Q is
+// dP = G + G^T with G = Q^T dQ. With r = x~ - mu~ (both about the origin c,
+// which the tangent leaves fixed) and dy = dQ r - Q dmu,
+//   y . dy = r^T dP r / 2 - r^T P dmu = (feature . dcoef) / 2 + const,
+// where dcoef is built from (dP, v = dP mu~ + P dmu) exactly as coef is from
+// (P, P mu~), and const = mu~ . (dP mu~ / 2 + P dmu). Hence
+//   dbeta = dkq' - (feature . dcoef) / 2,  dkq' = dalpha + sum_d dqd - const.
+constexpr size_t kQfTLds = 2 * 64 * 68 * 4 + 2 * 64 * 65 * 4 + (5 * 64 + 8) * 4;
+
+DEX_DEV void qf_tan_comp(int k, char* smem, const float* __restrict__ means,
+                         const float* __restrict__ qd, const float* __restrict__ l,
+                         const float* __restrict__ da, const float* __restrict__ dm,
+                         const float* __restrict__ dq, const float* __restrict__ dl, int K,
+                         const float* __restrict__ shift, _Float16* __restrict__ dW16,
+                         float* __restrict__ dkq, float* __restrict__ disc) {
+  constexpr int D = 64, L = D * (D - 1) / 2;
+  float(*Qs)[68] = reinterpret_cast<float(*)[68]>(smem);
+  float(*dQs)[68] = reinterpret_cast<float(*)[68]>(smem + 64 * 68 * 4);
+  float(*P)[65] = reinterpret_cast<float(*)[65]>(smem + 2 * 64 * 68 * 4);
+  float(*G)[65] = reinterpret_cast<float(*)[65]>(smem + 2 * 64 * 68 * 4 + 64 * 65 * 4);
+  float* mus = reinterpret_cast<float*>(smem + 2 * 64 * 68 * 4 + 2 * 64 * 65 * 4);
+  float* dms = mus + 64;
+  float* v = dms + 64;
+  float* Pdm = v + 64;
+  float* dPm = Pdm + 64;
+  float* red = dPm + 64;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const size_t ct = (size_t)(k >> 4), c = (size_t)(k & 15);
+  auto wpos = [&](int ch, int g, int e) {
+    return (((ct * qf::kChunks + ch) * 4 + g) * 16 + c) * 8 + e;
+  };
+  if (k >= K) {  // padding component: zero tangent coefficients
+    for (int s = t; s < qf::kChunks * 32; s += 256)
+      dW16[wpos(s / 32, (s / 8) & 3, s & 7)] = (_Float16)0.f;
+    if (t == 0) {
+      dkq[k] = 0.f;
+      disc[k] = 0.f;
+    }
+    return;
+  }
+  // every global load first, issued together (branch-free, valid addresses)
+  float dv[16], lv[16], ddv[16], dlv[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = t + 256 * i;
+    const int a = e / D, b = e % D;
+    const size_t li = (size_t)k * L + (a > b ? a * (a - 1) / 2 + b : 0);
+    dv[i] = qd[(size_t)k * D + a];
+    ddv[i] = dq[(size_t)k * D + a];
+    lv[i] = l[li];
+    dlv[i] = dl[li];
+  }
+  const float mu_t = t < D ? means[(size_t)k * D + t] - shift[t] : 0.f;
+  const float dm_t = t < D ? dm[(size_t)k * D + t] : 0.f;
+  const float dq_t = t < D ? dq[(size_t)k * D + t] : 0.f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int e = t + 256 * i;
+    const int a = e / D, b = e % D;
+    const float ev = expf(dv[i]);
+    Qs[a][b] = a == b ? ev : a > b ? lv[i] : 0.f;
+    dQs[a][b] = a == b ? ev * ddv[i] : a > b ? dlv[i] : 0.f;
+  }
+  if (t < D) {
+    mus[t] = mu_t;
+    dms[t] = dm_t;
+  }
+  const float sdq = wave_sum(dq_t);  // sum of dqd_k, complete in wave 0
+  __syncthreads();
+  // P = Q^T Q and G = Q^T dQ: thread t owns column b = t % 64 and rows
+  // a = 16 (t / 64) + j; Q[r][a] = 0 for r < a, so the sums start at r = a0
+  const int b = t & 63, a0 = 16 * wv;
+  {
+    float accP[16], accG[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) accP[j] = accG[j] = 0.f;
+#pragma unroll 4
+    for (int r = a0; r < D; ++r) {
+      const float qb = Qs[r][b], dqb = dQs[r][b];
+      const f32x4* qrow = reinterpret_cast<const f32x4*>(&Qs[r][a0]);
+#pragma unroll
+      for (int j4 = 0; j4 < 4; ++j4) {
+        const f32x4 q = qrow[j4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          accP[4 * j4 + i] = fmaf(q[i], qb, accP[4 * j4 + i]);
+          accG[4 * j4 + i] = fmaf(q[i], dqb, accG[4 * j4 + i]);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      P[a0 + j][b] = accP[j];
+      G[a0 + j][b] = accG[j];
+    }
+  }
+  __syncthreads();
+  // dP = G + G^T, into G (read all, then write)
+  {
+    float dp[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) dp[j] = G[a0 + j][b] + G[b][a0 + j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) G[a0 + j][b] = dp[j];
+  }
+  __syncthreads();
+  // P dmu and dP mu~: four threads per row, combined over the quad
+  {
+    const int a = t >> 2, r = t & 3;
+    float s1 = 0.f, s2 = 0.f;
+#pragma unroll 4
+    for (int bb = r; bb < D; bb += 4) {
+      s1 = fmaf(P[a][bb], dms[bb], s1);
+      s2 = fmaf(G[a][bb], mus[bb], s2);
+    }
+    s1 += xor_lane(s1, 1);
+    s1 += xor_lane(s1, 2);
+    s2 += xor_lane(s2, 1);
+    s2 += xor_lane(s2, 2);
+    if (r == 0) {
+      Pdm[a] = s1;
+      dPm[a] = s2;
+      v[a] = s1 + s2;
+    }
+  }
+  __syncthreads();
+  constexpr int kPer = qf::kChunks * 32 / 256;
+  float cv[kPer + 1];
+  float cm = 0.f;
+#pragma unroll
+  for (int i = 0; i <= kPer; ++i) {
+    const int s = t + 256 * i;
+    float val = 0.f;
+    if (s < qf::kChunks * 32) {
+      const int ch = s / 32, g = (s / 8) & 3, e = s & 7;
+      val = qf::coef(4 * ch + (e >> 1), e & 1, g, G, v);
+    }
+    cv[i] = val;
+    cm = fmaxf(cm, fabsf(val));
+  }
+  const float cst = wave_sum(t < D ? mus[t] * (0.5f * dPm[t] + Pdm[t]) : 0.f);
+  cm = wave_max(cm);
+  if (lane == 0) red[wv] = cm;
+  if (t == 0) {
+    red[4] = cst;
+    red[5] = sdq;
+  }
+  __syncthreads();
+  cm = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  int ew = 0;
+  if (cm > 0.f) {
+    int E;
+    frexpf(cm, &E);
+    ew = 14 - E;
+  }
+  const float sw = ldexpf(1.f, ew);
+#pragma unroll
+  for (int i = 0; i <= kPer; ++i) {
+    const int s = t + 256 * i;
+    if (s < qf::kChunks * 32) {
+      const int ch = s / 32, g = (s / 8) & 3, e = s & 7;
+      dW16[wpos(ch, g, e)] = (_Float16)(sw * cv[i]);
+    }
+  }
+  if (t == 0) {
+    dkq[k] = da[k] + red[5] - red[4];
+    disc[k] = ldexpf(1.f, -ew);
+  }
+}
+
+// Forward-mode preparation in one launch: blocks [0, Kp) the tangent
+// coefficients of one component each, the others two 64-point tiles of the
+// scaled FP16 copy of x~ each (no reverse operand).
+__global__ void __launch_bounds__(256) k_qf_tan_prep(
+    const float* __restrict__ x, int N, int Npad, _Float16* __restrict__ x16,
+    int* __restrict__ tile_exp, const float* __restrict__ means, const float* __restrict__ qd,
+    const float* __restrict__ l, const float* __restrict__ da, const float* __restrict__ dm,
+    const float* __restrict__ dq, const float* __restrict__ dl, int K, int Kp,
+    const float* __restrict__ shift, _Float16* __restrict__ dW16, float* __restrict__ dkq,
+    float* __restrict__ disc) {
+  __shared__ __attribute__((aligned(16))) char smem[kQfTLds > 2 * kQfXLds ? kQfTLds : 2 * kQfXLds];
+  if ((int)blockIdx.x < Kp)
+    qf_tan_comp(blockIdx.x, smem, means, qd, l, da, dm, dq, dl, K, shift, dW16, dkq, disc);
+  else
+    qf_x_tile(2 * (blockIdx.x - Kp), Npad / 64, smem, x, N, Npad, nullptr, x16, tile_exp, shift);
+}
+
 // One launch for both parts of the preparation: blocks [0, Kp) build the
 // coefficient operand of one component each (latency-bound), the others two
 // 64-point x tiles each (bandwidth-bound), so the two overlap.
@@ -323,12 +517,13 @@ __global__ void __launch_bounds__(256) k_qf_prep(const float* __restrict__ x, in
                                                  const float* __restrict__ qd,
                                                  const float* __restrict__ l, int K, int Kp,
                                                  _Float16* __restrict__ W16,
-                                                 float* __restrict__ kq, float* __restrict__ isc) {
+                                                 float* __restrict__ kq, float* __restrict__ isc,
+                                                 const float* __restrict__ shift) {
   __shared__ __attribute__((aligned(16))) char smem[kQfWLds > 2 * kQfXLds ? kQfWLds : 2 * kQfXLds];
   if ((int)blockIdx.x < Kp)
-    qf_w_comp(blockIdx.x, smem, alphas, means, qd, l, K, W16, kq, isc);
+    qf_w_comp(blockIdx.x, smem, alphas, means, qd, l, K, W16, kq, isc, shift);
   else
-    qf_x_tile(2 * (blockIdx.x - Kp), Npad / 64, smem, x, N, Npad, xhT, x16, tile_exp);
+    qf_x_tile(2 * (blockIdx.x - Kp), Npad / 64, smem, x, N, Npad, xhT, x16, tile_exp, shift);
 }
 
 // Sum / max over the 16 lanes of a row (DPP: quad swaps, half-row and row
@@ -427,10 +622,17 @@ DEX_DEV void qf_load_x(const _Float16* __restrict__ x16, int pb, int c, int g,
   }
 }
 
+// TAN = false: the forward (beta and log-sum-exp partials). TAN = true: forward
+// mode with the tangent coefficient operand: the same products give dbeta, and
+// each (pass, tile) unit writes sum_{i, k} exp(beta_ik - f_i) dbeta_ik over its
+// 64 points and 32 components into part[pass * ntiles + tile] (FP64), beta and
+// f being the forward's residuals.
+template <bool TAN>
 __global__ void __launch_bounds__(64 * kQfWaves) k_gmm_fwd_qf(
     const _Float16* __restrict__ x16, int N, int Npad, int K, const _Float16* __restrict__ W16,
     const float* __restrict__ kq, const float* __restrict__ isc, const int* __restrict__ tile_exp,
-    int npass, float* __restrict__ beta, float2* __restrict__ ml) {
+    int npass, float* __restrict__ beta, float2* __restrict__ ml, const float* __restrict__ fres,
+    double* __restrict__ part) {
   __shared__ __attribute__((aligned(16))) qf::h8 wsh[qf::kChunks][2][64];
   const int t = threadIdx.x, lane = t & 63, g = lane >> 4, c = lane & 15;
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -482,6 +684,31 @@ __global__ void __launch_bounds__(64 * kQfWaves) k_gmm_fwd_qf(
       __builtin_amdgcn_s_setprio(2);
       qf_chunks(xr, one, wsh, lane, acc, std::make_integer_sequence<int, qf::kChunks>{});
       __builtin_amdgcn_s_setprio(0);
+      if constexpr (TAN) {
+        // dbeta = dkq' - disc 2^(2 ex) / 2 * product, weighted by exp(beta - f)
+        float lsum = 0.f;
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          const int k = pass * qf::kPass + 16 * n + c;  // < Kp: beta has the row
+          const bool vk = k < K;
+          const float kk = kqv[n], is = ldexpf(iscv[n], 2 * ex);
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) {
+            const int p0 = pb + 16 * tt + 4 * g;
+            const f32x4 bv = *reinterpret_cast<const f32x4*>(beta + (size_t)k * Npad + p0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int p = p0 + i;
+              const float fv = fres[min(p, N - 1)];
+              const float w = vk && p < N ? __expf(bv[i] - fv) : 0.f;
+              lsum = fmaf(w, kk - 0.5f * is * acc[tt][n][i], lsum);
+            }
+          }
+        }
+        const double ds = wave_sum((double)lsum);
+        if (lane == 0) part[(size_t)pass * ntiles + (pb >> 6)] = ds;
+        continue;
+      }
       // epilogue: beta = kappa' - isc 2^(2 ex) / 2 * product; log-sum-exp over the pass
 #pragma unroll
       for (int n = 0; n < 2; ++n) {
@@ -550,22 +777,24 @@ using SM = typename MomT<MomOf<P>::MP>::S;
 template <int DP>
 static void prep_dp(const GmmGeom& g, const float* x, const float* alphas, const float* means,
                     const float* qd, const float* l, void* xh, void* xl, void* xhT, void* xlT,
-                    void* Qh, void* Ql, float* negc, float* kappa, hipStream_t st) {
+                    void* Qh, void* Ql, float* negc, float* kappa, const float* shift,
+                    hipStream_t st) {
   hipLaunchKernelGGL((k_prep<P, DP>), dim3((unsigned)(g.K + g.Npad / 64)), dim3(256), 0, st, x,
                      (int)g.N, (int)g.D, (int)g.Npad, (int)g.K, alphas, means, qd, l, (S*)xh,
-                     (S*)xl, (SM*)xhT, (SM*)xlT, (S*)Qh, (S*)Ql, negc, kappa);
+                     (S*)xl, (SM*)xhT, (SM*)xlT, (S*)Qh, (S*)Ql, negc, kappa, shift);
 }
 
 template <>
 void mfma_prep<P>(const GmmGeom& g, const float* x, const float* alphas, const float* means,
                   const float* qd, const float* l, void* xh, void* xl, void* xhT, void* xlT,
-                  void* Qh, void* Ql, float* negc, float* kappa, hipStream_t st) {
+                  void* Qh, void* Ql, float* negc, float* kappa, const float* shift,
+                  hipStream_t st) {
   if (g.DP == 16)
-    prep_dp<16>(g, x, alphas, means, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
+    prep_dp<16>(g, x, alphas, means, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, shift, st);
   else if (g.DP == 32)
-    prep_dp<32>(g, x, alphas, means, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
+    prep_dp<32>(g, x, alphas, means, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, shift, st);
   else
-    prep_dp<64>(g, x, alphas, means, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, st);
+    prep_dp<64>(g, x, alphas, means, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, shift, st);
 }
 
 // Resident 256-thread blocks of `kernel` per CU.
@@ -669,12 +898,12 @@ FlatSplit mfma_bwd<P>(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const
 #if DEX_PREC == 1
 void qf_prep(const GmmGeom& g, const float* x, const float* alphas, const float* means,
              const float* qd, const float* l, void* xhT, void* x16, int* tile_exp, void* W16,
-             float* kq, float* isc, hipStream_t st) {
+             float* kq, float* isc, const float* shift, hipStream_t st) {
   const int ntiles = (int)(g.Npad / 64);
   const int Kp = (int)((g.K + qf::kPass - 1) / qf::kPass * qf::kPass);
   hipLaunchKernelGGL(k_qf_prep, dim3((unsigned)(Kp + (ntiles + 1) / 2)), dim3(256), 0, st, x,
                      (int)g.N, (int)g.Npad, (_Float16*)xhT, (_Float16*)x16, tile_exp, alphas, means, qd, l,
-                     (int)g.K, Kp, (_Float16*)W16, kq, isc);
+                     (int)g.K, Kp, (_Float16*)W16, kq, isc, shift);
 }
 
 FlatSplit qf_fwd(const GmmGeom& g, const FwdCfg& c, const void* x16, const void* W16,
@@ -685,10 +914,36 @@ FlatSplit qf_fwd(const GmmGeom& g, const FwdCfg& c, const void* x16, const void*
   sp.sk = (int)((g.K + qf::kPass - 1) / qf::kPass);
   sp.T = (int64_t)sp.sk * (g.Npad / 64);
   sp.W = std::max(8, num_cus() / 8 * 8);  // one block per CU, a multiple of 8
-  hipLaunchKernelGGL(k_gmm_fwd_qf, dim3((unsigned)sp.W), dim3(64 * kQfWaves), 0, st,
+  hipLaunchKernelGGL(k_gmm_fwd_qf<false>, dim3((unsigned)sp.W), dim3(64 * kQfWaves), 0, st,
                      (const _Float16*)x16, (int)g.N, (int)g.Npad, (int)g.K, (const _Float16*)W16,
-                     kq, isc, tile_exp, sp.sk, beta, ml);
+                     kq, isc, tile_exp, sp.sk, beta, ml, (const float*)nullptr, (double*)nullptr);
   return sp;
+}
+
+void qf_tan_prep(const GmmGeom& g, const float* x, const float* means, const float* qd,
+                 const float* l, const float* da, const float* dm, const float* dq,
+                 const float* dl, const float* shift, void* x16, int* tile_exp, void* dW16,
+                 float* dkq, float* disc, hipStream_t st) {
+  const int ntiles = (int)(g.Npad / 64);
+  const int Kp = (int)((g.K + qf::kPass - 1) / qf::kPass * qf::kPass);
+  hipLaunchKernelGGL(k_qf_tan_prep, dim3((unsigned)(Kp + (ntiles + 1) / 2)), dim3(256), 0, st, x,
+                     (int)g.N, (int)g.Npad, (_Float16*)x16, tile_exp, means, qd, l, da, dm, dq, dl,
+                     (int)g.K, Kp, shift, (_Float16*)dW16, dkq, disc);
+}
+
+int64_t qf_tan_parts(const GmmGeom& g) {
+  return (g.K + qf::kPass - 1) / qf::kPass * (g.Npad / 64);
+}
+
+void qf_jvp(const GmmGeom& g, const void* x16, const void* dW16, const float* dkq,
+            const float* disc, const int* tile_exp, const float* beta, const float* f,
+            double* part, hipStream_t st) {
+  const int npass = (int)((g.K + qf::kPass - 1) / qf::kPass);
+  const int blocks = std::max(8, num_cus() / 8 * 8);
+  hipLaunchKernelGGL(k_gmm_fwd_qf<true>, dim3((unsigned)blocks), dim3(64 * kQfWaves), 0, st,
+                     (const _Float16*)x16, (int)g.N, (int)g.Npad, (int)g.K, (const _Float16*)dW16,
+                     dkq, disc, tile_exp, npass, const_cast<float*>(beta), (float2*)nullptr, f,
+                     part);
 }
 #endif
 

@@ -43,8 +43,9 @@ size_t gmm_ws_bytes(const dex_desc& d, int role);
 int gmm_num_configs(const dex_desc& d, int role);
 dex_status gmm_fwd(const dex_desc& d, int cfg, const GmmPtrs& in, void* F, void* f,
                    void* cache, void* ws, hipStream_t s);
-// Forward mode of the scalar objective: dF = <grad F, t> (reverse pass with
-// cotangent 1, then a fixed-order compensated inner product with t).
+// Forward mode of the scalar objective: the linearized loop run forward over
+// the tangents (matrix-core tangent products for the 16-bit variant at D = 64,
+// a vector-ALU pass otherwise), FP64 fixed-order sums.
 dex_status gmm_jvp(const dex_desc& d, int cfg, const GmmPtrs& in, const void* f,
                    const void* cache, const GmmGrads& t, void* dF, void* ws, hipStream_t st);
 dex_status gmm_vjp(const dex_desc& d, int cfg, const GmmPtrs& in, const void* f,

@@ -366,7 +366,7 @@ def dex_autotune_reset():
 
 DEX_PROF = dict(GMM_FWD=0, GMM_VJP=1, SCATTER=2, HIST=3, GATHER=4, GATHER_DW=5, BGMM_FWD=6,
                 BGMM_VJP=7, STENCIL_FWD=8, STENCIL_VJP=9, GATHER_JVP=10, REDUCE_ROWS=11,
-                REDUCE_ALL=12)
+                REDUCE_ALL=12, GMM_JVP=13)
 
 
 def dex_profile_enable(on: bool = True):

@@ -86,8 +86,12 @@ def test_forward_mode_argument_checks(dex):
     assert dex.dex_workspace_bytes(d, dex.DEX_WS_JVP) == 0
     assert _status(lambda: dex.dex_jvp(d, [T, idx, w], [tT, tw], [out], None, resid=[out])) \
         == dex.DEX_ERR_INVALID_ARG
+    # the matrix-core tangent pass holds its own FP16 copy of x (N_pad x 64) and
+    # the tangent coefficient operand; the vector-ALU pass only its partial sums
     gd = dex.gmm_desc(100_000, 64, 200, dex.DEX_F32, dex.DEX_GMM_BF16)
-    assert dex.dex_workspace_bytes(gd, dex.DEX_WS_JVP) > dex.dex_workspace_bytes(gd, dex.DEX_WS_VJP)
+    assert dex.dex_workspace_bytes(gd, dex.DEX_WS_JVP) >= 100_096 * 64 * 2 + 224 * 2176 * 2
+    gv = dex.gmm_desc(1000, 5, 20, dex.DEX_F32, dex.DEX_GMM_PLAIN)
+    assert 0 < dex.dex_workspace_bytes(gv, dex.DEX_WS_JVP) < 1 << 16
 
 
 def test_accum_scatter_argument_checks(dex):
@@ -208,3 +212,65 @@ def test_reduction_binding_rejects_bad_tensors(dex):
     for o, x, w in bad_all:
         with pytest.raises(ValueError):
             dex.dex_reduce_all(o, x, w)
+
+
+def test_undersized_workspace_rejected_on_host(dex):
+    """Every entry point that takes a workspace refuses a missing or one-byte
+    short one with DEX_ERR_WORKSPACE, on the host, before any device work."""
+    import torch
+    u8 = torch.uint8
+
+    def short(n):
+        return torch.zeros(max(n - 1, 0), dtype=u8)
+
+    N, D, K = 300, 8, 4
+    L = D * (D - 1) // 2
+    for variant in (dex.DEX_GMM_PLAIN, dex.DEX_GMM_BF16):
+        d = dex.gmm_desc(N, D, K, dex.DEX_F32, variant)
+        ins = [torch.zeros(K), torch.zeros(K, D), torch.zeros(K, D), torch.zeros(K, L), torch.zeros(N, D)]
+        resid = [torch.zeros(N), torch.zeros(dex.dex_workspace_bytes(d, dex.DEX_WS_RESID), dtype=u8)]
+        grads = [torch.zeros_like(t) for t in ins[:4]]
+        calls = {
+            dex.DEX_WS_FWD: lambda ws: dex.dex_fwd(d, ins, [torch.zeros(1)], resid, ws),
+            dex.DEX_WS_VJP: lambda ws: dex.dex_vjp(d, ins, resid, [torch.ones(1)], grads, 0, ws),
+            dex.DEX_WS_JVP: lambda ws: dex.dex_jvp(d, ins, grads, [torch.zeros(1)], ws, resid=resid),
+        }
+        for role, call in calls.items():
+            need = dex.dex_workspace_bytes(d, role)
+            assert need > 0, (variant, role)
+            for ws in (None, short(need)):
+                assert _status(call, ws) == dex.DEX_ERR_WORKSPACE, (variant, role, need)
+    # the checkpointed loop's reverse pass and forward mode
+    st = dex.stencil_desc(32, 32, 10, 4, rho=0.1)
+    u = [torch.zeros(32, 32), torch.zeros(32, 32)]
+    ck = [torch.zeros(3 * 32 * 32), torch.zeros(32, 32)]
+    for role, call in ((dex.DEX_WS_VJP, lambda ws: dex.dex_vjp(st, u, ck, [torch.ones(1)],
+                                                                [torch.zeros(32, 32)], 0, ws)),
+                       (dex.DEX_WS_JVP, lambda ws: dex.dex_jvp(st, u, u, [torch.zeros(1)], ws))):
+        need = dex.dex_workspace_bytes(st, role)
+        assert need > 0
+        for ws in (None, short(need)):
+            assert _status(call, ws) == dex.DEX_ERR_WORKSPACE, role
+    # the deterministic (sorted) transposed gather
+    gd = dex.gather_desc(100, 8, 1000)
+    gd.config = 2
+    T, idx, w = torch.zeros(100, 8), torch.zeros(1000, dtype=torch.int32), torch.zeros(1000)
+    need = dex.dex_workspace_bytes(gd, dex.DEX_WS_VJP)
+    assert need > 0
+    for ws in (None, short(need)):
+        assert _status(dex.dex_vjp, gd, [T, idx, w], [], [torch.zeros(1000, 8)],
+                       [torch.zeros(100, 8), torch.zeros(1000)], 0, ws) == dex.DEX_ERR_WORKSPACE
+    # dex_accum_scatter: the histogram's private counters and the sorted float form
+    h = torch.zeros(65536, dtype=torch.int32)
+    keys = torch.zeros(1 << 12, dtype=torch.int32)
+    need = dex.dex_accum_scatter_workspace_bytes(dex.DEX_I32, 65536, 1, 1 << 12, False)
+    assert _status(lambda: dex.dex_accum_scatter(h, keys, ws=short(need))) == dex.DEX_ERR_WORKSPACE
+    acc, vals = torch.zeros(100, 8), torch.zeros(1000, 8)
+    need = dex.dex_accum_scatter_workspace_bytes(dex.DEX_F32, 100, 8, 1000, True, dex.DEX_DETERMINISTIC)
+    assert need > 0
+    assert _status(lambda: dex.dex_accum_scatter(acc, idx, vals, flags=dex.DEX_DETERMINISTIC,
+                                                 ws=short(need))) == dex.DEX_ERR_WORKSPACE
+    # the complete reduction
+    L_ = dex.lib()
+    assert L_.dex_reduce_all(ctypes.c_void_p(16), ctypes.c_void_p(16), 5, 0, None, 0, None) \
+        == dex.DEX_ERR_WORKSPACE

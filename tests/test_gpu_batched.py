@@ -85,11 +85,44 @@ def test_per_instance_cotangents(dev):
     check_instances(shapes, insts, got, range(len(insts)), ct)
 
 
-def test_full_batch_sampled(dev):
-    """512 instances, N ~ U[1000, 50000], D in {8,16,32}, K ~ U[10,100]."""
+def _oracle_instance(args):
+    """Objective, f and gradient of one instance (regenerated from its seed)."""
+    b, (N, D, K), seed_base = args
+    g = workloads.gmm_inputs(int(N), int(D), int(K), seed_base + 1 + b, np.float32)
+    Fo, fo = ogmm.objective(*g.params(), g.x)
+    return b, Fo, fo, ogmm.vjp(*g.params(), g.x, fo)
+
+
+@pytest.mark.timeout(600)
+def test_full_batch_every_instance(dev):
+    """512 instances, N ~ U[1000, 50000], D in {8,16,32}, K ~ U[10,100], in the
+    benchmark's single launch per phase; every instance's F, f and gradient
+    against the oracle (the oracle runs on a pool of host threads)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
     shapes = workloads.batched_shapes()
     insts = workloads.batched_inputs(shapes)
-    got = run_batched(shapes, insts)
+    F, f, grads = run_batched(shapes, insts)
+    del insts
+    fs = split(shapes, f, lambda N, D, K: N)
+    ga = split(shapes, grads[0], lambda N, D, K: K)
+    gm = split(shapes, grads[1], lambda N, D, K: K * D)
+    gq = split(shapes, grads[2], lambda N, D, K: K * D)
+    gl = split(shapes, grads[3], lambda N, D, K: K * D * (D - 1) // 2)
+    base = workloads.BATCHED["seed"]
     cost = shapes[:, 0] * shapes[:, 2] * shapes[:, 1] ** 2
-    which = sorted({int(np.argmax(cost)), int(np.argmin(cost)), 0, 511, 100, 257})
-    check_instances(shapes, insts, got, which)
+    order = [int(b) for b in np.argsort(-cost)]  # largest first
+    workers = max(1, min(16, os.cpu_count() or 1))
+    print(f"  oracle for {len(order)} instances on {workers} threads", flush=True)
+    bad = []
+    with threadpool_limits(1), ThreadPoolExecutor(workers) as ex:
+        for done, (b, Fo, fo, go) in enumerate(
+                ex.map(_oracle_instance, [(b, shapes[b], base) for b in order])):
+            errs = [abs(F[b] - Fo) / abs(Fo), rel(fs[b], fo)] + \
+                [rel(a, o.ravel()) for a, o in zip((ga[b], gm[b], gq[b], gl[b]), go)]
+            if max(errs) > 1e-5:
+                bad.append((b, errs))
+            if done % 128 == 127:
+                print(f"  {done + 1} instances checked", flush=True)
+    assert not bad, bad[:5]
