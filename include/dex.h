@@ -280,6 +280,18 @@ dex_status dex_reduce_rows(float* out, const float* values, int64_t rows, int64_
 dex_status dex_reduce_all(float* out, const float* values, int64_t n, uint32_t flags,
                           void* workspace, size_t ws_bytes, void* hip_stream);
 
+/* dex_reduce_all without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). It allocates nothing: the per-block FP64
+ * partials go to a fixed 8 KiB array (1024 doubles) that the library holds in
+ * each GPU's memory from the first call on that GPU (or dex_init) until the
+ * process ends. That size does not depend on n, so any n >= 0 is accepted;
+ * arguments and flags otherwise as for dex_reduce_all, and the result is bit
+ * for bit the same. Calls that overlap on one GPU (other streams, other host
+ * threads) share the array and race; calls on one stream are ordered. */
+dex_status dex_reduce_all_noalloc(float* out, const float* values, int64_t n, uint32_t flags,
+                                  void* hip_stream);
+
 /*
  * acc!(idx[j]) += scale[j] * vals[j, :]  for j in [0, n)      (Sec. 2.3.2-2.3.3)
  *

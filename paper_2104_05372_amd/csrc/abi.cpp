@@ -34,6 +34,7 @@ namespace {
 struct DevInfo {
   bool checked = false;
   bool ok = false;
+  bool scratch_ready = false;
   int cus = 0;
   char arch[64] = "";
 };
@@ -131,6 +132,11 @@ static dex_status ensure_device() {
     di.checked = true;
   }
   if (!di.ok) return fail(DEX_ERR_UNSUPPORTED, "device %d is %s, libdexmi is built for gfx950", dev, di.arch);
+  if (!di.scratch_ready) {  // per-device address of the library's own scratch array
+    const dex_status st = reduce_scratch_init();
+    if (st != DEX_OK) return st;
+    di.scratch_ready = true;
+  }
   return DEX_OK;
 }
 
@@ -494,6 +500,15 @@ dex_status dex_reduce_all(float* out, const float* values, int64_t n, uint32_t f
     return fail(DEX_ERR_WORKSPACE, "workspace of %d bytes needed", DEX_REDUCE_WS_BYTES);
   DEX_TRY(ensure_device());
   return reduce_all(out, values, n, flags & DEX_ACCUMULATE, workspace, (hipStream_t)hip_stream);
+}
+
+dex_status dex_reduce_all_noalloc(float* out, const float* values, int64_t n, uint32_t flags,
+                                  void* hip_stream) {
+  if (n < 0) return fail(DEX_ERR_INVALID_ARG, "negative size");
+  if (!out || (n > 0 && !values)) return fail(DEX_ERR_INVALID_ARG, "null buffer");
+  if (flags & ~DEX_ACCUMULATE) return fail(DEX_ERR_INVALID_ARG, "unknown flags");
+  DEX_TRY(ensure_device());
+  return reduce_all_noalloc(out, values, n, flags & DEX_ACCUMULATE, (hipStream_t)hip_stream);
 }
 
 dex_status dex_vjp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex_buf* resid,

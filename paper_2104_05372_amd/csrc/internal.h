@@ -86,6 +86,12 @@ dex_status reduce_rows(float* out, const float* values, int64_t rows, int64_t co
                        bool accumulate, hipStream_t s);
 dex_status reduce_all(float* out, const float* values, int64_t n, bool accumulate, void* ws,
                       hipStream_t s);
+// The allocation-free complete reduction: partials in the library's own
+// per-GPU device array, whose address reduce_scratch_init looks up once per
+// device (called from device set-up).
+dex_status reduce_scratch_init();
+dex_status reduce_all_noalloc(float* out, const float* values, int64_t n, bool accumulate,
+                              hipStream_t s);
 
 // ----------------------------------------------------------- stencil -----
 dex_status stencil_jvp(const dex_desc& d, const float* u0, const float* target, const float* du0,

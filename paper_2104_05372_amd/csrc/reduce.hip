@@ -4,6 +4,9 @@
 //   complete   for i.   acc   += values.i     -> out    = sum_i values[i]
 // Both are HBM bound (4 bytes per value) and sum in FP64 in a fixed order, so
 // the results do not depend on scheduling.
+#include <mutex>
+#include <unordered_map>
+
 #include "common.h"
 #include "internal.h"
 
@@ -86,8 +89,34 @@ __global__ void reduce_all_final(const double* __restrict__ part, int nb, bool a
 
 }  // namespace dexk
 
+// Scratch of the allocation-free complete reduction: the FP64 block partials,
+// in device memory the library itself holds (one copy per GPU, until the
+// process ends). On the host `scratch` is only a stand-in symbol, never a
+// device address: host code uses the address hipGetSymbolAddress returns for
+// the current device, kept per device by reduce_scratch_init.
+static __device__ __align__(256) double scratch[dexi::kReduceBlocks];
+
 namespace dexi {
 using namespace dexk;
+
+namespace {
+std::mutex g_scratch_mu;
+std::unordered_map<int, void*> g_scratch;  // device -> address of its `scratch`
+}  // namespace
+
+dex_status reduce_scratch_init() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return check_hip(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch.count(dev)) return DEX_OK;
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) return check_hip(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                              "hipGetSymbolAddress(scratch)");
+  g_scratch[dev] = p;
+  return DEX_OK;
+}
 
 dex_status reduce_rows(float* out, const float* values, int64_t rows, int64_t cols,
                        bool accumulate, hipStream_t s) {
@@ -125,6 +154,23 @@ dex_status reduce_all(float* out, const float* values, int64_t n, bool accumulat
                      accumulate, out);
   pr.end(1);
   return check_hip(hipGetLastError(), "reduce_all");
+}
+
+dex_status reduce_all_noalloc(float* out, const float* values, int64_t n, bool accumulate,
+                              hipStream_t s) {
+  const dex_status st = reduce_scratch_init();
+  if (st != DEX_OK) return st;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return check_hip(e, "hipGetDevice");
+  void* p = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    p = g_scratch[dev];
+  }
+  // every partial is written by the first kernel before the second reads it,
+  // so nothing has to be cleared between calls
+  return reduce_all(out, values, n, accumulate, p, s);
 }
 
 }  // namespace dexi

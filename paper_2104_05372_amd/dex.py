@@ -38,7 +38,7 @@ DEX_WS_FWD, DEX_WS_VJP, DEX_WS_RESID, DEX_WS_JVP = 0, 1, 2, 3
 EXPORTS = (
     "dex_status_string", "dex_last_error", "dex_version", "dex_init", "dex_workspace_bytes",
     "dex_num_configs", "dex_fwd", "dex_vjp", "dex_jvp", "dex_reduce_rows", "dex_reduce_all",
-    "dex_accum_scatter",
+    "dex_reduce_all_noalloc", "dex_accum_scatter",
     "dex_accum_scatter_workspace_bytes", "dex_gmm_batched_plan", "dex_autotune",
     "dex_autotune_reset", "dex_profile_enable", "dex_profile_read", "dex_profile_reset",
 )
@@ -92,6 +92,8 @@ def lib():
         L.dex_reduce_rows.restype = S
         L.dex_reduce_all.argtypes = [P, P, I64, ctypes.c_uint32, P, SZ, P]
         L.dex_reduce_all.restype = S
+        L.dex_reduce_all_noalloc.argtypes = [P, P, I64, ctypes.c_uint32, P]
+        L.dex_reduce_all_noalloc.restype = S
         L.dex_accum_scatter.argtypes = [P, I32, I64, I64, P, I32, P, P, I64, ctypes.c_uint32, P, P, SZ, P]
         L.dex_accum_scatter.restype = S
         L.dex_accum_scatter_workspace_bytes.argtypes = [I32, I64, I64, I64, I32, ctypes.c_uint32,
@@ -284,6 +286,18 @@ def dex_reduce_all(out: torch.Tensor, values: torch.Tensor, ws: torch.Tensor, fl
     _check_device(ws, "ws")
     check(lib().dex_reduce_all(_ptr(out), _ptr(values), values.numel(), flags, _ptr(ws),
                                ws.numel(), stream_ptr(stream)))
+
+
+def dex_reduce_all_noalloc(out: torch.Tensor, values: torch.Tensor, flags=0, stream=None):
+    """out[0] (=|+=) sum of all of float32 `values`, with no workspace: the
+    library's own per-GPU scratch holds the partials (calls that overlap on one
+    GPU race)."""
+    _f32_buffer(values, "values")
+    _f32_buffer(out, "out")
+    if out.numel() != 1:
+        raise ValueError(f"out must hold one value, got {out.numel()}")
+    check(lib().dex_reduce_all_noalloc(_ptr(out), _ptr(values), values.numel(), flags,
+                                       stream_ptr(stream)))
 
 
 def dex_vjp(d: DexDesc, ins, resid, ct_out, ct_in, flags=0, ws: torch.Tensor | None = None,

@@ -270,7 +270,7 @@ def test_undersized_workspace_rejected_on_host(dex):
     assert need > 0
     assert _status(lambda: dex.dex_accum_scatter(acc, idx, vals, flags=dex.DEX_DETERMINISTIC,
                                                  ws=short(need))) == dex.DEX_ERR_WORKSPACE
-    # the complete reduction
+    # the complete reduction (its allocation-free form takes none)
     L_ = dex.lib()
     assert L_.dex_reduce_all(ctypes.c_void_p(16), ctypes.c_void_p(16), 5, 0, None, 0, None) \
         == dex.DEX_ERR_WORKSPACE
