@@ -74,6 +74,22 @@ def timed(fn, steps, sync):
     return (time.perf_counter() - t0) / steps
 
 
+CHECK = {"on": True}  # the rows' oracle checks (off for profiling runs)
+
+
+def rel_l2(a, b):
+    import numpy as np
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cpu_timed(fn):
+    t0 = time.perf_counter()
+    r = fn()
+    return r, time.perf_counter() - t0
+
+
 # ---------------------------------------------------------------------------
 def gmm_setup(torch, dex, g, variant, dev, configs=None):
     t = [torch.tensor(a, device=dev) for a in (g.alphas, g.means, g.qd, g.l, g.x)]
@@ -202,7 +218,7 @@ def run_fp32_form(torch, dex, g, dev, steps):
 
 
 # ---------------------------------------------------------------------------
-def row_scatter(torch, dex, workloads, dev, steps, scatter_config=1):
+def row_scatter(torch, dex, workloads, dev, steps, scatter_config=1, check=True):
     import numpy as np
     c = workloads.SCATTER
     V, R, n = c["rows"], c["row_len"], c["n"]
@@ -242,8 +258,8 @@ def row_scatter(torch, dex, workloads, dev, steps, scatter_config=1):
     j_ms = timed(jvp, steps, torch.cuda.synchronize) * 1e3 if scatter_config == 1 else None
     dex.dex_profile_enable(False)
     res = {"workload": f"gather/scatter table {V}x{R} f32, {n} Zipf(1.1) indices",
-           "scatter_form": {1: "block sort + run sums + atomics", 2: "radix sort, fixed-order run sums"}[
-               scatter_config],
+           "scatter_form": {1: "radix sort, one owner per row, no atomics",
+                            2: "block sort + run sums + atomics"}[scatter_config],
            "fwd_ms": round(f_ms, 4), "vjp_ms": round(b_ms, 4), "bwd_fwd_ratio": round(b_ms / f_ms, 3),
            "touched_rows": touched}
     bytes_k = {"GATHER": 2 * n * 4 + 2 * n * R * 4, "SCATTER": 2 * n * 4 + n * R * 4 + touched * R * 4,
@@ -256,8 +272,54 @@ def row_scatter(torch, dex, workloads, dev, steps, scatter_config=1):
         a = b / (ms / max(cnt, 1) * 1e-3) / 1e9
         res[k.lower()] = {"avg_ms": round(ms / max(cnt, 1), 4), "GBps": round(a, 1),
                           "frac_hbm": round(a / PEAK["hbm"], 4), "bytes_per_launch": b}
+    if check and CHECK["on"]:
+        res.update(scatter_vs_oracle(torch, idx_np, T, w, g, out, dT, dw, fwd, vjp, V))
     del T, g, out, dT
     return res
+
+
+def scatter_vs_oracle(torch, idx_np, T, w, g, out, dT, dw, fwd, vjp, V):
+    """The reverse pass's cotangent rows of a sample of rows (the three hottest,
+    61 others drawn among the touched rows, 4 untouched) and 64 sampled dw_j and
+    gathered rows, against the FP64 oracle applied to the entries they depend on;
+    and the oracle's own time on the first 2^18 indices, scaled to all of them."""
+    import numpy as np
+    from oracle import scatter as osc
+    fwd()
+    vjp()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    rows, cnt = np.unique(idx_np, return_counts=True)
+    hot = rows[np.argsort(-cnt)[:3]]
+    untouched = np.setdiff1d(np.arange(2000), rows)[:4]
+    sample = np.concatenate([hot, rng.choice(rows, 61, replace=False), untouched])
+    order = np.argsort(idx_np, kind="stable")
+    sidx = idx_np[order]
+    dT_s = dT[torch.tensor(sample.astype(np.int64), device=dT.device)].cpu().numpy()
+    w_np = w.cpu().numpy()
+    want = []
+    for v in sample:
+        a, b = np.searchsorted(sidx, v), np.searchsorted(sidx, v, side="right")
+        js = order[a:b]
+        gs = g[torch.tensor(js.astype(np.int64), device=g.device)].cpu().numpy()
+        want.append(osc.scatter_rows([v], idx_np[js], w_np[js], gs)[0])
+    js = rng.integers(0, idx_np.size, 64)
+    jt = torch.tensor(js.astype(np.int64), device=g.device)
+    Ts = T[torch.tensor(idx_np[js].astype(np.int64), device=T.device)].cpu().numpy()
+    gs = g[jt].cpu().numpy()
+    loc = np.arange(64)
+    err = {"dT_sampled_rows": rel_l2(dT_s, np.array(want)),
+           "dw_sampled": rel_l2(dw[jt].cpu().numpy(), osc.scatter_dw(Ts, loc, gs)),
+           "out_sampled": rel_l2(out[jt].cpu().numpy(), osc.gather(Ts, loc, w_np[js]))}
+    m = 1 << 18
+    g_m = g[:m].cpu().numpy()
+    _, t = cpu_timed(lambda: osc.scatter(V, idx_np[:m], w_np[:m], g_m))
+    n = idx_np.size
+    return {"rel_l2_vs_fp64_oracle": {k: float(f"{v:.3e}") for k, v in err.items()},
+            "cpu_oracle": {"ms_per_call": round(t * n / m * 1e3, 1), "cores": 1,
+                           "sample": f"FP64 oracle scatter on the first {m} of {n} indices, "
+                                     f"{t:.2f} s, times {n // m} (one thread; the sample includes "
+                                     f"the table's FP64 zero fill)"}}
 
 
 def row_histogram(torch, dex, workloads, dev, steps):
@@ -280,10 +342,23 @@ def row_histogram(torch, dex, workloads, dev, steps):
     kms, kn = dex.dex_profile_read("HIST")
     b = c["n"] * 4 + c["bins"] * 4
     a = b / (kms / max(kn, 1) * 1e-3) / 1e9
-    return {"workload": f"int32 histogram of 2^26 Zipf(1.1) keys mod {c['bins']}",
-            "ms": round(ms, 4), "hist_kernel": {"avg_ms": round(kms / max(kn, 1), 4), "GBps": round(a, 1),
-                                                 "frac_hbm": round(a / PEAK["hbm"], 4),
-                                                 "bytes_per_launch": b}}
+    res = {"workload": f"int32 histogram of 2^26 Zipf(1.1) keys mod {c['bins']}",
+           "ms": round(ms, 4), "hist_kernel": {"avg_ms": round(kms / max(kn, 1), 4), "GBps": round(a, 1),
+                                                "frac_hbm": round(a / PEAK["hbm"], 4),
+                                                "bytes_per_launch": b}}
+    if not CHECK["on"]:
+        return res
+    import numpy as np
+    from oracle import scatter as osc
+    h.zero_()
+    run()
+    got = h.cpu().numpy()
+    keys_np = keys.cpu().numpy().view(np.uint32)
+    want, t = cpu_timed(lambda: osc.histogram(keys_np, c["bins"]))
+    res["bit_exact_vs_oracle"] = bool(np.array_equal(got, want))
+    res["cpu_oracle"] = {"ms_per_call": round(t * 1e3, 1), "cores": 1,
+                         "sample": "FP64/int64 oracle on all 2^26 keys (one thread)"}
+    return res
 
 
 def row_batched(torch, dex, workloads, dev, steps):
@@ -331,6 +406,36 @@ def row_batched(torch, dex, workloads, dev, steps):
         a = fl / (ms / max(cnt, 1) * 1e-3) / 1e12
         res[k.lower()] = {"avg_ms": round(ms / max(cnt, 1), 4), "tflops": round(a, 2),
                           "frac_fp32": round(a / PEAK["fp32"], 4)}
+    if not CHECK["on"]:
+        return res
+    # a sample of instances against the FP64 oracle (the largest, the smallest
+    # and two others), and the oracle's time on them scaled by algorithmic cost
+    from oracle import gmm as ogmm
+    fwd()
+    vjp()
+    torch.cuda.synchronize()
+    Fg, fg, gg = F.cpu().numpy(), f.cpu().numpy(), [x.cpu().numpy() for x in grads]
+    cost = N * K * D * D
+    pick = sorted({int(np.argmax(cost)), int(np.argmin(cost)), 0, B // 2})
+    offs = {name: np.concatenate([[0], np.cumsum(v)]) for name, v in
+            (("N", N), ("K", K), ("KD", K * D), ("KL", K * D * (D - 1) // 2))}
+    errs, t_cpu = [], 0.0
+    for b in pick:
+        gi = workloads.gmm_inputs(int(N[b]), int(D[b]), int(K[b]), workloads.BATCHED["seed"] + 1 + b,
+                                  np.float32)
+        (Fo, fo), t1 = cpu_timed(lambda: ogmm.objective(*gi.params(), gi.x))
+        go, t2 = cpu_timed(lambda: ogmm.vjp(*gi.params(), gi.x, fo))
+        t_cpu += t1 + t2
+        sl = lambda key, i: slice(offs[key][i], offs[key][i + 1])
+        blk = [gg[0][sl("K", b)], gg[1][sl("KD", b)], gg[2][sl("KD", b)], gg[3][sl("KL", b)]]
+        errs.append(max([abs(Fg[b] - Fo) / abs(Fo), rel_l2(fg[sl("N", b)], fo)] +
+                        [rel_l2(a, o) for a, o in zip(blk, go) if o.size]))
+    scale = float(cost.sum() / cost[pick].sum())
+    res["rel_l2_vs_fp64_oracle"] = {"max_over_sampled_instances": float(f"{max(errs):.3e}"),
+                                    "instances": pick}
+    res["cpu_oracle"] = {"ms_per_grad_eval": round(t_cpu * scale * 1e3, 1), "cores": blas_threads(),
+                         "sample": f"FP64 oracle on instances {pick} ({t_cpu:.2f} s), scaled by "
+                                   f"the batch's N K D^2 over theirs ({scale:.1f}x)"}
     return res
 
 
@@ -394,6 +499,30 @@ def row_stencil(torch, dex, workloads, dev, steps):
     out["forward_mode"] = {"jvp_ms": round(j_ms, 3), "avg_ms_per_step": round(per, 5),
                            "GBps": round(a, 1), "frac_hbm": round(a / PEAK["hbm"], 4)}
     del wsj
+    if not CHECK["on"]:
+        return out
+    # the same grid and kernels for 8 steps (checkpoint every 4, so the reverse
+    # pass recomputes) against the FP64 oracle loop; its time scaled to 1000 steps
+    from oracle import stencil as ost
+    Ts, es = 8, 4
+    d = dex.stencil_desc(H, W, Ts, es, 0.2, 0.0, dex.DEX_STENCIL_RECOMPUTE)
+    L = torch.empty(1, device=dev)
+    uT = torch.empty_like(u0)
+    ck = torch.empty((Ts // es) * H * W, device=dev)
+    du = torch.empty_like(u0)
+    dex.dex_fwd(d, [u0, tg], [L, uT], [ck, uT], dex.workspace(dex.dex_workspace_bytes(d, 0), dev))
+    dex.dex_vjp(d, [u0, tg], [ck, uT], [torch.ones(1, device=dev)], [du], 0,
+                dex.workspace(dex.dex_workspace_bytes(d, 1), dev))
+    torch.cuda.synchronize()
+    (Lo, uTo, duo), t = cpu_timed(lambda: ost.loss_and_grad(u0.cpu().numpy(), tg.cpu().numpy(), Ts))
+    out["rel_l2_vs_fp64_oracle"] = {"L": float(f"{abs(L.item() - Lo) / abs(Lo):.3e}"),
+                                    "uT": float(f"{rel_l2(uT.cpu().numpy(), uTo):.3e}"),
+                                    "du0": float(f"{rel_l2(du.cpu().numpy(), duo):.3e}"),
+                                    "at": f"{H}x{W}, {Ts} steps, checkpoint every {es}"}
+    out["cpu_oracle"] = {"ms_per_1000_steps_fwd_and_vjp": round(t * 1000 / Ts * 1e3, 1),
+                         "cores": blas_threads(),
+                         "sample": f"FP64 oracle loop and its transpose, {Ts} steps on the {H}x{W} "
+                                   f"grid ({t:.2f} s), times {1000 // Ts}"}
     return out
 
 
@@ -420,7 +549,6 @@ def row_reduce(torch, dex, workloads, dev, steps):
         dex.dex_reduce_all(o1, w, ws)
     torch.cuda.synchronize()
     dex.dex_profile_enable(False)
-    del v, w
     res = {"workload": f"segmented {rows}x{cols} f32 -> {rows}; complete {n} f32 -> 1"}
     for k, key, b in (("segmented", "REDUCE_ROWS", 4 * rows * cols + 4 * rows),
                       ("complete", "REDUCE_ALL", 4 * n)):
@@ -429,6 +557,28 @@ def row_reduce(torch, dex, workloads, dev, steps):
         a = b / (per * 1e-3) / 1e9
         res[k] = {"avg_ms": round(per, 4), "GBps": round(a, 1), "frac_hbm": round(a / PEAK["hbm"], 4),
                   "bytes_per_launch": b}
+    if not CHECK["on"]:
+        del v, w
+        return res
+    # 4096 sampled rows and the complete sum of the first 2^24 values (a call of
+    # its own) against the FP64 oracle (math.fsum); the oracle's time scaled up
+    import numpy as np
+    from oracle import reduce as ored
+    rs = np.random.default_rng(1).integers(0, rows, 4096)
+    vs = v[torch.tensor(rs, device=dev)].cpu().numpy()
+    want_rows, t_rows = cpu_timed(lambda: ored.reduce_rows(vs))
+    m = 1 << 24
+    o2 = torch.empty(1, device=dev)
+    dex.dex_reduce_all(o2, w[:m].contiguous(), ws)
+    wm = w[:m].cpu().numpy()
+    want_all, t_all = cpu_timed(lambda: ored.reduce_all(wm))
+    res["rel_l2_vs_fp64_oracle"] = {"segmented_sampled_rows": float(f"{rel_l2(out[torch.tensor(rs, device=dev)].cpu().numpy(), want_rows):.3e}"),
+                                    "complete_first_2^24": float(f"{abs(o2.item() - want_all) / max(abs(want_all), 1e-300):.3e}")}
+    res["cpu_oracle"] = {"segmented_ms": round(t_rows * rows / 4096 * 1e3, 1),
+                         "complete_ms": round(t_all * n / m * 1e3, 1), "cores": 1,
+                         "sample": f"math.fsum over 4096 rows ({t_rows:.2f} s, times {rows // 4096}) "
+                                   f"and over 2^24 values ({t_all:.2f} s, times {n // m})"}
+    del v, w
     return res
 
 
@@ -487,8 +637,15 @@ def main(argv=None):
                     help="also run one 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--configs", default=None,
                     help="forward,reverse tile configuration (1-based); skips the autotuner")
-    ap.add_argument("--rows-only", default=None, help="comma list of rows to run (scatter,hist,batched,stencil)")
+    ap.add_argument("--rows-only", default=None,
+                    help="comma list of rows to run (scatter,scatter_atomic,hist,batched,stencil,reduce); "
+                         "with --skip-headline, only these run (for profiling a row's kernels)")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the rows' oracle checks and CPU timings (profiling runs)")
+    ap.add_argument("--skip-headline", action="store_true",
+                    help="profiling aid: run only the rows named by --rows-only and print them")
     args = ap.parse_args(argv)
+    CHECK["on"] = not args.no_check
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path has no "
               f"multi-GPU component in this build", file=sys.stderr)
@@ -499,6 +656,18 @@ def main(argv=None):
     from paper_2104_05372_amd import dex
     dev = torch.device("cuda:0")
     dex.dex_init()
+    if args.skip_headline:
+        fns = {"scatter": row_scatter, "hist": row_histogram, "batched": row_batched,
+               "stencil": row_stencil, "reduce": row_reduce,
+               "scatter_atomic": lambda *a: row_scatter(*a, scatter_config=2)}
+        rows = {}
+        for name in (args.rows_only or "").split(","):
+            if name:
+                log("row", name)
+                rows[name] = fns[name](torch, dex, workloads, dev, 5 if name != "stencil" else 2)
+                torch.cuda.empty_cache()
+        print(json.dumps({"rows": rows}), flush=True)
+        return 0
     log("headline: GMM gradient N=100000 D=64 K=200", args.variant)
     H = run_headline(torch, dex, workloads, args, dev)
     if args.calibration_copy:
@@ -589,11 +758,11 @@ def main(argv=None):
             line["fp32_form"] = {"error": repr(e)}
     if not args.no_rows:
         rows = {}
-        sel = args.rows_only.split(",") if args.rows_only else ["scatter", "scatter_det", "hist", "batched",
-                                                                "stencil", "reduce"]
+        sel = args.rows_only.split(",") if args.rows_only else ["scatter", "scatter_atomic", "hist",
+                                                                "batched", "stencil", "reduce"]
         fns = {"scatter": row_scatter, "hist": row_histogram, "batched": row_batched, "stencil": row_stencil,
                "reduce": row_reduce,
-               "scatter_det": lambda *a: row_scatter(*a, scatter_config=2)}
+               "scatter_atomic": lambda *a: row_scatter(*a, scatter_config=2)}
         for name in sel:
             log("row", name)
             try:

@@ -160,8 +160,10 @@ typedef struct dex_buf {
  *   out    = out[n*R];  resid = none;  ct_out = g[n*R]
  *   ct_in  = dT[V*R], dw[n] (dw may be numel 0 with DEX_NO_DW)
  *   dT is the transposed gather: dT!(idx.j) += w.j * g.j (Sec. 5.3.3).
- *   config 1 (default): block-local sort + run sums + atomics; config 2: the
- *   DEX_DETERMINISTIC sorted form (needs DEX_WS_VJP workspace).
+ *   config 1 (default): the (row, position) pairs are radix sorted and every
+ *   row's sum is formed by one owner in index order and written once -- no
+ *   atomics, bit-reproducible (needs DEX_WS_VJP workspace); config 2: block-local
+ *   sort + run sums + float atomics (rounding order unspecified).
  *
  * DEX_STENCIL5 (dims {H, W, steps, every}; FP32): the State loop
  *     for t in 0..steps-1:  u := u + c (u[y+1,x]+u[y-1,x]+u[y,x+1]+u[y,x-1]-4u) + rho sin(u)

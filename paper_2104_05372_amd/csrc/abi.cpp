@@ -592,9 +592,13 @@ dex_status dex_vjp(const dex_desc* d, const dex_buf* in, int32_t n_in, const dex
       const bool with_dw = !(flags & DEX_NO_DW);
       DEX_TRY(want(ct_in, 1, "ct_in", DEX_F32, with_dw ? n : 0));
       DEX_TRY(ensure_device());
+      // config 1 (default): radix sort + one owner per row; config 2: block sort +
+      // run sums + atomics
+      const int path = cfg == 0 ? kScatterSorted : kScatterAtomic;
       if (!acc) DEX_TRY(fill_zero(ct_in[0].ptr, (size_t)(V * R) * 4, s));
       DEX_TRY(accum_scatter(ct_in[0].ptr, DEX_F32, V, R, in[1].ptr, DEX_I32, ct_out[0].ptr,
-                            (const float*)in[2].ptr, n, false, nullptr, workspace, ws_bytes_, cfg, s));
+                            (const float*)in[2].ptr, n, false, nullptr, workspace, ws_bytes_, path,
+                            s, !acc));
       if (with_dw)
         DEX_TRY(gather_dw((const float*)in[0].ptr, (const int32_t*)in[1].ptr,
                           (const float*)ct_out[0].ptr, V, R, n, (float*)ct_in[1].ptr, acc, s));
@@ -664,7 +668,7 @@ dex_status dex_accum_scatter(void* acc, int32_t acc_dtype, int64_t n_rows, int64
     DEX_TRY(check_hip(hipMemcpyAsync(&before, oob_count_dev, 8, hipMemcpyDeviceToHost, s), "oob read"));
     DEX_TRY(check_hip(hipStreamSynchronize(s), "sync"));
   }
-  const int path = (flags & DEX_DETERMINISTIC) ? 1 : 0;
+  const int path = (flags & DEX_DETERMINISTIC) ? kScatterSorted : kScatterAtomic;
   if (path == 1 && acc_dtype != DEX_F32)
     return fail(DEX_ERR_INVALID_ARG, "DEX_DETERMINISTIC applies to float accumulation");
   DEX_TRY(accum_scatter(acc, acc_dtype, n_rows, row_len, idx, idx_dtype, vals, scale, n, check,

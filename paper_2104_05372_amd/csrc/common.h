@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+#include <utility>
+
 #define DEX_DEV __device__ __forceinline__
 
 namespace dexk {
@@ -14,6 +17,17 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 typedef __attribute__((__vector_size__(8 * sizeof(float)))) float f32x8;
 
 constexpr int kWave = 64;
+
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>), in order:
+// a loop whose index is a compile-time constant in the body.
+template <typename F, int... I>
+DEX_DEV void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+DEX_DEV void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 // ---- wave-level exchange -------------------------------------------------
 // gfx950 lane swaps (VALU, no LDS traffic, no lgkm wait). As measured on the

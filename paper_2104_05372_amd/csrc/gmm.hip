@@ -412,33 +412,6 @@ __global__ void __launch_bounds__(256) k_bwd_finalize_mom(
                    ct[0], d_alphas, d_means, d_qd, d_l, accumulate, shift);
 }
 
-// The origin about which the matrix-core forms take their operands: the mean
-// of the component means, c[d] = (1/K) sum_k means[k][d] (FP64, fixed order),
-// zero for d >= D. Every term of the objective and of its gradient depends on
-// x_i and mu_k only through x_i - mu_k = (x_i - c) - (mu_k - c), so moving the
-// origin changes no result; it keeps the 16-bit operands, and the expansion
-// ||Q(x - mu)||^2 = x^T P x - 2 (P mu)^T x + mu^T P mu of the feature-product
-// form, free of the cancellation that data far from the origin would cause.
-// One block of 1024 threads: 16 slices of the components per coordinate.
-__global__ void __launch_bounds__(1024) k_shift(const float* __restrict__ means, int K, int D,
-                                                float* __restrict__ shift) {
-  __shared__ double part[16][64];
-  const int d = threadIdx.x & 63, q = threadIdx.x >> 6;
-  double s = 0.0;
-  if (d < D) {
-#pragma unroll 8
-    for (int k = q; k < K; k += 16) s += (double)means[(size_t)k * D + d];
-  }
-  part[q][d] = s;
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    double t = 0.0;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) t += part[j][d];
-    shift[d] = d < D ? (float)(t / K) : 0.f;
-  }
-}
-
 }  // namespace dexk
 
 // ===========================================================================
@@ -683,8 +656,7 @@ dex_status gmm_fwd(const dex_desc& d, int cfg, const GmmPtrs& in, void* F, void*
   void *xh = cc + cl.xh, *xl = cc + cl.xl, *xhT = cc + cl.xhT, *xlT = cc + cl.xlT, *Qh = cc + cl.Qh,
        *Ql = cc + cl.Ql;
   float *negc = (float*)(cc + cl.negc), *kappa = (float*)(cc + cl.kappa);
-  float* shift = (float*)(cc + cl.shift);
-  hipLaunchKernelGGL(k_shift, dim3(1), dim3(1024), 0, st, mu, (int)s.g.K, (int)s.g.D, shift);
+  float* shift = (float*)(cc + cl.shift);  // written by the preparation launch
   FlatSplit sp{};
   switch (s.prec) {
     case PREC_BF16:

@@ -375,6 +375,31 @@ struct MfmaOps {
 };
 
 // ---------------------------------------------------------------------------
+// The origin about which the matrix-core forms take their operands: the mean
+// of the component means, c[d] = (1/K) sum_k means[k][d] (FP64 sums in a fixed
+// order, the same in every block), zero for d >= D, into csh[64] (LDS). Every
+// term of the objective and of its gradient depends on x_i and mu_k only
+// through x_i - mu_k = (x_i - c) - (mu_k - c), so moving the origin changes no
+// result; it keeps the 16-bit operands, and the expansion
+// ||Q(x - mu)||^2 = x^T P x - 2 (P mu)^T x + mu^T P mu of the feature-product
+// form, free of the cancellation that data far from the origin would cause.
+// For 256-thread blocks; every thread must call it.
+DEX_DEV void block_shift(const float* __restrict__ means, int K, int D, float* csh) {
+  __shared__ double part[4][64];
+  const int t = threadIdx.x, d = t & 63, q = t >> 6;
+  double s = 0.0;
+  if (d < D) {
+#pragma unroll 8
+    for (int k = q; k < K; k += 4) s += (double)means[(size_t)k * D + d];
+  }
+  part[q][d] = s;
+  __syncthreads();
+  if (t < 64)
+    csh[t] = t < D ? (float)((((part[0][t] + part[1][t]) + part[2][t]) + part[3][t]) / K) : 0.f;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // Operand preparation for 64 points starting at p0: x~ (row-major) and x~^T,
 // zero padded to DP features and Npad points.
 // Optional outputs: xh == nullptr skips x~; tmax != nullptr receives the

@@ -60,7 +60,7 @@ inline int64_t bwd_max_slots(int64_t Npad, int64_t K) {
 template <int PREC>
 void mfma_prep(const GmmGeom& g, const float* x, const float* alphas, const float* means,
                const float* qd, const float* l, void* xh, void* xl, void* xhT, void* xlT, void* Qh,
-               void* Ql, float* negc, float* kappa, const float* shift, hipStream_t st);
+               void* Ql, float* negc, float* kappa, float* shift, hipStream_t st);
 template <int PREC>
 FlatSplit mfma_fwd(const GmmGeom& g, const FwdCfg& c, const dexk::MfmaOps& o, float* beta,
                    float2* ml, hipStream_t st);
@@ -69,12 +69,12 @@ FlatSplit mfma_bwd(const GmmGeom& g, const BwdCfg& c, const dexk::MfmaOps& o, co
                    const float* f, const float* ct, float* part, hipStream_t st);
 
 // Feature-product forward (BF16 variant, D = 64; defined with the BF16 kernels).
-// qf_prep: x~^T, the per-tile scaled FP16 copy of x and its exponents, the
-// coefficient operand, kappa' and rescale factors. qf_fwd: beta and the per-pass
+// qf_prep: the origin (shift), x~^T, the per-tile scaled FP16 copy of x and
+// its exponents, the coefficient operand, kappa' and rescale factors. qf_fwd: beta and the per-pass
 // log-sum-exp partials (FlatSplit::sk passes; W holds the block count).
 void qf_prep(const GmmGeom& g, const float* x, const float* alphas, const float* means,
              const float* qd, const float* l, void* xhT, void* x16, int* tile_exp, void* W16,
-             float* kq, float* isc, const float* shift, hipStream_t st);
+             float* kq, float* isc, float* shift, hipStream_t st);
 FlatSplit qf_fwd(const GmmGeom& g, const FwdCfg& c, const void* x16, const void* W16,
                  const float* kq, const float* isc, const int* tile_exp, float* beta, float2* ml,
                  hipStream_t st);
@@ -96,15 +96,15 @@ void qf_jvp(const GmmGeom& g, const void* x16, const void* dW16, const float* dk
 template <>
 void mfma_prep<dexk::PREC_F32>(const GmmGeom&, const float*, const float*, const float*,
                                const float*, const float*, void*, void*, void*, void*, void*,
-                               void*, float*, float*, const float*, hipStream_t);
+                               void*, float*, float*, float*, hipStream_t);
 template <>
 void mfma_prep<dexk::PREC_BF16>(const GmmGeom&, const float*, const float*, const float*,
                                 const float*, const float*, void*, void*, void*, void*, void*,
-                                void*, float*, float*, const float*, hipStream_t);
+                                void*, float*, float*, float*, hipStream_t);
 template <>
 void mfma_prep<dexk::PREC_BF16X3>(const GmmGeom&, const float*, const float*, const float*,
                                   const float*, const float*, void*, void*, void*, void*, void*,
-                                  void*, float*, float*, const float*, hipStream_t);
+                                  void*, float*, float*, float*, hipStream_t);
 template <>
 FlatSplit mfma_fwd<dexk::PREC_F32>(const GmmGeom&, const FwdCfg&, const dexk::MfmaOps&, float*,
                               float2*, hipStream_t);

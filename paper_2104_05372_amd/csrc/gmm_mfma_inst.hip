@@ -28,12 +28,16 @@ __global__ void __launch_bounds__(256) k_prep(const float* __restrict__ x, int N
                                               typename MomT<MomOf<PREC>::MP>::S* xlT,
                                               typename Store<PREC>::S* Qh,
                                               typename Store<PREC>::S* Ql, float* negc,
-                                              float* kappa, const float* __restrict__ shift) {
+                                              float* kappa, float* __restrict__ shift) {
+  // every block computes the origin itself (one launch less); block 0 keeps it
+  // for the reverse pass
+  __shared__ float csh[64];
+  block_shift(means, K, D, csh);
+  if (blockIdx.x == 0 && threadIdx.x < 64) shift[threadIdx.x] = csh[threadIdx.x];
   if ((int)blockIdx.x < K)
-    prep_q_comp<PREC, DP>(alphas, means, qd, l, D, blockIdx.x, Qh, Ql, negc, kappa, shift);
+    prep_q_comp<PREC, DP>(alphas, means, qd, l, D, blockIdx.x, Qh, Ql, negc, kappa, csh);
   else
-    prep_x_tile<PREC, DP>(x, N, D, Npad, (blockIdx.x - K) * 64, xh, xl, xhT, xlT, nullptr,
-                          shift);
+    prep_x_tile<PREC, DP>(x, N, D, Npad, (blockIdx.x - K) * 64, xh, xl, xhT, xlT, nullptr, csh);
 }
 
 // The grid kernels split their work evenly over the waves (split_lo), so every
@@ -518,12 +522,17 @@ __global__ void __launch_bounds__(256) k_qf_prep(const float* __restrict__ x, in
                                                  const float* __restrict__ l, int K, int Kp,
                                                  _Float16* __restrict__ W16,
                                                  float* __restrict__ kq, float* __restrict__ isc,
-                                                 const float* __restrict__ shift) {
+                                                 float* __restrict__ shift) {
   __shared__ __attribute__((aligned(16))) char smem[kQfWLds > 2 * kQfXLds ? kQfWLds : 2 * kQfXLds];
+  // every block computes the origin itself (one launch less); block 0 keeps it
+  // for the reverse pass and forward mode
+  __shared__ float csh[64];
+  block_shift(means, K, 64, csh);
+  if (blockIdx.x == 0 && threadIdx.x < 64) shift[threadIdx.x] = csh[threadIdx.x];
   if ((int)blockIdx.x < Kp)
-    qf_w_comp(blockIdx.x, smem, alphas, means, qd, l, K, W16, kq, isc, shift);
+    qf_w_comp(blockIdx.x, smem, alphas, means, qd, l, K, W16, kq, isc, csh);
   else
-    qf_x_tile(2 * (blockIdx.x - Kp), Npad / 64, smem, x, N, Npad, xhT, x16, tile_exp, shift);
+    qf_x_tile(2 * (blockIdx.x - Kp), Npad / 64, smem, x, N, Npad, xhT, x16, tile_exp, csh);
 }
 
 // Sum / max over the 16 lanes of a row (DPP: quad swaps, half-row and row
@@ -777,7 +786,7 @@ using SM = typename MomT<MomOf<P>::MP>::S;
 template <int DP>
 static void prep_dp(const GmmGeom& g, const float* x, const float* alphas, const float* means,
                     const float* qd, const float* l, void* xh, void* xl, void* xhT, void* xlT,
-                    void* Qh, void* Ql, float* negc, float* kappa, const float* shift,
+                    void* Qh, void* Ql, float* negc, float* kappa, float* shift,
                     hipStream_t st) {
   hipLaunchKernelGGL((k_prep<P, DP>), dim3((unsigned)(g.K + g.Npad / 64)), dim3(256), 0, st, x,
                      (int)g.N, (int)g.D, (int)g.Npad, (int)g.K, alphas, means, qd, l, (S*)xh,
@@ -787,7 +796,7 @@ static void prep_dp(const GmmGeom& g, const float* x, const float* alphas, const
 template <>
 void mfma_prep<P>(const GmmGeom& g, const float* x, const float* alphas, const float* means,
                   const float* qd, const float* l, void* xh, void* xl, void* xhT, void* xlT,
-                  void* Qh, void* Ql, float* negc, float* kappa, const float* shift,
+                  void* Qh, void* Ql, float* negc, float* kappa, float* shift,
                   hipStream_t st) {
   if (g.DP == 16)
     prep_dp<16>(g, x, alphas, means, qd, l, xh, xl, xhT, xlT, Qh, Ql, negc, kappa, shift, st);
@@ -898,7 +907,7 @@ FlatSplit mfma_bwd<P>(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const
 #if DEX_PREC == 1
 void qf_prep(const GmmGeom& g, const float* x, const float* alphas, const float* means,
              const float* qd, const float* l, void* xhT, void* x16, int* tile_exp, void* W16,
-             float* kq, float* isc, const float* shift, hipStream_t st) {
+             float* kq, float* isc, float* shift, hipStream_t st) {
   const int ntiles = (int)(g.Npad / 64);
   const int Kp = (int)((g.K + qf::kPass - 1) / qf::kPass * qf::kPass);
   hipLaunchKernelGGL(k_qf_prep, dim3((unsigned)(Kp + (ntiles + 1) / 2)), dim3(256), 0, st, x,

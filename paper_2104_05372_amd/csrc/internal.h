@@ -67,10 +67,16 @@ dex_status gmm_batched_vjp(const dex_desc& d, int cfg, const void* plan, const G
 // ------------------------------------------------ scatter / gather -----
 size_t scatter_ws_bytes(int32_t acc_dtype, int64_t n_rows, int64_t row_len, int64_t n,
                         bool has_vals, bool deterministic);
+// path: kScatterAtomic (block sort + run sums + atomics, no workspace) or
+// kScatterSorted (radix sort + one owner per row, deterministic, workspace).
+// overwrite (sorted path): acc was cleared by the caller and untouched rows stay
+// zero, so a row's owner stores its sum without reading the row.
+constexpr int kScatterAtomic = 0, kScatterSorted = 1;
 dex_status accum_scatter(void* acc, int32_t acc_dtype, int64_t n_rows, int64_t row_len,
                          const void* idx, int32_t idx_dtype, const void* vals,
                          const float* scale, int64_t n, bool count_oob, int64_t* oob,
-                         void* ws, size_t ws_bytes, int cfg, hipStream_t s);
+                         void* ws, size_t ws_bytes, int path, hipStream_t s,
+                         bool overwrite = false);
 dex_status gather_fwd(const float* T, const int32_t* idx, const float* w, int64_t V, int64_t R,
                       int64_t n, float* out, bool count_oob, int64_t* oob, hipStream_t s);
 dex_status gather_jvp(const float* T, const float* tT, const int32_t* idx, const float* w,

@@ -19,6 +19,7 @@
 // under any schedule.
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 
 #include "common.h"
 #include "internal.h"
@@ -231,21 +232,30 @@ __global__ void __launch_bounds__(1024) hist_private_kernel(int32_t* __restrict_
   for (int i = threadIdx.x; i < nwords; i += blockDim.x) mine[i] = cnt[i];
 }
 
-// acc[b] += sum over blocks of the packed partial counters (fixed order).
+// acc[b] += sum over blocks of the packed partial counters. Thread (w, y) adds
+// the counters of word w over blocks y * kHistGroup .. + kHistGroup - 1 (their
+// loads issued together) and adds the two bins' totals with integer atomics:
+// integer addition is exact, so the result does not depend on their order.
+constexpr int kHistGroup = 16;
 __global__ void __launch_bounds__(256) hist_reduce_kernel(int32_t* __restrict__ acc, int n_bins,
                                                           const uint32_t* __restrict__ partial,
                                                           int nblocks) {
   const int w = blockIdx.x * 256 + threadIdx.x;
   const int nwords = (n_bins + 1) >> 1;
   if (w >= nwords) return;
+  const int b0 = blockIdx.y * kHistGroup;
+  uint32_t v[kHistGroup];
+#pragma unroll
+  for (int i = 0; i < kHistGroup; ++i)
+    v[i] = b0 + i < nblocks ? partial[(size_t)(b0 + i) * nwords + w] : 0u;
   uint32_t lo = 0, hi = 0;
-  for (int b = 0; b < nblocks; ++b) {
-    const uint32_t v = partial[(size_t)b * nwords + w];
-    lo += v & 0xFFFFu;
-    hi += v >> 16;
+#pragma unroll
+  for (int i = 0; i < kHistGroup; ++i) {
+    lo += v[i] & 0xFFFFu;
+    hi += v[i] >> 16;
   }
-  acc[2 * w] += (int32_t)lo;
-  if (2 * w + 1 < n_bins) acc[2 * w + 1] += (int32_t)hi;
+  if (lo) atomicAdd(&acc[2 * w], (int32_t)lo);
+  if (hi && 2 * w + 1 < n_bins) atomicAdd(&acc[2 * w + 1], (int32_t)hi);
 }
 
 // Generic integer accumulation (exact): one thread per (index, column).
@@ -395,210 +405,318 @@ __global__ void __launch_bounds__(256) gather_dw_kernel(const float* __restrict_
 // followed by run sums with a fixed owner per run, so the rounding order of
 // every row's sum is fixed (bit-reproducible), and no atomics are used.
 constexpr int kRsTile = 8192;   // keys per sort block (1024 threads x 8 rounds)
-constexpr int kSeg = 256;       // sorted entries per wave in the run-sum pass
 
 // keys[j] = idx[j] if it is inside [0, n_rows), else n_rows (sorts last and is
 // skipped); vals[j] = j.
-template <typename IdxT>
-__global__ void __launch_bounds__(256) rs_init(const IdxT* __restrict__ idx, int64_t n,
-                                               int64_t n_rows, uint32_t* __restrict__ keys,
-                                               uint32_t* __restrict__ vals, int64_t* oob) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  int bad = 0;
-  if (j < n) {
-    const int64_t v = load_index(idx, j);
-    const bool ok = v >= 0 && v < n_rows;
-    bad = !ok;
-    keys[j] = ok ? (uint32_t)v : (uint32_t)n_rows;
-    vals[j] = (uint32_t)j;
-  }
-  if (oob) count_oob(bad, oob);
-}
+// Radix digits of kRsBits bits (a million rows: 20-bit keys, three passes). With
+// 8192-key tiles a digit gets about 32 keys per tile, so the scatter writes runs
+// of 128 bytes of keys (wider digits leave runs too short to write efficiently).
+constexpr int kRsBits = 8;
+constexpr int kRsDigits = 1 << kRsBits;
 
-// Digit counts of one tile: cnt[digit * ntiles + tile]. Exact, order-free.
-__global__ void __launch_bounds__(1024) rs_hist(const uint32_t* __restrict__ keys, int64_t n,
-                                                int shift, uint32_t* __restrict__ cnt, int ntiles) {
-  __shared__ uint32_t h[256];
-  if (threadIdx.x < 256) h[threadIdx.x] = 0u;
-  __syncthreads();
-  const int64_t t0 = (int64_t)blockIdx.x * kRsTile;
-#pragma unroll
-  for (int r = 0; r < kRsTile / 1024; ++r) {
-    const int64_t j = t0 + r * 1024 + threadIdx.x;
-    if (j < n) atomicAdd(&h[(keys[j] >> shift) & 255u], 1u);
-  }
-  __syncthreads();
-  if (threadIdx.x < 256) cnt[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
-}
-
-// Per digit (one block each): exclusive prefix of the tile counts, and the total.
-__global__ void __launch_bounds__(256) rs_digit_scan(uint32_t* __restrict__ cnt, int ntiles,
-                                                     uint32_t* __restrict__ tot) {
-  __shared__ uint32_t sh[256];
-  uint32_t carry = 0;
-  uint32_t* row = cnt + (size_t)blockIdx.x * ntiles;
-  for (int b = 0; b < ntiles; b += 256) {
-    const int i = b + threadIdx.x;
-    const uint32_t v = i < ntiles ? row[i] : 0u;
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {  // inclusive Hillis-Steele scan
-      const uint32_t t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0u;
-      __syncthreads();
-      sh[threadIdx.x] += t;
-      __syncthreads();
-    }
-    if (i < ntiles) row[i] = carry + sh[threadIdx.x] - v;
-    carry += sh[255];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
-}
-
-// Lanes of this wave holding the same 8-bit digit as this lane (among `live`).
+// Lanes of this wave holding the same kRsBits-bit digit as this lane (among `live`).
 DEX_DEV uint64_t digit_peers(uint32_t d, uint64_t live) {
   uint64_t m = live;
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
+  for (int b = 0; b < kRsBits; ++b) {
     const uint64_t bal = __ballot((d >> b) & 1u);
     m &= ((d >> b) & 1u) ? bal : ~bal;
   }
   return m;
 }
 
-// Stable scatter of one tile by digit: keys are taken in index order (round r,
-// then thread), ranked within the wave by ballots and across waves by
-// per-wave digit counts in LDS; no atomics, so the output order is fixed.
-__global__ void __launch_bounds__(1024) rs_scatter(const uint32_t* __restrict__ kin,
-                                                   const uint32_t* __restrict__ vin,
-                                                   uint32_t* __restrict__ kout,
-                                                   uint32_t* __restrict__ vout, int64_t n,
-                                                   int shift, const uint32_t* __restrict__ cnt,
-                                                   const uint32_t* __restrict__ tot, int ntiles) {
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t whist[16][256];
-  __shared__ uint32_t wsum[4];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  // exclusive scan of the digit totals by the first 4 waves (whole waves)
-  uint32_t v = 0, x = 0;
-  if (tid < 256) {
-    v = tot[tid];
-    x = v;
+// The sort key of entry j: its row, or n_rows (sorts last, skipped) when the
+// index is outside [0, n_rows).
+template <typename IdxT>
+DEX_DEV uint32_t row_key(const IdxT* __restrict__ idx, int64_t j, int64_t n_rows, int& bad) {
+  const int64_t v = load_index(idx, j);
+  const bool ok = v >= 0 && v < n_rows;
+  bad += !ok;
+  return ok ? (uint32_t)v : (uint32_t)n_rows;
+}
+
+// Digit counts of one tile: cnt[digit * ntiles + tile]. Exact, order-free. The
+// lanes of a wave that share a digit add their count with one LDS atomic (skewed
+// keys would otherwise queue on one counter). The first pass reads the indices
+// themselves (and counts those outside the table, and clears the combine
+// lists' counters); later passes read the keys the previous pass wrote.
+template <bool FIRST, typename IdxT>
+__global__ void __launch_bounds__(1024) rs_hist(const IdxT* __restrict__ idx,
+                                                const uint32_t* __restrict__ keys, int64_t n,
+                                                int64_t n_rows, int shift,
+                                                uint32_t* __restrict__ cnt, int ntiles,
+                                                uint32_t* __restrict__ nlist, int64_t* oob) {
+  __shared__ uint32_t h[kRsDigits];
+  for (int i = threadIdx.x; i < kRsDigits; i += 1024) h[i] = 0u;
+  if (FIRST && blockIdx.x == 0 && threadIdx.x < 2) nlist[threadIdx.x] = 0u;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t t0 = (int64_t)blockIdx.x * kRsTile;
+  uint32_t kv[kRsTile / 1024];
+  int bad = 0;
+#pragma unroll
+  for (int r = 0; r < kRsTile / 1024; ++r) {  // all of a thread's loads in flight together
+    const int64_t j = t0 + r * 1024 + threadIdx.x;
+    if constexpr (FIRST)
+      kv[r] = j < n ? row_key(idx, j, n_rows, bad) : 0u;
+    else
+      kv[r] = j < n ? keys[j] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < kRsTile / 1024; ++r) {
+    const bool valid = t0 + r * 1024 + threadIdx.x < n;
+    const uint32_t d = (kv[r] >> shift) & (kRsDigits - 1);
+    const uint64_t peers = digit_peers(d, __ballot(valid));
+    if (valid && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+  }
+  if (FIRST && oob) count_oob(bad, oob);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kRsDigits; i += 1024) cnt[(size_t)i * ntiles + blockIdx.x] = h[i];
+}
+
+// Per digit (one block each): exclusive prefix of the tile counts, and the total.
+__global__ void __launch_bounds__(256) rs_digit_scan(uint32_t* __restrict__ cnt, int ntiles,
+                                                     uint32_t* __restrict__ tot) {
+  __shared__ uint32_t wsh[4];
+  uint32_t carry = 0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t* row = cnt + (size_t)blockIdx.x * ntiles;
+  for (int b = 0; b < ntiles; b += 256) {
+    const int i = b + threadIdx.x;
+    const uint32_t v = i < ntiles ? row[i] : 0u;
+    uint32_t x = v;  // inclusive scan: within the wave by shuffles, across waves by LDS
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const uint32_t y = __shfl_up(x, o, 64);
       if (lane >= o) x += y;
     }
-    if (lane == 63) wsum[wv] = x;
+    if (lane == 63) wsh[wv] = x;
+    __syncthreads();
+    uint32_t pre = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      pre += w < wv ? wsh[w] : 0u;
+      all += wsh[w];
+    }
+    if (i < ntiles) row[i] = carry + pre + x - v;
+    carry += all;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
+// Stable scatter of one tile by digit. Wave w ranks the tile's keys
+// [512 w, 512 w + 512) in index order, 64 at a time: ballots rank a key among
+// the equal digits of its 64, and a per-wave running count per digit in LDS
+// (read, then bumped by the first of the peers) ranks it among the wave's
+// earlier keys; no barrier is needed until the wave is done. The per-digit
+// counts of the 16 waves then give every key its place in the tile ordered by
+// digit (wave order within a digit, so index order is kept); the tile is
+// reordered in LDS and written out by consecutive threads, so each digit's keys
+// leave as one contiguous run. No atomics: the output order is fixed.
+// The first pass reads the indices and scales themselves: an entry's value is
+// its position j with its scale's bits above (the run sums then read the scales
+// in sorted order, not scattered).
+template <bool FIRST, typename IdxT>
+__global__ void __launch_bounds__(1024) rs_scatter(const IdxT* __restrict__ idx,
+                                                   const float* __restrict__ scale,
+                                                   int64_t n_rows,
+                                                   const uint32_t* __restrict__ kin,
+                                                   const uint64_t* __restrict__ vin,
+                                                   uint32_t* __restrict__ kout,
+                                                   uint64_t* __restrict__ vout, int64_t n,
+                                                   int shift, const uint32_t* __restrict__ cnt,
+                                                   const uint32_t* __restrict__ tot, int ntiles) {
+  static_assert(kRsDigits <= 256 && kRsTile == 16 * 512, "digits in the first four waves");
+  __shared__ uint32_t gbase[kRsDigits];   // where digit d of this tile starts in the output
+  __shared__ uint32_t lbase[kRsDigits];   // where digit d starts inside the reordered tile
+  __shared__ uint32_t hw[16][kRsDigits];  // per-wave digit counts, then per-wave offsets
+  __shared__ uint32_t wsum[2][4];
+  __shared__ uint32_t sk[kRsTile];
+  __shared__ uint64_t sv[kRsTile];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
+  const int64_t t0 = tile0 + (int64_t)wv * 512;
+  const int tlen = (int)min<int64_t>(kRsTile, n - tile0);
+  constexpr int R = 512 / 64;
+  uint32_t kk[R], rk[R];
+  uint64_t vv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {  // the wave's loads issued together
+    const int64_t j = t0 + r * 64 + lane;
+    if constexpr (FIRST) {
+      int bad = 0;
+      kk[r] = j < n ? row_key(idx, j, n_rows, bad) : 0u;
+      const float w = (j < n && scale) ? scale[j] : 1.f;
+      vv[r] = ((uint64_t)__float_as_uint(w) << 32) | (uint64_t)(uint32_t)j;
+    } else {
+      kk[r] = j < n ? kin[j] : 0u;
+      vv[r] = j < n ? vin[j] : 0ull;
+    }
+  }
+  const bool dig = tid < kRsDigits;  // thread tid owns digit tid in the prefix steps
+  if (dig) {
+#pragma unroll
+    for (int w = 0; w < 16; ++w) hw[w][tid] = 0u;
   }
   __syncthreads();
-  if (tid < 256) {
-    uint32_t pre = 0;
-    for (int w = 0; w < wv; ++w) pre += wsum[w];
-    base[tid] = pre + x - v + cnt[(size_t)tid * ntiles + blockIdx.x];
-  }
-  const int64_t t0 = (int64_t)blockIdx.x * kRsTile;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int r = 0; r < kRsTile / 1024; ++r) {
-    for (int e = tid; e < 16 * 256; e += 1024) (&whist[0][0])[e] = 0u;
-    const int64_t j = t0 + r * 1024 + tid;
-    const bool valid = j < n;
-    const uint32_t key = valid ? kin[j] : 0u;
-    const uint32_t val = valid ? vin[j] : 0u;
-    const uint32_t d = (key >> shift) & 255u;
-    const uint64_t live = __ballot(valid);
-    const uint64_t peers = digit_peers(d, live);
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    __syncthreads();
-    if (valid && rank == 0) whist[wv][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (tid < 256) {
-      uint32_t run = base[tid];
 #pragma unroll
-      for (int w = 0; w < 16; ++w) {
-        const uint32_t c = whist[w][tid];
-        whist[w][tid] = run;
-        run += c;
-      }
-      base[tid] = run;
+  for (int r = 0; r < R; ++r) {
+    const bool valid = t0 + r * 64 + lane < n;
+    const uint32_t d = (kk[r] >> shift) & (kRsDigits - 1);
+    const uint64_t peers = digit_peers(d, __ballot(valid));
+    const uint32_t before = (uint32_t)__popcll(peers & lt);
+    const uint32_t prev = hw[wv][d];
+    rk[r] = prev + before;
+    if (valid && before == 0) hw[wv][d] = prev + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // digit threads: this tile's count of digit d, its exclusive scans over the
+  // digits (inside the tile) and over the digit totals (the whole array)
+  uint32_t c = 0, g = 0;
+  if (dig) {
+#pragma unroll
+    for (int w = 0; w < 16; ++w) c += hw[w][tid];
+    g = tot[tid];
+  }
+  uint32_t xc = c, xg = g;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t yc = __shfl_up(xc, o, 64), yg = __shfl_up(xg, o, 64);
+    if (lane >= o) {
+      xc += yc;
+      xg += yg;
     }
-    __syncthreads();
-    if (valid) {
-      const uint32_t pos = whist[wv][d] + rank;
-      kout[pos] = key;
-      vout[pos] = val;
+  }
+  if (lane == 63 && wv < 4) {
+    wsum[0][wv] = xc;
+    wsum[1][wv] = xg;
+  }
+  __syncthreads();
+  if (dig) {
+    uint32_t pc = 0, pg = 0;
+    for (int w = 0; w < wv; ++w) {
+      pc += wsum[0][w];
+      pg += wsum[1][w];
     }
-    __syncthreads();
+    const uint32_t lb = pc + xc - c;
+    lbase[tid] = lb;
+    gbase[tid] = pg + xg - g + cnt[(size_t)tid * ntiles + blockIdx.x];
+    uint32_t run = lb;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      const uint32_t cw = hw[w][tid];
+      hw[w][tid] = run;
+      run += cw;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (t0 + r * 64 + lane < n) {
+      const uint32_t lp = hw[wv][(kk[r] >> shift) & (kRsDigits - 1)] + rk[r];
+      sk[lp] = kk[r];
+      sv[lp] = vv[r];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < tlen; i += 1024) {
+    const uint32_t key = sk[i];
+    const uint32_t d = (key >> shift) & (kRsDigits - 1);
+    const uint32_t pos = gbase[d] + (uint32_t)i - lbase[d];
+    kout[pos] = key;
+    vout[pos] = sv[i];
   }
 }
 
-// One wave per segment of kSeg sorted entries. Runs of equal rows are summed in
-// registers (row_len columns over the lanes); a run wholly inside the segment
-// is added to acc by this wave alone; a run that starts earlier leaves its
-// partial in part_first[seg], one that continues past the segment in
-// part_last[seg], for seg_fix. Every row thus receives exactly one addition
-// (here or in seg_fix), so a non-returning atomic add gives a fixed result and
-// never stalls the loop; the segment's keys and positions are staged in LDS
-// and the values of the next U entries are loaded before the current U are
-// summed (loads retire in issue order, so they never wait for the adds).
-template <int U, bool HV, bool HS>
-__global__ void __launch_bounds__(256) seg_sum(const uint32_t* __restrict__ skey,
-                                               const uint32_t* __restrict__ spos, int64_t n,
+// ---------------------------------------------------------------------------
+// Owner-per-run sum over the sorted (row, position, scale) entries, the default
+// form of the transposed gather. Each wave takes kOwnSeg consecutive sorted
+// entries; a lane holds VW consecutive columns of a row (a 128-column row is
+// one wave load of 512 bytes). A run of equal rows wholly inside the segment
+// has exactly one owner, this wave, which writes the row once: a plain store
+// (OVR: the table was cleared first) or a read-modify-write of the row (the
+// row's value is loaded with the run's first entry) -- no atomics, and the
+// rounding order of every row is fixed. The first run of a segment, when it
+// began in an earlier segment, leaves its partial in head[seg]; the last run,
+// when it began here and continues into the next segment, leaves its partial in
+// tail[seg], and the segment is put on the list for own_fix (the list's order
+// does not matter: each entry is combined on its own, in a fixed order). The
+// values of the next U entries are loaded before the current U are summed.
+constexpr int kOwnSeg = 512;
+
+template <int VW, int U, bool HV, bool OVR>
+__global__ void __launch_bounds__(256) own_sum(const uint32_t* __restrict__ skey,
+                                               const uint64_t* __restrict__ sval, int64_t n,
                                                uint32_t sentinel, const float* __restrict__ vals,
-                                               const float* __restrict__ scale, int R,
-                                               float* __restrict__ acc,
-                                               float* __restrict__ part_first,
-                                               float* __restrict__ part_last) {
-  __shared__ uint32_t sk[4][kSeg], sp[4][kSeg];
+                                               int R, float* __restrict__ acc,
+                                               float* __restrict__ head, float* __restrict__ tail,
+                                               uint32_t* __restrict__ list,
+                                               uint32_t* __restrict__ nlist) {
+  typedef float VT __attribute__((ext_vector_type(VW)));
+  constexpr int G = kOwnSeg / 64;  // groups of 64 entries
+  constexpr int NB = 64 / U;       // batches of U entries per group
+  static_assert(64 % U == 0 && NB % 2 == 0, "whole batch pairs per group");
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t seg = (int64_t)blockIdx.x * 4 + wv;
-  const int64_t e0 = seg * kSeg;
+  const int64_t e0 = seg * kOwnSeg;
   if (e0 >= n) return;
-  const int len = (int)min<int64_t>(kSeg, n - e0);
-#pragma unroll
-  for (int q = 0; q < kSeg / 64; ++q) {
-    const int e = q * 64 + lane;
-    sk[wv][e] = e < len ? skey[e0 + e] : sentinel;
-    sp[wv][e] = e < len ? spos[e0 + e] : 0u;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const uint32_t first = sk[wv][0];
+  const int len = (int)min<int64_t>(kOwnSeg, n - e0);
+  const uint32_t first = __builtin_amdgcn_readfirstlane(skey[e0]);
+  const uint32_t lastk = __builtin_amdgcn_readfirstlane(skey[e0 + len - 1]);
   if (first == sentinel) return;
   const bool cont_in = e0 > 0 && skey[e0 - 1] == first;
-  const uint32_t lastk = sk[wv][len - 1];
   const bool cont_out = e0 + len < n && skey[e0 + len] == lastk && lastk != sentinel;
-  for (int c0 = 0; c0 < R; c0 += 64) {
-    const int col = c0 + lane;
-    const bool cv = col < R;
-    const int colc = cv ? col : R - 1;
+  if (cont_out && !(cont_in && first == lastk) && lane == 0)
+    list[atomicAdd(nlist, 1u)] = (uint32_t)seg;  // a run starts here and spans segments
+  // lane t holds entry 64 g + t of the current group (key, position, scale);
+  // each entry is read back with readlane, so keys, positions and the run logic
+  // are wave-uniform (scalar) and a batch's row loads are issued back to back
+  struct Ent {
+    uint32_t k, j, s;
+  };
+  auto load_group = [&](int gq) {
+    const int e = gq * 64 + lane;
+    const bool in = gq < G && e < len;
+    const uint64_t pv = in ? sval[e0 + e] : 0ull;
+    return Ent{in ? skey[e0 + e] : sentinel, (uint32_t)pv, (uint32_t)(pv >> 32)};
+  };
+  for (int c0 = 0; c0 < R; c0 += 64 * VW) {
+    const int col = c0 + VW * lane;
+    const bool cv = col < R;  // R is a multiple of VW
+    const int colc = cv ? col : 0;
     uint32_t cur = first;
     bool started_before = cont_in;
-    float sum = 0.f;
+    VT sum = VT(0.f), base = VT(0.f);
     auto flush = [&](bool continues) {
       if (!cv || cur == sentinel) return;
       if (started_before)
-        part_first[seg * R + col] = sum;
+        *reinterpret_cast<VT*>(&head[seg * R + col]) = sum;
       else if (continues)
-        part_last[seg * R + col] = sum;
+        *reinterpret_cast<VT*>(&tail[seg * R + col]) = sum;
       else
-        atomicAdd(&acc[(int64_t)cur * R + col], sum);
+        *reinterpret_cast<VT*>(&acc[(int64_t)cur * R + col]) = OVR ? sum : base + sum;
     };
-    auto fetch = [&](int e, uint32_t(&kk)[U], float(&rv)[U]) {
+    auto fetch = [&](auto l0c, const Ent& g, uint32_t(&kk)[U], VT(&rv)[U], VT(&av)[U]) {
+      constexpr int l0 = decltype(l0c)::value;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int ec = min(e + u, kSeg - 1);
-        kk[u] = e + u < len ? sk[wv][ec] : sentinel;
+        kk[u] = __builtin_amdgcn_readlane(g.k, l0 + u);
+        const uint32_t j = __builtin_amdgcn_readlane(g.j, l0 + u);
+        const float sc = __uint_as_float(__builtin_amdgcn_readlane(g.s, l0 + u));
         const bool ok = kk[u] != sentinel;
-        const int64_t j = ok ? (int64_t)sp[wv][ec] : 0;
-        float v = 1.f;
-        if constexpr (HV) v = vals[j * R + colc];
-        if constexpr (HS) v *= scale[j];
-        rv[u] = ok ? v : 0.f;
+        VT v = VT(1.f);
+        if constexpr (HV) v = *reinterpret_cast<const VT*>(&vals[(int64_t)j * R + colc]);
+        rv[u] = ok ? v * sc : VT(0.f);
+        if constexpr (!OVR) {
+          const int64_t row = ok ? (int64_t)kk[u] : 0;
+          av[u] = *reinterpret_cast<const VT*>(&acc[row * R + colc]);
+        }
       }
     };
-    auto consume = [&](const uint32_t(&kk)[U], const float(&rv)[U]) {
+    auto consume = [&](const uint32_t(&kk)[U], const VT(&rv)[U], const VT(&av)[U]) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (kk[u] == sentinel) continue;
@@ -606,72 +724,162 @@ __global__ void __launch_bounds__(256) seg_sum(const uint32_t* __restrict__ skey
           flush(false);
           cur = kk[u];
           started_before = false;
-          sum = 0.f;
+          sum = VT(0.f);
+          base = av[u];
         }
         sum += rv[u];
       }
     };
     uint32_t ka[U], kb[U];
-    float ra[U], rb[U];
-    fetch(0, ka, ra);
-    for (int e = 0; e < len; e += 2 * U) {
-      fetch(e + U, kb, rb);
-      __builtin_amdgcn_sched_barrier(0);
-      consume(ka, ra);
-      __builtin_amdgcn_sched_barrier(0);
-      fetch(e + 2 * U, ka, ra);
-      __builtin_amdgcn_sched_barrier(0);
-      consume(kb, rb);
-      __builtin_amdgcn_sched_barrier(0);
+    VT ra[U], rb[U], aa[U], ab[U];
+    Ent gc = load_group(0);
+    fetch(std::integral_constant<int, 0>{}, gc, ka, ra, aa);
+    base = aa[0];  // the first run's row (unused when it began earlier)
+    // per group: batches 2p (set A) and 2p + 1 (set B); the next batch's loads
+    // (the next group's first batch after the last) are issued before the
+    // current batch is summed
+    for (int gq = 0; gq < G && gq * 64 < len; ++gq) {
+      const Ent gn = load_group(gq + 1);
+      static_for<NB / 2>([&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        fetch(std::integral_constant<int, (2 * P + 1) * U>{}, gc, kb, rb, ab);
+        __builtin_amdgcn_sched_barrier(0);
+        consume(ka, ra, aa);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (2 * P + 2 < NB)
+          fetch(std::integral_constant<int, (2 * P + 2) * U>{}, gc, ka, ra, aa);
+        else
+          fetch(std::integral_constant<int, 0>{}, gn, ka, ra, aa);
+        __builtin_amdgcn_sched_barrier(0);
+        consume(kb, rb, ab);
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      gc = gn;
     }
     flush(cont_out);
   }
 }
 
-// For each segment whose last run starts in it and continues into the next
-// segments: the run's end is found by binary search in the sorted keys; the
-// block then adds the segment's partial and the following segments' first-run
-// partials in a fixed order (wave w takes every fourth segment, the four wave
-// sums are combined in wave order) and adds the total to acc, the row's only
-// addition. One block per segment; most exit after two key reads.
-__global__ void __launch_bounds__(256) seg_fix(const uint32_t* __restrict__ skey, int64_t n,
-                                               uint32_t sentinel, int R, float* __restrict__ acc,
-                                               const float* __restrict__ part_first,
-                                               const float* __restrict__ part_last) {
-  __shared__ float wsum[4][64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t seg = blockIdx.x;
-  const int64_t e0 = seg * kSeg, e1 = min<int64_t>(n, e0 + kSeg);
-  if (e0 >= n) return;
-  const uint32_t row = skey[e1 - 1];
-  if (row == sentinel) return;
-  const bool cont_out = e1 < n && skey[e1] == row;
-  if (!cont_out) return;
-  const bool whole_from_before = e0 > 0 && skey[e0 - 1] == row && skey[e0] == row;
-  if (whole_from_before) return;  // the run started in an earlier segment
-  // last position of the run: largest q with skey[q] == row (keys ascending)
-  int64_t lo = e1, hi = n - 1;
-  while (lo < hi) {
-    const int64_t mid = hi - (hi - lo) / 2;
-    if (skey[mid] == row)
-      lo = mid;
-    else
-      hi = mid - 1;
+// Runs that span segments: each list entry is a run's first segment s0. One
+// wave per entry: lane t tests whether segment s0 + 1 + t begins with the run's
+// row; the first failing test ends the run. Runs over at most 64 later
+// segments are combined by the wave itself -- tail[s0] and head[] of those
+// segments in a fixed order (eight interleaved sums, then in order) -- and the
+// total is the row's only write (store, or added to the row's value). Longer
+// runs (the hottest rows) go to a second list for own_fix_long.
+template <int VW, bool OVR>
+__global__ void __launch_bounds__(256) own_fix(const uint32_t* __restrict__ skey, int64_t n,
+                                               int R, float* __restrict__ acc,
+                                               const float* __restrict__ head,
+                                               const float* __restrict__ tail,
+                                               const uint32_t* __restrict__ list,
+                                               const uint32_t* __restrict__ nlist,
+                                               uint32_t* __restrict__ llist,
+                                               uint32_t* __restrict__ nllist) {
+  typedef float VT __attribute__((ext_vector_type(VW)));
+  const int lane = threadIdx.x & 63;
+  const int64_t nseg = (n + kOwnSeg - 1) / kOwnSeg;
+  const uint32_t items = *nlist;
+  const uint32_t gw = blockIdx.x * 4 + (threadIdx.x >> 6), nw = gridDim.x * 4;
+  for (uint32_t it = gw; it < items; it += nw) {
+    const int64_t s0 = __builtin_amdgcn_readfirstlane(list[it]);
+    const int64_t e1 = min<int64_t>(n, (s0 + 1) * kOwnSeg);
+    const uint32_t row = __builtin_amdgcn_readfirstlane(skey[e1 - 1]);
+    const int64_t st = s0 + 1 + lane;
+    const bool in = st < nseg && skey[st * kOwnSeg] == row;
+    const uint64_t miss = __ballot(!in);
+    if (miss == 0) {  // continues past 64 more segments
+      if (lane == 0) llist[atomicAdd(nllist, 1u)] = (uint32_t)s0;
+      continue;
+    }
+    const int64_t send = s0 + __ffsll((long long)miss) - 1;  // last segment of the run
+    for (int c0 = 0; c0 < R; c0 += 64 * VW) {
+      const int col = c0 + VW * lane;
+      const bool cv = col < R;
+      const int colc = cv ? col : 0;
+      VT a8[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a8[q] = VT(0.f);
+      int64_t s = s0 + 1;
+      for (; s + 7 <= send; s += 8) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a8[q] += *reinterpret_cast<const VT*>(&head[(s + q) * R + colc]);
+      }
+#pragma unroll
+      for (int q = 0; q < 7; ++q)
+        if (s + q <= send) a8[q] += *reinterpret_cast<const VT*>(&head[(s + q) * R + colc]);
+      if (cv) {
+        const VT t = *reinterpret_cast<const VT*>(&tail[s0 * R + col]) +
+                     (((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7])));
+        VT* p = reinterpret_cast<VT*>(&acc[(int64_t)row * R + col]);
+        *p = OVR ? t : *p + t;
+      }
+    }
   }
-  const int64_t send = lo / kSeg;  // segments seg+1 .. send hold the rest of the run
-  for (int c0 = 0; c0 < R; c0 += 64) {
-    const int col = c0 + lane;
-    const bool cv = col < R;
-    float s = 0.f;
-    if (cv)
-      for (int64_t s2 = seg + 1 + wv; s2 <= send; s2 += 4) s += part_first[s2 * R + col];
-    __syncthreads();
-    wsum[wv][lane] = s;
-    __syncthreads();
-    if (wv == 0 && cv) {
-      const float total =
-          part_last[seg * R + col] + (((wsum[0][lane] + wsum[1][lane]) + wsum[2][lane]) + wsum[3][lane]);
-      atomicAdd(&acc[(int64_t)row * R + col], total);  // the row's only addition
+}
+
+// The runs own_fix left: one block of 16 waves per entry. Thread t tests segment
+// s0 + 1 + t (in rounds of 1024) and the first failing test ends the run; the
+// waves add head[] over the run's later segments in a fixed order (wave w takes
+// every 16th, eight interleaved sums each), the wave sums are combined in wave
+// order with tail[s0], and the total is the row's only write.
+template <int VW, bool OVR>
+__global__ void __launch_bounds__(1024) own_fix_long(const uint32_t* __restrict__ skey, int64_t n,
+                                                     int R, float* __restrict__ acc,
+                                                     const float* __restrict__ head,
+                                                     const float* __restrict__ tail,
+                                                     const uint32_t* __restrict__ llist,
+                                                     const uint32_t* __restrict__ nllist) {
+  typedef float VT __attribute__((ext_vector_type(VW)));
+  __shared__ VT wsum[16][64];
+  __shared__ int64_t first_miss[16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t nseg = (n + kOwnSeg - 1) / kOwnSeg;
+  const uint32_t items = *nllist;
+  for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+    const int64_t s0 = llist[it];
+    const int64_t e1 = min<int64_t>(n, (s0 + 1) * kOwnSeg);
+    const uint32_t row = skey[e1 - 1];
+    int64_t send = s0;
+    for (int64_t b = s0 + 1;; b += 1024) {
+      const int64_t st = b + threadIdx.x;
+      const bool in = st < nseg && skey[st * kOwnSeg] == row;
+      const uint64_t miss = __ballot(!in);
+      __syncthreads();
+      first_miss[wv] = miss ? (int64_t)(64 * wv + __ffsll((long long)miss) - 1) : 1024;
+      __syncthreads();
+      int64_t m = 1024;
+#pragma unroll
+      for (int w = 0; w < 16; ++w) m = min(m, first_miss[w]);
+      send = b + m - 1;
+      if (m < 1024) break;
+    }
+    for (int c0 = 0; c0 < R; c0 += 64 * VW) {
+      const int col = c0 + VW * lane;
+      const bool cv = col < R;
+      const int colc = cv ? col : 0;
+      VT a8[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a8[q] = VT(0.f);
+      int64_t s = s0 + 1 + wv;
+      for (; s + 7 * 16 <= send; s += 8 * 16) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          a8[q] += *reinterpret_cast<const VT*>(&head[(s + 16 * q) * R + colc]);
+      }
+#pragma unroll
+      for (int q = 0; q < 7; ++q)
+        if (s + 16 * q <= send) a8[q] += *reinterpret_cast<const VT*>(&head[(s + 16 * q) * R + colc]);
+      __syncthreads();
+      wsum[wv][lane] = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
+      __syncthreads();
+      if (wv == 0 && cv) {
+        VT t = *reinterpret_cast<const VT*>(&tail[s0 * R + col]);
+#pragma unroll
+        for (int w = 0; w < 16; ++w) t += wsum[w][lane];
+        VT* p = reinterpret_cast<VT*>(&acc[(int64_t)row * R + col]);
+        *p = OVR ? t : *p + t;
+      }
     }
   }
 }
@@ -726,8 +934,9 @@ static dex_status scatter_typed(void* acc, int32_t acc_dtype, int64_t n_rows, in
     hipLaunchKernelGGL((hist_private_kernel<IdxT>), dim3(nb), dim3(1024), nwords * 4, s,
                        (int32_t*)acc, (int)n_rows, idx, n, per, (uint32_t*)ws, oob);
     pr.end(1);
-    hipLaunchKernelGGL(hist_reduce_kernel, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, s,
-                       (int32_t*)acc, (int)n_rows, (const uint32_t*)ws, nb);
+    hipLaunchKernelGGL(hist_reduce_kernel,
+                       dim3((unsigned)((nwords + 255) / 256), (unsigned)((nb + kHistGroup - 1) / kHistGroup)),
+                       dim3(256), 0, s, (int32_t*)acc, (int)n_rows, (const uint32_t*)ws, nb);
     return check_hip(hipGetLastError(), "histogram");
   }
   if (acc_dtype == DEX_I32 && scale)
@@ -775,7 +984,8 @@ static dex_status scatter_typed(void* acc, int32_t acc_dtype, int64_t n_rows, in
 
 // Workspace of the sorted (deterministic) float scatter.
 struct SortWs {
-  uint32_t *ka, *va, *kb, *vb, *cnt, *tot;
+  uint32_t *ka, *kb, *cnt, *tot, *list, *nlist, *llist;
+  uint64_t *va, *vb;
   float *pf, *pl;
   size_t bytes;
 };
@@ -789,62 +999,92 @@ static SortWs sort_ws(int64_t n, int64_t R, char* base) {
     return base ? (void*)(base + at) : nullptr;
   };
   const int64_t ntiles = (n + kRsTile - 1) / kRsTile;
-  const int64_t nseg = (n + kSeg - 1) / kSeg;
+  const int64_t nseg = (n + kOwnSeg - 1) / kOwnSeg;
   w.ka = (uint32_t*)take((size_t)n * 4);
-  w.va = (uint32_t*)take((size_t)n * 4);
   w.kb = (uint32_t*)take((size_t)n * 4);
-  w.vb = (uint32_t*)take((size_t)n * 4);
-  w.cnt = (uint32_t*)take((size_t)256 * ntiles * 4);
-  w.tot = (uint32_t*)take(256 * 4);
+  w.va = (uint64_t*)take((size_t)n * 8);
+  w.vb = (uint64_t*)take((size_t)n * 8);
+  w.cnt = (uint32_t*)take((size_t)kRsDigits * ntiles * 4);
+  w.tot = (uint32_t*)take(kRsDigits * 4);
   w.pf = (float*)take((size_t)nseg * R * 4);
   w.pl = (float*)take((size_t)nseg * R * 4);
+  w.list = (uint32_t*)take((size_t)nseg * 4);
+  w.llist = (uint32_t*)take((size_t)nseg * 4);
+  w.nlist = (uint32_t*)take(8);  // [0]: spanning runs, [1]: the long ones among them
   w.bytes = o;
   return w;
 }
 
 size_t sorted_scatter_ws_bytes(int64_t n, int64_t R) { return sort_ws(n, R, nullptr).bytes; }
 
+template <int VW, bool OVR>
+static void launch_own(const SortWs& w, const uint32_t* skey, const uint64_t* sval, int64_t n,
+                       uint32_t sentinel, const float* vals, int R, float* acc, hipStream_t s) {
+  const int64_t nseg = (n + kOwnSeg - 1) / kOwnSeg;
+  const unsigned sb = (unsigned)((nseg + 3) / 4);
+  if (vals)
+    hipLaunchKernelGGL((own_sum<VW, 16, true, OVR>), dim3(sb), dim3(256), 0, s, skey, sval, n,
+                       sentinel, vals, R, acc, w.pf, w.pl, w.list, w.nlist);
+  else
+    hipLaunchKernelGGL((own_sum<VW, 16, false, OVR>), dim3(sb), dim3(256), 0, s, skey, sval, n,
+                       sentinel, vals, R, acc, w.pf, w.pl, w.list, w.nlist);
+  // fixed grids that walk the lists of spanning runs (their lengths stay on the device)
+  const unsigned fb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nseg + 3) / 4, 4 * num_cus()));
+  hipLaunchKernelGGL((own_fix<VW, OVR>), dim3(fb), dim3(256), 0, s, skey, n, R, acc, w.pf, w.pl,
+                     w.list, w.nlist, w.llist, w.nlist + 1);
+  hipLaunchKernelGGL((own_fix_long<VW, OVR>), dim3((unsigned)num_cus()), dim3(1024), 0, s, skey, n,
+                     R, acc, w.pf, w.pl, w.llist, w.nlist + 1);
+}
+
 template <typename IdxT>
 static dex_status scatter_sorted(float* acc, int64_t n_rows, int64_t R, const IdxT* idx,
                                  const float* vals, const float* scale, int64_t n, int64_t* oob,
-                                 void* ws, size_t ws_bytes, hipStream_t s) {
+                                 bool overwrite, void* ws, size_t ws_bytes, hipStream_t s) {
   if (n_rows > 0xFFFFFFFEll || n > 0xFFFFFFFFll)
     return fail(DEX_ERR_UNSUPPORTED, "sorted scatter: at most 2^32-2 rows and 2^32 indices");
   const SortWs w = sort_ws(n, R, (char*)ws);
   if (!ws || ws_bytes < w.bytes)
     return fail(DEX_ERR_WORKSPACE, "sorted scatter needs %zu workspace bytes, got %zu", w.bytes, ws_bytes);
   const int ntiles = (int)((n + kRsTile - 1) / kRsTile);
-  const int64_t nseg = (n + kSeg - 1) / kSeg;
   const int nbits = 64 - __builtin_clzll((unsigned long long)n_rows);  // n_rows itself is the sentinel
-  const int passes = (nbits + 7) / 8;
+  const int passes = (nbits + kRsBits - 1) / kRsBits;
   ProfRange pr(DEX_PROF_SCATTER, s);
-  hipLaunchKernelGGL((rs_init<IdxT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, idx, n,
-                     n_rows, w.ka, w.va, oob);
-  uint32_t *kin = w.ka, *vin = w.va, *kout = w.kb, *vout = w.vb;
+  // pass 0 reads the indices and scales directly; the sorted pairs then
+  // alternate between the two buffers
+  uint32_t *kin = w.ka, *kout = w.kb;
+  uint64_t *vin = w.va, *vout = w.vb;
   for (int p = 0; p < passes; ++p) {
-    const int shift = 8 * p;
-    hipLaunchKernelGGL(rs_hist, dim3(ntiles), dim3(1024), 0, s, kin, n, shift, w.cnt, ntiles);
-    hipLaunchKernelGGL(rs_digit_scan, dim3(256), dim3(256), 0, s, w.cnt, ntiles, w.tot);
-    hipLaunchKernelGGL(rs_scatter, dim3(ntiles), dim3(1024), 0, s, kin, vin, kout, vout, n, shift,
-                       w.cnt, w.tot, ntiles);
+    const int shift = kRsBits * p;
+    if (p == 0)
+      hipLaunchKernelGGL((rs_hist<true, IdxT>), dim3(ntiles), dim3(1024), 0, s, idx, kin, n, n_rows,
+                         shift, w.cnt, ntiles, w.nlist, oob);
+    else
+      hipLaunchKernelGGL((rs_hist<false, IdxT>), dim3(ntiles), dim3(1024), 0, s, idx, kin, n,
+                         n_rows, shift, w.cnt, ntiles, w.nlist, oob);
+    hipLaunchKernelGGL(rs_digit_scan, dim3(kRsDigits), dim3(256), 0, s, w.cnt, ntiles, w.tot);
+    if (p == 0)
+      hipLaunchKernelGGL((rs_scatter<true, IdxT>), dim3(ntiles), dim3(1024), 0, s, idx, scale, n_rows,
+                         kin, vin, kout, vout, n, shift, w.cnt, w.tot, ntiles);
+    else
+      hipLaunchKernelGGL((rs_scatter<false, IdxT>), dim3(ntiles), dim3(1024), 0, s, idx, scale,
+                         n_rows, kin, vin, kout, vout, n, shift, w.cnt, w.tot, ntiles);
     std::swap(kin, kout);
     std::swap(vin, vout);
   }
-  const unsigned sb = (unsigned)((nseg + 3) / 4);
-  if (vals && scale)
-    hipLaunchKernelGGL((seg_sum<8, true, true>), dim3(sb), dim3(256), 0, s, kin, vin, n,
-                       (uint32_t)n_rows, vals, scale, (int)R, acc, w.pf, w.pl);
-  else if (vals)
-    hipLaunchKernelGGL((seg_sum<8, true, false>), dim3(sb), dim3(256), 0, s, kin, vin, n,
-                       (uint32_t)n_rows, vals, scale, (int)R, acc, w.pf, w.pl);
-  else if (scale)
-    hipLaunchKernelGGL((seg_sum<8, false, true>), dim3(sb), dim3(256), 0, s, kin, vin, n,
-                       (uint32_t)n_rows, vals, scale, (int)R, acc, w.pf, w.pl);
+  // widest column vector the row length and the pointers' alignment allow
+  const uintptr_t al = (uintptr_t)acc | (uintptr_t)(vals ? vals : acc);
+  const int vw = (R % 4 == 0 && R >= 256 && (al & 15) == 0) ? 4 : (R % 2 == 0 && (al & 7) == 0) ? 2 : 1;
+  const uint32_t sent = (uint32_t)n_rows;
+#define DEX_OWNL(V)                                                                   \
+  (overwrite ? launch_own<V, true>(w, kin, vin, n, sent, vals, (int)R, acc, s)        \
+             : launch_own<V, false>(w, kin, vin, n, sent, vals, (int)R, acc, s))
+  if (vw == 4)
+    DEX_OWNL(4);
+  else if (vw == 2)
+    DEX_OWNL(2);
   else
-    hipLaunchKernelGGL((seg_sum<8, false, false>), dim3(sb), dim3(256), 0, s, kin, vin, n,
-                       (uint32_t)n_rows, vals, scale, (int)R, acc, w.pf, w.pl);
-  hipLaunchKernelGGL(seg_fix, dim3((unsigned)nseg), dim3(256), 0, s, kin, n, (uint32_t)n_rows,
-                     (int)R, acc, w.pf, w.pl);
+    DEX_OWNL(1);
+#undef DEX_OWNL
   pr.end(1);
   return check_hip(hipGetLastError(), "sorted scatter");
 }
@@ -852,15 +1092,15 @@ static dex_status scatter_sorted(float* acc, int64_t n_rows, int64_t R, const Id
 dex_status accum_scatter(void* acc, int32_t acc_dtype, int64_t n_rows, int64_t row_len,
                          const void* idx, int32_t idx_dtype, const void* vals,
                          const float* scale, int64_t n, bool count_oob, int64_t* oob, void* ws,
-                         size_t ws_bytes, int cfg, hipStream_t s) {
+                         size_t ws_bytes, int path, hipStream_t s, bool overwrite) {
   if (n == 0) return DEX_OK;
   int64_t* o = count_oob ? oob : nullptr;
-  if (cfg == 1 && acc_dtype == DEX_F32) {
+  if (path == kScatterSorted && acc_dtype == DEX_F32) {
     if (idx_dtype == DEX_I32)
       return scatter_sorted<int32_t>((float*)acc, n_rows, row_len, (const int32_t*)idx,
-                                     (const float*)vals, scale, n, o, ws, ws_bytes, s);
+                                     (const float*)vals, scale, n, o, overwrite, ws, ws_bytes, s);
     return scatter_sorted<uint32_t>((float*)acc, n_rows, row_len, (const uint32_t*)idx,
-                                    (const float*)vals, scale, n, o, ws, ws_bytes, s);
+                                    (const float*)vals, scale, n, o, overwrite, ws, ws_bytes, s);
   }
   if (idx_dtype == DEX_I32)
     return scatter_typed<int32_t>(acc, acc_dtype, n_rows, row_len, (const int32_t*)idx, vals,
