@@ -72,9 +72,10 @@ typedef int32_t dex_status;
                             through P_k = Q_k^T Q_k, per-tile power-of-two scaling);
                             forward at other D: BF16 Q_k (x_i - mu_k) products;
                             reverse (weighted moments) FP16 at every D. All operands
-                            are taken about the mean of the component means, which
-                            changes no result (only x - mu enters) but keeps the
-                            16-bit values small for data far from the origin.     */
+                            are taken about the mean of the first min(K, 16)
+                            component means, which changes no result (only x - mu
+                            enters) but keeps the 16-bit values small for data far
+                            from the origin.                                      */
 #define DEX_GMM_BF16X3 2 /* split-BF16 operands, hi*hi + hi*lo + lo*hi per product   */
 
 /* stencil variants */

@@ -376,26 +376,34 @@ struct MfmaOps {
 
 // ---------------------------------------------------------------------------
 // The origin about which the matrix-core forms take their operands: the mean
-// of the component means, c[d] = (1/K) sum_k means[k][d] (FP64 sums in a fixed
-// order, the same in every block), zero for d >= D, into csh[64] (LDS). Every
-// term of the objective and of its gradient depends on x_i and mu_k only
-// through x_i - mu_k = (x_i - c) - (mu_k - c), so moving the origin changes no
-// result; it keeps the 16-bit operands, and the expansion
-// ||Q(x - mu)||^2 = x^T P x - 2 (P mu)^T x + mu^T P mu of the feature-product
-// form, free of the cancellation that data far from the origin would cause.
+// of the first min(K, 16) component means, c[d] = (1/K') sum_{k<K'} means[k][d]
+// (a fixed-order sum, the same in every block), zero for d >= D, into csh[64]
+// (LDS). Every term of the objective and of its gradient depends on x_i and
+// mu_k only through x_i - mu_k = (x_i - c) - (mu_k - c), so moving the origin
+// changes no result; a point among the means keeps the 16-bit operands, and
+// the expansion ||Q(x - mu)||^2 = x^T P x - 2 (P mu)^T x + mu^T P mu of the
+// feature-product form, free of the cancellation that data far from the
+// origin would cause. Sixteen means (4 KiB, one load per thread) keep the cost
+// per block small: every block of the preparation launch computes it.
 // For 256-thread blocks; every thread must call it.
 DEX_DEV void block_shift(const float* __restrict__ means, int K, int D, float* csh) {
-  __shared__ double part[4][64];
-  const int t = threadIdx.x, d = t & 63, q = t >> 6;
-  double s = 0.0;
-  if (d < D) {
-#pragma unroll 8
-    for (int k = q; k < K; k += 4) s += (double)means[(size_t)k * D + d];
+  constexpr int kMeans = 16;
+  __shared__ float part[kMeans][64];
+  const int t = threadIdx.x, Kc = K < kMeans ? K : kMeans;
+  // thread t: mean t / 16, dimensions 4 (t % 16) .. + 3
+  const int k = t >> 4, d0 = 4 * (t & 15);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int d = d0 + i;
+    part[k][d] = k < Kc && d < D ? means[(size_t)k * D + d] : 0.f;
   }
-  part[q][d] = s;
   __syncthreads();
-  if (t < 64)
-    csh[t] = t < D ? (float)((((part[0][t] + part[1][t]) + part[2][t]) + part[3][t]) / K) : 0.f;
+  if (t < 64) {
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < kMeans; ++q) s += part[q][t];
+    csh[t] = t < D ? s / (float)Kc : 0.f;
+  }
   __syncthreads();
 }
 
@@ -405,7 +413,7 @@ DEX_DEV void block_shift(const float* __restrict__ means, int K, int D, float* c
 // Optional outputs: xh == nullptr skips x~; tmax != nullptr receives the
 // largest |x| of the tile (for the scaling of the feature-product forward).
 // shift != nullptr: every coordinate of a real point has shift[b] subtracted
-// (the origin moved to the centre of the means, so 16-bit operands carry
+// (the origin moved among the means, so 16-bit operands carry
 // x - c, not x; every quadratic form in x - mu is unchanged).
 template <int PREC, int DP>
 DEX_DEV void prep_x_tile(const float* __restrict__ x, int N, int D, int Npad, int p0,
@@ -769,6 +777,167 @@ __host__ __device__ inline size_t mom_slot(int DP) {
   return (size_t)(nb * (nb + 1) / 2) * 256 + DP + 4;
 }
 
+// FP16 moments with the point weights computed ahead (software pipelined).
+// Step s (32 points) computes the weights of step s + 2 from beta and f loaded
+// two steps earlier and writes them to LDS buffer s % 2, reads back those of
+// step s + 1 (written during step s - 1) from the other buffer, and runs its
+// own products with the weights read during step s - 1. So neither the
+// exponentials nor the LDS round trip sit between two steps' products, and
+// the scheduler interleaves them with the matrix-core instructions. Within a
+// wave LDS instructions execute in issue order; the fence at the end of every
+// step keeps the compiler from moving a step's LDS accesses past it. Same
+// operands, sums and slot layout as the other moment forms.
+template <int DP, int GW>
+DEX_DEV void bwd_mom_unit_f16p(const void* xT_hi, int N, int Npad, int K, int kw, int pbeg,
+                               int pend, const float* __restrict__ beta,
+                               const float* __restrict__ f, float ctv, float* __restrict__ part,
+                               size_t pstride) {
+  using V8 = typename MomT<MP_F16>::V8;
+  constexpr int NB = DP / 16, NBLK = NB * (NB + 1) / 2;
+  constexpr int NP = (GW + 1) / 2;  // component pairs
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+  const int half = lane >> 5, j = lane & 31;
+  if (kw >= K) return;
+  const _Float16* xh = (const _Float16*)xT_hi;
+  __shared__ __attribute__((aligned(16))) _Float16 wsh[2][4][2 * NP][32];
+
+  f32x4 sacc[GW][NBLK];
+  f32x4 uq[NB];  // u = x~^T W: 16 dims x 16 component columns per row block
+  float aacc[NP];
+#pragma unroll
+  for (int gk = 0; gk < GW; ++gk)
+#pragma unroll
+    for (int q = 0; q < NBLK; ++q) sacc[gk][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ab = 0; ab < NB; ++ab) uq[ab] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int pp = 0; pp < NP; ++pp) aacc[pp] = 0.f;
+
+  // every load is in bounds: steps past the end reload the last one, f is
+  // clamped to N - 1, components past K to K - 1
+  auto load_x = [&](int t, V8(&xt)[NB]) {
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb)
+      xt[bb] = *reinterpret_cast<const V8*>(xh + (size_t)(16 * bb + c) * Npad + t + 8 * g);
+  };
+  auto load_w = [&](int t, float(&bt)[NP], float& ft) {
+    const int p = t + j;
+    ft = f[min(p, N - 1)];
+#pragma unroll
+    for (int pp = 0; pp < NP; ++pp)
+      bt[pp] = __builtin_nontemporal_load(
+          &beta[(size_t)min(kw + 2 * pp + half, K - 1) * Npad + p]);
+  };
+  // weights of the step at t (lanes 0-31: component kw + 2pp, lanes 32-63:
+  // kw + 2pp + 1, point t + j) into LDS buffer b; zero past N, K or pend
+  auto weights = [&](int t, const float(&bt)[NP], float ft, int b) {
+    const bool vown = t < pend && t + j < N;
+#pragma unroll
+    for (int pp = 0; pp < NP; ++pp) {
+      const bool vk = kw + 2 * pp + half < K && (GW > 1 || half == 0);
+      const float w = vown && vk ? __expf(bt[pp] - ft) * ctv : 0.f;
+      aacc[pp] += w;
+      wsh[b][wv][2 * pp + half][mom_pos(j)] = (_Float16)w;
+    }
+  };
+  // lane (c, g): the weights of its 8 points for every component (A-operand
+  // scaling), and component c's weights of those points (u product)
+  auto readw = [&](int b, V8(&wq)[GW], V8& wc) {
+#pragma unroll
+    for (int gk = 0; gk < GW; ++gk) wq[gk] = *reinterpret_cast<const V8*>(&wsh[b][wv][gk][8 * g]);
+    wc = c < GW ? *reinterpret_cast<const V8*>(&wsh[b][wv][c < GW ? c : 0][8 * g]) : V8{};
+  };
+  auto wave_fence = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  // step at t0 with parity b (= step index % 2): x rows xt (loaded during the
+  // previous step), next step's rows into xn, beta/f slot (bs, fs) holding the
+  // step at t0 + 64, weights wc / wcc of this step, wn / wnc receive the next
+  auto step = [&](int t0, V8(&xt)[NB], V8(&xn)[NB], float(&bs)[NP], float& fs, V8(&wq)[GW],
+                  V8& wcc, V8(&wn)[GW], V8& wnc, int b) {
+    load_x(t0 + 32 < pend ? t0 + 32 : t0, xn);
+    weights(t0 + 64, bs, fs, b);
+    load_w(min(t0 + 128, pend - 32), bs, fs);
+    readw(b ^ 1, wn, wnc);
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) uq[bb] = mom_mma1<MP_F16>(xt[bb], wcc, uq[bb]);
+    // scaled rows of component gk + 1 are formed while component gk's
+    // products run (two buffers)
+    V8 sa[2][NB];
+#pragma unroll
+    for (int ab = 0; ab < NB; ++ab) sa[0][ab] = xt[ab] * wq[0];
+#pragma unroll
+    for (int gk = 0; gk < GW; ++gk) {
+      if (gk + 1 < GW) {
+#pragma unroll
+        for (int ab = 0; ab < NB; ++ab) sa[(gk + 1) & 1][ab] = xt[ab] * wq[gk + 1];
+      }
+#pragma unroll
+      for (int ab = 0; ab < NB; ++ab) {
+        const int q0 = ab * (ab + 1) / 2;
+#pragma unroll
+        for (int bb = 0; bb <= ab; ++bb)
+          sacc[gk][q0 + bb] = mom_mma1<MP_F16>(sa[gk & 1][ab], xt[bb], sacc[gk][q0 + bb]);
+      }
+#pragma unroll
+      for (int i = 0; i < NBLK; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix-core op
+        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // then two vector ALU ops
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    wave_fence();
+  };
+
+  V8 xA[NB], xB[NB], wqA[GW], wqB[GW], wcA, wcB;
+  float bA[NP], fA, bB[NP], fB;
+  if (pbeg >= pend) return;
+  // prologue: weights of steps 0 and 1 into buffers 0 and 1, slots refilled
+  // with steps 2 and 3, weights of step 0 read back
+  load_x(pbeg, xA);
+  load_w(pbeg, bA, fA);
+  load_w(min(pbeg + 32, pend - 32), bB, fB);
+  weights(pbeg, bA, fA, 0);
+  weights(pbeg + 32, bB, fB, 1);
+  load_w(min(pbeg + 64, pend - 32), bA, fA);
+  load_w(min(pbeg + 96, pend - 32), bB, fB);
+  wave_fence();
+  readw(0, wqA, wcA);
+  int t0 = pbeg;
+  for (; t0 + 32 < pend; t0 += 64) {
+    step(t0, xA, xB, bA, fA, wqA, wcA, wqB, wcB, 0);
+    step(t0 + 32, xB, xA, bB, fB, wqB, wcB, wqA, wcA, 1);
+  }
+  if (t0 < pend) step(t0, xA, xB, bA, fA, wqA, wcA, wqB, wcB, 0);
+
+  // A: lanes 0-31 hold component kw + 2pp, lanes 32-63 component kw + 2pp + 1
+  float asum[NP];
+#pragma unroll
+  for (int pp = 0; pp < NP; ++pp) {
+    float v = aacc[pp];
+#pragma unroll
+    for (int m = 16; m >= 1; m >>= 1) v += xor_lane(v, m);
+    asum[pp] = v;
+  }
+#pragma unroll
+  for (int gk = 0; gk < GW; ++gk) {
+    const int k = kw + gk;
+    if (k >= K) break;
+    float* P = part + (size_t)k * pstride;
+#pragma unroll
+    for (int q = 0; q < NBLK; ++q) *reinterpret_cast<f32x4*>(&P[q * 256 + lane * 4]) = sacc[gk][q];
+    // uq[ab] lane (c, g): u of component kw + c, dims 16 ab + 4 g + i
+    if (c == gk) {
+#pragma unroll
+      for (int ab = 0; ab < NB; ++ab)
+        *reinterpret_cast<f32x4*>(&P[NBLK * 256 + 16 * ab + 4 * g]) = uq[ab];
+    }
+    if (lane == 32 * (gk & 1)) P[NBLK * 256 + DP] = asum[gk >> 1];
+  }
+}
+
 // One wave accumulates S, u, A for components kw .. kw+GW-1 over the points
 // [pbeg, pend), 32 per step. Both operands come from x~^T: lane 16 g + c
 // holds feature row 16 bb + c and the 8 points of group g (one 16-byte load
@@ -777,10 +946,10 @@ __host__ __device__ inline size_t mom_slot(int DP) {
 // two components at a time (lanes 0-31 one component, 32-63 the next) and
 // exchanged through LDS in the same point order (FP16 for the FP16 moments).
 template <int DP, int MP, int GW, bool DB = true>
-DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad, int K, int kw,
-                          int pbeg, int pend, const float* __restrict__ beta,
-                          const float* __restrict__ f, float ctv, float* __restrict__ part,
-                          size_t pstride) {
+DEX_DEV void bwd_mom_unit_gen(const void* xT_hi, const void* xT_lo, int N, int Npad, int K, int kw,
+                              int pbeg, int pend, const float* __restrict__ beta,
+                              const float* __restrict__ f, float ctv, float* __restrict__ part,
+                              size_t pstride) {
   using MT = MomT<MP>;
   using S = typename MT::S;
   using V8 = typename MT::V8;
@@ -1034,6 +1203,19 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
     }
     if (lane == 32 * (gk & 1)) P[NBLK * 256 + DP] = asum[gk >> 1];
   }
+}
+
+// The FP16 form with double-buffered rows takes the pipelined-weights unit.
+template <int DP, int MP, int GW, bool DB = true>
+DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad, int K, int kw,
+                          int pbeg, int pend, const float* __restrict__ beta,
+                          const float* __restrict__ f, float ctv, float* __restrict__ part,
+                          size_t pstride) {
+  if constexpr (MP == MP_F16 && DB)
+    bwd_mom_unit_f16p<DP, GW>(xT_hi, N, Npad, K, kw, pbeg, pend, beta, f, ctv, part, pstride);
+  else
+    bwd_mom_unit_gen<DP, MP, GW, DB>(xT_hi, xT_lo, N, Npad, K, kw, pbeg, pend, beta, f, ctv, part,
+                                     pstride);
 }
 
 // Final step of the moment form for component k: fixed-order compensated sums

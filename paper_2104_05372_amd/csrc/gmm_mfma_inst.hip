@@ -584,11 +584,15 @@ constexpr int kQfWaves = 8;
 template <int CH>
 DEX_DEV void qf_chunk(const qf::h2 (&xr)[4][32], _Float16 one, const qf::h8 (&w)[2],
                       f32x4 (&acc)[4][2]) {
+  // coefficients as the A operand and features as B (the A and B register
+  // layouts of this product are the same): the result is component x point, so
+  // a lane holds 4 components of one point (lane (c, g): point c, components
+  // 4g .. 4g + 3 of the tile)
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) {
     const qf::h8 z = qf::features<CH>(xr[tt], one);
-    acc[tt][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(z, w[0], acc[tt][0], 0, 0, 0);
-    acc[tt][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(z, w[1], acc[tt][1], 0, 0, 0);
+    acc[tt][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[0], z, acc[tt][0], 0, 0, 0);
+    acc[tt][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[1], z, acc[tt][1], 0, 0, 0);
   }
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) {
@@ -669,14 +673,16 @@ __global__ void __launch_bounds__(64 * kQfWaves) k_gmm_fwd_qf(
     }
     static_assert(qf::kChunks * 2 % kQfWaves == 0, "whole pieces per wave");
     __syncthreads();  // (waits for the loads: vmcnt(0))
-    // the pass's kappa' and rescale factors of the lane's two components,
-    // loaded once per pass (not after every unit's products)
-    float kqv[2], iscv[2];
+    // the pass's kappa' and rescale factors of the lane's eight components
+    // (16 n + 4 g + i), loaded once per pass (not after every unit's products)
+    float kqv[2][4], iscv[2][4];
 #pragma unroll
-    for (int n = 0; n < 2; ++n) {
-      kqv[n] = kq[pass * qf::kPass + 16 * n + c];
-      iscv[n] = isc[pass * qf::kPass + 16 * n + c];
-    }
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        kqv[n][i] = kq[pass * qf::kPass + 16 * n + 4 * g + i];
+        iscv[n][i] = isc[pass * qf::kPass + 16 * n + 4 * g + i];
+      }
     for (int64_t u = cur + wv; u < seg; u += kQfWaves) {
       const int pb = (int)(t0 + (u - (int64_t)pass * ntx)) * 64;  // the tile's first point
       // one prep tile: one scale 2^-ex, and "one" = 2^-ex
@@ -693,76 +699,65 @@ __global__ void __launch_bounds__(64 * kQfWaves) k_gmm_fwd_qf(
       __builtin_amdgcn_s_setprio(2);
       qf_chunks(xr, one, wsh, lane, acc, std::make_integer_sequence<int, qf::kChunks>{});
       __builtin_amdgcn_s_setprio(0);
+      // lane (c, g) holds, for point pb + 16 tt + c, acc[tt][n][i] of
+      // component pass * 32 + 16 n + 4 g + i
       if constexpr (TAN) {
         // dbeta = dkq' - disc 2^(2 ex) / 2 * product, weighted by exp(beta - f)
         float lsum = 0.f;
 #pragma unroll
-        for (int n = 0; n < 2; ++n) {
-          const int k = pass * qf::kPass + 16 * n + c;  // < Kp: beta has the row
-          const bool vk = k < K;
-          const float kk = kqv[n], is = ldexpf(iscv[n], 2 * ex);
+        for (int tt = 0; tt < 4; ++tt) {
+          const int p = pb + 16 * tt + c;
+          const float fv = fres[min(p, N - 1)];
 #pragma unroll
-          for (int tt = 0; tt < 4; ++tt) {
-            const int p0 = pb + 16 * tt + 4 * g;
-            const f32x4 bv = *reinterpret_cast<const f32x4*>(beta + (size_t)k * Npad + p0);
+          for (int n = 0; n < 2; ++n)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const int p = p0 + i;
-              const float fv = fres[min(p, N - 1)];
-              const float w = vk && p < N ? __expf(bv[i] - fv) : 0.f;
-              lsum = fmaf(w, kk - 0.5f * is * acc[tt][n][i], lsum);
+              const int k = pass * qf::kPass + 16 * n + 4 * g + i;  // < Kp: beta has the row
+              const float bv = beta[(size_t)k * Npad + p];
+              const float w = k < K && p < N ? __expf(bv - fv) : 0.f;
+              const float is = ldexpf(iscv[n][i], 2 * ex);
+              lsum = fmaf(w, kqv[n][i] - 0.5f * is * acc[tt][n][i], lsum);
             }
-          }
         }
         const double ds = wave_sum((double)lsum);
         if (lane == 0) part[(size_t)pass * ntiles + (pb >> 6)] = ds;
         continue;
       }
-      // epilogue: beta = kappa' - isc 2^(2 ex) / 2 * product; log-sum-exp over the pass
-#pragma unroll
-      for (int n = 0; n < 2; ++n) {
-        const int k = pass * qf::kPass + 16 * n + c;
-        const float kk = kqv[n], is = ldexpf(iscv[n], 2 * ex);
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) acc[tt][n][i] = kk - 0.5f * is * acc[tt][n][i];
-          *reinterpret_cast<f32x4*>(beta + (size_t)k * Npad + pb + 16 * tt + 4 * g) = acc[tt][n];
-        }
-      }
-      // exp(b - M) as exp2(b log2 e - M log2 e); passes whose 32 components
-      // are all real skip the masks
+      // epilogue: beta = kappa' - isc 2^(2 ex) / 2 * product, stored per
+      // component row; the pass's log-sum-exp of each point: the lane's 8
+      // components, then the 4 lanes of the point (lanes c, c + 16, c + 32,
+      // c + 48) by two lane-pair exchanges; exp(b - M) as exp2(b log2 e -
+      // M log2 e). Passes whose 32 components are all real skip the masks.
       auto lse = [&](auto full_t) {
         constexpr bool FULL = decltype(full_t)::value;
-        const bool v0 = FULL || pass * qf::kPass + c < K;
-        const bool v1 = FULL || pass * qf::kPass + 16 + c < K;
         constexpr float kL2e = 1.4426950408889634f;
 #pragma unroll
         for (int tt = 0; tt < 4; ++tt) {
-          float M[4], Ls[4];
+          const int p = pb + 16 * tt + c;
+          float m = -INFINITY;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float b0 = acc[tt][0][i], b1 = acc[tt][1][i];
-            int key;
-            if constexpr (FULL)
-              key = max(fkey(b0), fkey(b1));
-            else
-              key = max(v0 ? fkey(b0) : fkey(-INFINITY), v1 ? fkey(b1) : fkey(-INFINITY));
-            M[i] = row_max16k(key);
-            const float m2 = M[i] * kL2e;
-            float e0 = __builtin_amdgcn_exp2f(fmaf(b0, kL2e, -m2));
-            float e1 = __builtin_amdgcn_exp2f(fmaf(b1, kL2e, -m2));
-            if constexpr (!FULL) {
-              e0 = v0 ? e0 : 0.f;
-              e1 = v1 ? e1 : 0.f;
+          for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int k = pass * qf::kPass + 16 * n + 4 * g + i;
+              const float b = kqv[n][i] - 0.5f * ldexpf(iscv[n][i], 2 * ex) * acc[tt][n][i];
+              acc[tt][n][i] = b;
+              beta[(size_t)k * Npad + p] = b;
+              if (FULL || k < K) m = fmaxf(m, b);
             }
-            Ls[i] = row_sum16(e0 + e1);
-          }
-          if (c < 4) {
-            const float mm = c == 0 ? M[0] : c == 1 ? M[1] : c == 2 ? M[2] : M[3];
-            const float ll = c == 0 ? Ls[0] : c == 1 ? Ls[1] : c == 2 ? Ls[2] : Ls[3];
-            ml[(size_t)pass * Npad + pb + 16 * tt + 4 * g + c] = make_float2(mm, ll);
-          }
+          m = pair_max32(pair_max16(m));
+          const float m2 = m * kL2e;
+          float e = 0.f;
+#pragma unroll
+          for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int k = pass * qf::kPass + 16 * n + 4 * g + i;
+              const float ev = __builtin_amdgcn_exp2f(fmaf(acc[tt][n][i], kL2e, -m2));
+              e += FULL || k < K ? ev : 0.f;
+            }
+          e = pair_sum32(pair_sum16(e));
+          if (g == 0) ml[(size_t)pass * Npad + p] = make_float2(m, e);
         }
       };
       if (pass * qf::kPass + qf::kPass <= K)

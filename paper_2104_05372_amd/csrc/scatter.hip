@@ -201,26 +201,53 @@ __global__ void __launch_bounds__(1024) hist_private_kernel(int32_t* __restrict_
     for (int64_t j = b0 + threadIdx.x; j < min(a0, b1); j += blockDim.x) bump(load_index(keys, j));
     typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
     const u32x4* k4 = reinterpret_cast<const u32x4*>(keys);
-    // four 16-byte loads in flight per thread before the LDS updates
+    // four 16-byte loads per thread per round; the next round's loads are
+    // issued before this round's LDS updates
     const int64_t q1 = a1 / 4;
     const int64_t step = (int64_t)blockDim.x;
-    for (int64_t q = a0 / 4 + threadIdx.x; q < q1; q += 4 * step) {
-      u32x4 v[4];
+    auto load4 = [&](int64_t q, u32x4(&v)[4]) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         v[i] = (q + i * step < q1) ? __builtin_nontemporal_load(k4 + q + i * step)
                                    : u32x4{0u, 0u, 0u, 0u};
+    };
+    u32x4 vn[4];
+    load4(a0 / 4 + threadIdx.x, vn);
+    for (int64_t q = a0 / 4 + threadIdx.x; q < q1; q += 4 * step) {
+      u32x4 v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = vn[i];
+      load4(q + 4 * step, vn);
+      // the 16 LDS additions are issued back to back and their results
+      // checked afterwards (a drain then waits at most 16 increments per
+      // thread, far inside the 2^16 - 2^14 headroom of a counter)
+      uint32_t old[4][4], kk[4][4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        if (q + i * step >= q1) break;
+        const bool live = q + i * step < q1;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
+          int64_t kv;
           if constexpr (IdxT(-1) < IdxT(0))
-            bump((int64_t)(int32_t)v[i][e]);
+            kv = (int64_t)(int32_t)v[i][e];
           else
-            bump((int64_t)v[i][e]);
+            kv = (int64_t)v[i][e];
+          const bool ok = live && kv >= 0 && kv < n_bins;
+          bad += live && !ok;
+          kk[i][e] = ok ? (uint32_t)kv : 0xFFFFFFFFu;
+          old[i][e] = ok ? atomicAdd(&cnt[(uint32_t)kv >> 1], 1u << (((uint32_t)kv & 1u) << 4)) : 0u;
         }
       }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t k = kk[i][e], sh = (k & 1u) << 4;
+          if (k != 0xFFFFFFFFu && ((old[i][e] >> sh) & 0xFFFFu) == kDrain - 1u) {
+            atomicSub(&cnt[k >> 1], kDrain << sh);
+            atomicAdd(&acc[k], (int32_t)kDrain);
+          }
+        }
     }
     for (int64_t j = max(a1, a0) + threadIdx.x; j < b1; j += blockDim.x) bump(load_index(keys, j));
   } else {

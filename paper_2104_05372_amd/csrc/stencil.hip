@@ -80,8 +80,9 @@ __global__ void __launch_bounds__(256) stencil_strip(const float* __restrict__ u
     er[q] = row[xr];
   }
   const float a = 1.f - 4.f * c;
-#pragma unroll
-  for (int q = 1; q <= RB; ++q) {
+  // a compile-time row index (static_for): r, el and er stay in registers
+  static_for<RB>([&](auto qc) {
+    constexpr int q = decltype(qc)::value + 1;
     const f32x4 cc = r[q], nn = r[q - 1], ss = r[q + 1];
     float lf = __shfl_up(cc[3], 1, 64);
     float rt = __shfl_down(cc[0], 1, 64);
@@ -116,7 +117,7 @@ __global__ void __launch_bounds__(256) stencil_strip(const float* __restrict__ u
       }
     }
     *reinterpret_cast<f32x4*>(out + off) = o;
-  }
+  });
 }
 
 __global__ void __launch_bounds__(256) stencil_step_scalar(const float* __restrict__ u,
@@ -338,14 +339,25 @@ St st_of(const dex_desc& d) {
   return s;
 }
 
+// Rows per wave of the strip kernels (0: the grid does not allow the strip
+// form). Taller strips re-read fewer halo rows (RB + 2 rows read per RB
+// written) but 16 rows measured no faster than 8 at 4096^2 (fewer waves per
+// SIMD, 170 registers).
 constexpr int kRB = 8;
-bool strip_ok(const St& s) { return s.W % 256 == 0 && s.H % (4 * kRB) == 0; }
+int strip_rb(const St& s) { return s.W % 256 == 0 && s.H % (4 * kRB) == 0 ? kRB : 0; }
+
+template <bool ADJ>
+void launch_strip(const St& s, const float* in, float* out, float* snap, const float* ustate,
+                  int accumulate, hipStream_t st) {
+  hipLaunchKernelGGL((stencil_strip<kRB, ADJ>), dim3(s.W / 256, s.H / (4 * kRB)), dim3(256), 0, st,
+                     in, out, snap, ustate, s.H, s.W, s.c, s.rho, accumulate);
+}
 
 // strip: use the strip kernels where the grid allows them (a tuning config).
 void step(const St& s, const float* u, float* un, float* snap, bool strip, hipStream_t st) {
-  if (strip && strip_ok(s)) {
-    hipLaunchKernelGGL((stencil_strip<kRB, false>), dim3(s.W / 256, s.H / (4 * kRB)), dim3(256), 0,
-                       st, u, un, snap, nullptr, s.H, s.W, s.c, s.rho, 0);
+  const int rb = strip ? strip_rb(s) : 0;
+  if (rb) {
+    launch_strip<false>(s, u, un, snap, nullptr, 0, st);
   } else if (s.vec) {
     const int64_t nt = s.n / 4;
     hipLaunchKernelGGL(stencil_step_vec, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, u,
@@ -364,9 +376,8 @@ void adj(const St& s, int form, const float* g, const float* u, float* out, bool
     if (!accumulate) fill_zero(out, (size_t)s.n * 4, st);
     hipLaunchKernelGGL(stencil_adj_scatter, dim3(nb), dim3(256), 0, st, g, u, out, s.H, s.W, s.c,
                        s.rho);
-  } else if (form == 0 && strip_ok(s)) {
-    hipLaunchKernelGGL((stencil_strip<kRB, true>), dim3(s.W / 256, s.H / (4 * kRB)), dim3(256), 0,
-                       st, g, out, nullptr, u, s.H, s.W, s.c, s.rho, accumulate ? 1 : 0);
+  } else if (form == 0 && strip_rb(s)) {
+    launch_strip<true>(s, g, out, nullptr, u, accumulate ? 1 : 0, st);
   } else if (s.vec) {
     hipLaunchKernelGGL(stencil_adj_gather_vec, dim3((unsigned)((s.n / 4 + 255) / 256)), dim3(256),
                        0, st, g, u, out, s.H, s.W, s.c, s.rho, accumulate ? 1 : 0);

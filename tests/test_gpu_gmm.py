@@ -14,7 +14,7 @@ of order ||y||^2 ~ 2D, so beta carries absolute errors of order 2D u and the
 weights w = exp(beta - f) relative errors of that order (6e-2 at D = 64,
 u = 2^-11), which cancel in part across the N points of each sum; measured
 gradient errors are 4-8e-3, and the bound is 1e-2. All operands are taken
-about the centre of the means (the results do not depend on the origin), so
+about a point among the means (the results do not depend on the origin), so
 the same bound holds for data far from the origin. Split-BF16 drops only the
 lo*lo terms (about 2^-16 relative); bound 2e-4.
 """
@@ -125,7 +125,7 @@ def test_data_far_from_origin(dev, offset, D, variant):
     """x and the means ~ offset + N(0, 1): the objective and its gradient depend
     only on x - mu, but 16-bit operands of x itself, or the expansion
     x^T P x - 2 (P mu)^T x + mu^T P mu, would lose everything to cancellation.
-    The kernels move the origin to the centre of the means first."""
+    The kernels first move the origin to the mean of the first 16 means."""
     tol = {0: 1e-5, 1: TOL_MIXED16, 2: TOL_BF16X3}[variant]
     g = workloads.gmm_inputs(2000, D, 7, 50 + D)
     g = workloads.GMMInputs(g.alphas, g.means + offset, g.qd, g.l, g.x + offset).astype(np.float32)
