@@ -127,7 +127,8 @@ constexpr size_t kQfWLds = 64 * 68 * 4 + 64 * 65 * 4 + (64 + 64 + 12) * 4;
 // tile is past the end only joins the barriers.
 DEX_DEV void qf_x_tile(int tix0, int ntiles, char* smem, const float* __restrict__ x, int N,
                        int Npad, _Float16* __restrict__ xhT, _Float16* __restrict__ x16,
-                       int* __restrict__ tile_exp, const float* __restrict__ shift) {
+                       int* __restrict__ tile_exp, const float* __restrict__ means, int K,
+                       float* csh) {
   // x~^T for the reverse pass, and x scaled by the tile's 2^-ex (|x| 2^-ex <
   // 2^7) in FP16, row-major, for the feature products
   const int hf = threadIdx.x >> 7, t = threadIdx.x & 127, tix = tix0 + hf;
@@ -136,14 +137,21 @@ DEX_DEV void qf_x_tile(int tix0, int ntiles, char* smem, const float* __restrict
   float* red = reinterpret_cast<float*>(smem + hf * kQfXLds + 64 * 65 * 4);
   const int p0 = tix * 64;
   float mx = 0.f;
+  // the tile's x first, then the origin (its loads overlap these)
+  float v[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const int e = t + 128 * i, p = p0 + (e >> 6);
+    v[i] = live && p < N ? x[(size_t)p * 64 + (e & 63)] : 0.f;
+  }
+  block_shift(means, K, 64, csh);
   if (live) {
     // x - c: thread t always meets coordinate t & 63
-    const float cs = shift[t & 63];
-    float v[32];
+    const float cs = csh[t & 63];
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
       const int e = t + 128 * i, p = p0 + (e >> 6);
-      v[i] = p < N ? x[(size_t)p * 64 + (e & 63)] - cs : 0.f;
+      v[i] = p < N ? v[i] - cs : 0.f;
     }
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
@@ -188,8 +196,8 @@ DEX_DEV void qf_x_tile(int tix0, int ntiles, char* smem, const float* __restrict
 DEX_DEV void qf_w_comp(int k, char* smem, const float* __restrict__ alphas,
                        const float* __restrict__ means, const float* __restrict__ qd,
                        const float* __restrict__ l, int K, _Float16* __restrict__ W16,
-                       float* __restrict__ kq, float* __restrict__ isc,
-                       const float* __restrict__ shift) {
+                       float* __restrict__ kq, float* __restrict__ isc, float* csh,
+                       float* __restrict__ keep) {
   constexpr int D = 64, L = D * (D - 1) / 2;
   // Qs: row stride 68 floats keeps 16-byte row pieces aligned for vector reads
   float(*Qs)[68] = reinterpret_cast<float(*)[68]>(smem);
@@ -229,8 +237,13 @@ DEX_DEV void qf_w_comp(int k, char* smem, const float* __restrict__ alphas,
     const float ev = expf(dv[i]);
     qv[i] = a == b ? ev : a > b ? lv[i] : 0.f;
   }
-  const float mu_t = t < D ? means[(size_t)k * D + t] - shift[t] : 0.f;
+  const float mu_raw = t < D ? means[(size_t)k * D + t] : 0.f;
   const float qd_t = t < D ? qd[(size_t)k * D + t] : 0.f;
+  // the origin, once the component's loads are in flight (block 0 keeps it for
+  // the reverse pass and forward mode)
+  block_shift(means, K, 64, csh);
+  if (keep && t < 64) keep[t] = csh[t];
+  const float mu_t = t < D ? mu_raw - csh[t] : 0.f;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int e = t + 256 * i;
@@ -503,10 +516,14 @@ __global__ void __launch_bounds__(256) k_qf_tan_prep(
     const float* __restrict__ shift, _Float16* __restrict__ dW16, float* __restrict__ dkq,
     float* __restrict__ disc) {
   __shared__ __attribute__((aligned(16))) char smem[kQfTLds > 2 * kQfXLds ? kQfTLds : 2 * kQfXLds];
+  // (the x tiles recompute the forward's origin: the same fixed-order sum of
+  // the same means, so the same bits as the stored one)
+  __shared__ float csh[64];
   if ((int)blockIdx.x < Kp)
     qf_tan_comp(blockIdx.x, smem, means, qd, l, da, dm, dq, dl, K, shift, dW16, dkq, disc);
   else
-    qf_x_tile(2 * (blockIdx.x - Kp), Npad / 64, smem, x, N, Npad, nullptr, x16, tile_exp, shift);
+    qf_x_tile(2 * (blockIdx.x - Kp), Npad / 64, smem, x, N, Npad, nullptr, x16, tile_exp, means, K,
+              csh);
 }
 
 // One launch for both parts of the preparation: blocks [0, Kp) build the
@@ -526,13 +543,15 @@ __global__ void __launch_bounds__(256) k_qf_prep(const float* __restrict__ x, in
   __shared__ __attribute__((aligned(16))) char smem[kQfWLds > 2 * kQfXLds ? kQfWLds : 2 * kQfXLds];
   // every block computes the origin itself (one launch less); block 0 keeps it
   // for the reverse pass and forward mode
+  // (each part issues its own global loads first, so their latency and that of
+  // the origin's loads overlap)
   __shared__ float csh[64];
-  block_shift(means, K, 64, csh);
-  if (blockIdx.x == 0 && threadIdx.x < 64) shift[threadIdx.x] = csh[threadIdx.x];
+  float* keep = blockIdx.x == 0 ? shift : nullptr;
   if ((int)blockIdx.x < Kp)
-    qf_w_comp(blockIdx.x, smem, alphas, means, qd, l, K, W16, kq, isc, csh);
+    qf_w_comp(blockIdx.x, smem, alphas, means, qd, l, K, W16, kq, isc, csh, keep);
   else
-    qf_x_tile(2 * (blockIdx.x - Kp), Npad / 64, smem, x, N, Npad, xhT, x16, tile_exp, csh);
+    qf_x_tile(2 * (blockIdx.x - Kp), Npad / 64, smem, x, N, Npad, xhT, x16, tile_exp, means, K,
+              csh);
 }
 
 // Sum / max over the 16 lanes of a row (DPP: quad swaps, half-row and row
@@ -577,11 +596,14 @@ DEX_DEV float row_sum16(float v) {
 // of the XCD's units. The block holds the coefficient operand of its current
 // pass in LDS (68 chunks x 2 component tiles x 64 lanes x 16 B = 136 KiB), so
 // the waves run their units with no barrier; the block meets only to load the
-// next pass. A wave computes its tile as 4 point tiles x 2 component tiles:
-// per chunk 4 feature sets (4 packed multiplies each) and 8 products.
+// next pass. A wave computes its tile as 4 point tiles x NT component tiles:
+// per chunk 4 feature sets (4 packed multiplies each) and 4 NT products. NT
+// is 2, except in a last pass with at most 16 real components (K = 200: the
+// seventh pass holds 8), which runs one component tile: half the products and
+// half the coefficient operand.
 constexpr int kQfWaves = 8;
 
-template <int CH>
+template <int CH, int NT>
 DEX_DEV void qf_chunk(const qf::h2 (&xr)[4][32], _Float16 one, const qf::h8 (&w)[2],
                       f32x4 (&acc)[4][2]) {
   // coefficients as the A operand and features as B (the A and B register
@@ -591,30 +613,31 @@ DEX_DEV void qf_chunk(const qf::h2 (&xr)[4][32], _Float16 one, const qf::h8 (&w)
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) {
     const qf::h8 z = qf::features<CH>(xr[tt], one);
-    acc[tt][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[0], z, acc[tt][0], 0, 0, 0);
-    acc[tt][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[1], z, acc[tt][1], 0, 0, 0);
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+      acc[tt][n] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[n], z, acc[tt][n], 0, 0, 0);
   }
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) {
-    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);  // a feature set (4 packed muls)
-    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // its two products
+    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);   // a feature set (4 packed muls)
+    __builtin_amdgcn_sched_group_barrier(0x008, NT, 0);  // its products
   }
 }
 
 // chunks CH.. with the operands of chunk CH + 1 read from LDS during chunk CH
-template <int... CH>
+template <int NT, int... CH>
 DEX_DEV void qf_chunks(const qf::h2 (&xr)[4][32], _Float16 one, const qf::h8 (*wsh)[2][64],
                        int lane, f32x4 (&acc)[4][2], std::integer_sequence<int, CH...>) {
   qf::h8 w[2][2];
-  w[0][0] = wsh[0][0][lane];
-  w[0][1] = wsh[0][1][lane];
+#pragma unroll
+  for (int n = 0; n < NT; ++n) w[0][n] = wsh[0][n][lane];
   (
       [&] {
         if constexpr (CH + 1 < qf::kChunks) {
-          w[(CH + 1) & 1][0] = wsh[CH + 1][0][lane];
-          w[(CH + 1) & 1][1] = wsh[CH + 1][1][lane];
+#pragma unroll
+          for (int n = 0; n < NT; ++n) w[(CH + 1) & 1][n] = wsh[CH + 1][n][lane];
         }
-        qf_chunk<CH>(xr, one, w[CH & 1], acc);
+        qf_chunk<CH, NT>(xr, one, w[CH & 1], acc);
         __builtin_amdgcn_sched_barrier(0);
       }(),
       ...);
@@ -652,119 +675,137 @@ __global__ void __launch_bounds__(64 * kQfWaves) k_gmm_fwd_qf(
   const int64_t ntiles = Npad / 64;
   const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3, Gx = gridDim.x >> 3;
   const int64_t t0 = xcd * ntiles / 8, ntx = (xcd + 1) * ntiles / 8 - t0;
-  const int64_t Tx = (int64_t)npass * ntx;
-  const int64_t ua = split_lo(lb, Tx, Gx), ub = split_lo(lb + 1, Tx, Gx);
+  // the XCD's units split over its blocks by cost: a unit of a full pass
+  // weighs 3, one of a last pass with a single component tile 2 (half the
+  // products, the same feature work)
+  const bool half_last = K - (npass - 1) * qf::kPass <= 16;
+  const int64_t wh = half_last ? 2 : 3, Wfull = 3 * (int64_t)(npass - 1) * ntx,
+                Wtot = Wfull + wh * ntx;
+  auto unit_at = [&](int64_t w) {  // the first unit that starts at weight >= w
+    return w <= Wfull ? (w + 2) / 3 : (int64_t)(npass - 1) * ntx + (w - Wfull + wh - 1) / wh;
+  };
+  const int64_t ua = unit_at(split_lo(lb, Wtot, Gx)), ub = unit_at(split_lo(lb + 1, Wtot, Gx));
   qf::h2 xr[4][32];
   f32x4 acc[4][2];
   for (int64_t cur = ua; cur < ub;) {
     const int pass = (int)(cur / ntx);
     const int64_t seg = min<int64_t>(ub, (int64_t)(pass + 1) * ntx);
-    // the pass's coefficient operand into LDS (component tiles 2 pass, 2 pass + 1)
-    // by direct loads (global_load_lds_dwordx4: a wave moves one 1 KiB (chunk,
-    // tile) piece per instruction, lane i's 16 bytes to the piece's base + 16 i),
-    // all 17 of a wave in flight together and no registers used
-    __syncthreads();
+    // the pass's units with NT component tiles
+    auto run = [&](auto ntc) {
+      constexpr int NT = decltype(ntc)::value;
+      // the pass's coefficient operand into LDS (component tiles 2 pass + n,
+      // n < NT) by direct loads (global_load_lds_dwordx4: a wave moves one
+      // 1 KiB (chunk, tile) piece per instruction, lane i's 16 bytes to the
+      // piece's base + 16 i), all of a wave's pieces in flight together and no
+      // registers used
+      constexpr int kPieces = qf::kChunks * NT;
+      __syncthreads();
 #pragma unroll
-    for (int i = 0; i < qf::kChunks * 2 / kQfWaves; ++i) {
-      const int q = kQfWaves * i + wv, ch = q >> 1, n = q & 1;
-      __builtin_amdgcn_global_load_lds(
-          W16 + ((((size_t)(2 * pass + n) * qf::kChunks + ch) * 64 + lane) * 8),
-          (__attribute__((address_space(3))) void*)&wsh[ch][n][0], 16, 0, 0);
-    }
-    static_assert(qf::kChunks * 2 % kQfWaves == 0, "whole pieces per wave");
-    __syncthreads();  // (waits for the loads: vmcnt(0))
-    // the pass's kappa' and rescale factors of the lane's eight components
-    // (16 n + 4 g + i), loaded once per pass (not after every unit's products)
-    float kqv[2][4], iscv[2][4];
-#pragma unroll
-    for (int n = 0; n < 2; ++n)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        kqv[n][i] = kq[pass * qf::kPass + 16 * n + 4 * g + i];
-        iscv[n][i] = isc[pass * qf::kPass + 16 * n + 4 * g + i];
+      for (int i = 0; i < (kPieces + kQfWaves - 1) / kQfWaves; ++i) {
+        const int q = kQfWaves * i + wv, ch = q / NT, n = q % NT;
+        if (kPieces % kQfWaves == 0 || q < kPieces)
+          __builtin_amdgcn_global_load_lds(
+              W16 + ((((size_t)(2 * pass + n) * qf::kChunks + ch) * 64 + lane) * 8),
+              (__attribute__((address_space(3))) void*)&wsh[ch][n][0], 16, 0, 0);
       }
-    for (int64_t u = cur + wv; u < seg; u += kQfWaves) {
-      const int pb = (int)(t0 + (u - (int64_t)pass * ntx)) * 64;  // the tile's first point
-      // one prep tile: one scale 2^-ex, and "one" = 2^-ex
-      const int ex = tile_exp[pb >> 6];
-      const _Float16 one = (_Float16)ldexpf(1.f, -ex);
-      qf_load_x(x16, pb, c, g, xr);
+      __syncthreads();  // (waits for the loads: vmcnt(0))
+      // the pass's kappa' and rescale factors of the lane's components
+      // (16 n + 4 g + i), loaded once per pass (not after every unit's products)
+      float kqv[NT][4], iscv[NT][4];
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt)
+      for (int n = 0; n < NT; ++n)
 #pragma unroll
-        for (int n = 0; n < 2; ++n) acc[tt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-      // the products at a higher wave priority than the loads and epilogues,
-      // so the two waves of a SIMD drift apart and one's epilogue overlaps the
-      // other's products
-      __builtin_amdgcn_s_setprio(2);
-      qf_chunks(xr, one, wsh, lane, acc, std::make_integer_sequence<int, qf::kChunks>{});
-      __builtin_amdgcn_s_setprio(0);
-      // lane (c, g) holds, for point pb + 16 tt + c, acc[tt][n][i] of
-      // component pass * 32 + 16 n + 4 g + i
-      if constexpr (TAN) {
-        // dbeta = dkq' - disc 2^(2 ex) / 2 * product, weighted by exp(beta - f)
-        float lsum = 0.f;
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-          const int p = pb + 16 * tt + c;
-          const float fv = fres[min(p, N - 1)];
-#pragma unroll
-          for (int n = 0; n < 2; ++n)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int k = pass * qf::kPass + 16 * n + 4 * g + i;  // < Kp: beta has the row
-              const float bv = beta[(size_t)k * Npad + p];
-              const float w = k < K && p < N ? __expf(bv - fv) : 0.f;
-              const float is = ldexpf(iscv[n][i], 2 * ex);
-              lsum = fmaf(w, kqv[n][i] - 0.5f * is * acc[tt][n][i], lsum);
-            }
+        for (int i = 0; i < 4; ++i) {
+          kqv[n][i] = kq[pass * qf::kPass + 16 * n + 4 * g + i];
+          iscv[n][i] = isc[pass * qf::kPass + 16 * n + 4 * g + i];
         }
-        const double ds = wave_sum((double)lsum);
-        if (lane == 0) part[(size_t)pass * ntiles + (pb >> 6)] = ds;
-        continue;
+      for (int64_t u = cur + wv; u < seg; u += kQfWaves) {
+        const int pb = (int)(t0 + (u - (int64_t)pass * ntx)) * 64;  // the tile's first point
+        // one prep tile: one scale 2^-ex, and "one" = 2^-ex
+        const int ex = tile_exp[pb >> 6];
+        const _Float16 one = (_Float16)ldexpf(1.f, -ex);
+        qf_load_x(x16, pb, c, g, xr);
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+          for (int n = 0; n < NT; ++n) acc[tt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // the products at a higher wave priority than the loads and epilogues,
+        // so the two waves of a SIMD drift apart and one's epilogue overlaps
+        // the other's products
+        __builtin_amdgcn_s_setprio(2);
+        qf_chunks<NT>(xr, one, wsh, lane, acc, std::make_integer_sequence<int, qf::kChunks>{});
+        __builtin_amdgcn_s_setprio(0);
+        // lane (c, g) holds, for point pb + 16 tt + c, acc[tt][n][i] of
+        // component pass * 32 + 16 n + 4 g + i
+        if constexpr (TAN) {
+          // dbeta = dkq' - disc 2^(2 ex) / 2 * product, weighted by exp(beta - f)
+          float lsum = 0.f;
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) {
+            const int p = pb + 16 * tt + c;
+            const float fv = fres[min(p, N - 1)];
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int k = pass * qf::kPass + 16 * n + 4 * g + i;  // < Kp: beta has the row
+                const float bv = beta[(size_t)k * Npad + p];
+                const float w = k < K && p < N ? __expf(bv - fv) : 0.f;
+                const float is = ldexpf(iscv[n][i], 2 * ex);
+                lsum = fmaf(w, kqv[n][i] - 0.5f * is * acc[tt][n][i], lsum);
+              }
+          }
+          const double ds = wave_sum((double)lsum);
+          if (lane == 0) part[(size_t)pass * ntiles + (pb >> 6)] = ds;
+          continue;
+        }
+        // epilogue: beta = kappa' - isc 2^(2 ex) / 2 * product, stored per
+        // component row; the pass's log-sum-exp of each point: the lane's 4 NT
+        // components, then the 4 lanes of the point (lanes c, c + 16, c + 32,
+        // c + 48) by two lane-pair exchanges; exp(b - M) as exp2(b log2 e -
+        // M log2 e). Passes whose components are all real skip the masks.
+        auto lse = [&](auto full_t) {
+          constexpr bool FULL = decltype(full_t)::value;
+          constexpr float kL2e = 1.4426950408889634f;
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) {
+            const int p = pb + 16 * tt + c;
+            float m = -INFINITY;
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int k = pass * qf::kPass + 16 * n + 4 * g + i;
+                const float b = kqv[n][i] - 0.5f * ldexpf(iscv[n][i], 2 * ex) * acc[tt][n][i];
+                acc[tt][n][i] = b;
+                beta[(size_t)k * Npad + p] = b;
+                if (FULL || k < K) m = fmaxf(m, b);
+              }
+            m = pair_max32(pair_max16(m));
+            const float m2 = m * kL2e;
+            float e = 0.f;
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int k = pass * qf::kPass + 16 * n + 4 * g + i;
+                const float ev = __builtin_amdgcn_exp2f(fmaf(acc[tt][n][i], kL2e, -m2));
+                e += FULL || k < K ? ev : 0.f;
+              }
+            e = pair_sum32(pair_sum16(e));
+            if (g == 0) ml[(size_t)pass * Npad + p] = make_float2(m, e);
+          }
+        };
+        if (pass * qf::kPass + 16 * NT <= K)
+          lse(std::true_type{});
+        else
+          lse(std::false_type{});
       }
-      // epilogue: beta = kappa' - isc 2^(2 ex) / 2 * product, stored per
-      // component row; the pass's log-sum-exp of each point: the lane's 8
-      // components, then the 4 lanes of the point (lanes c, c + 16, c + 32,
-      // c + 48) by two lane-pair exchanges; exp(b - M) as exp2(b log2 e -
-      // M log2 e). Passes whose 32 components are all real skip the masks.
-      auto lse = [&](auto full_t) {
-        constexpr bool FULL = decltype(full_t)::value;
-        constexpr float kL2e = 1.4426950408889634f;
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-          const int p = pb + 16 * tt + c;
-          float m = -INFINITY;
-#pragma unroll
-          for (int n = 0; n < 2; ++n)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int k = pass * qf::kPass + 16 * n + 4 * g + i;
-              const float b = kqv[n][i] - 0.5f * ldexpf(iscv[n][i], 2 * ex) * acc[tt][n][i];
-              acc[tt][n][i] = b;
-              beta[(size_t)k * Npad + p] = b;
-              if (FULL || k < K) m = fmaxf(m, b);
-            }
-          m = pair_max32(pair_max16(m));
-          const float m2 = m * kL2e;
-          float e = 0.f;
-#pragma unroll
-          for (int n = 0; n < 2; ++n)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int k = pass * qf::kPass + 16 * n + 4 * g + i;
-              const float ev = __builtin_amdgcn_exp2f(fmaf(acc[tt][n][i], kL2e, -m2));
-              e += FULL || k < K ? ev : 0.f;
-            }
-          e = pair_sum32(pair_sum16(e));
-          if (g == 0) ml[(size_t)pass * Npad + p] = make_float2(m, e);
-        }
-      };
-      if (pass * qf::kPass + qf::kPass <= K)
-        lse(std::true_type{});
-      else
-        lse(std::false_type{});
-    }
+    };
+    if (pass == npass - 1 && half_last)
+      run(std::integral_constant<int, 1>{});
+    else
+      run(std::integral_constant<int, 2>{});
     cur = seg;
   }
 }

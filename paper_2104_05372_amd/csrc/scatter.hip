@@ -305,6 +305,11 @@ __global__ void __launch_bounds__(256) scatter_int_generic(int32_t* __restrict__
   if (oob) count_oob(bad, oob);
 }
 
+// Rows a half-wave has in flight in the gathers: the index and weight loads of
+// kGU rows are issued together, then their kGU row loads, so the two dependent
+// global reads (index, then row) are paid once per kGU rows.
+constexpr int kGU = 4;
+
 // out[j, :] = w[j] * T[idx[j], :]; half a wave per row, 4 floats per lane.
 __global__ void __launch_bounds__(256) gather_scale_kernel(const float* __restrict__ T,
                                                            const int32_t* __restrict__ idx,
@@ -313,17 +318,31 @@ __global__ void __launch_bounds__(256) gather_scale_kernel(const float* __restri
                                                            float* __restrict__ out,
                                                            int64_t* oob) {
   const int half = threadIdx.x >> 5, hl = threadIdx.x & 31;
-  const int64_t rows_per_iter = (int64_t)gridDim.x * 8;
+  const int64_t stride = (int64_t)gridDim.x * 8;  // rows per round of the grid
   int bad = 0;
-  for (int64_t j = (int64_t)blockIdx.x * 8 + half; j < n; j += rows_per_iter) {
-    const int64_t v = idx[j];
-    const bool ok = v >= 0 && v < V;
-    if (!ok && hl == 0) ++bad;
-    const float s = w[j];
+  for (int64_t j0 = (int64_t)blockIdx.x * 8 + half; j0 < n; j0 += stride * kGU) {
+    int64_t v[kGU];
+    float s[kGU];
+    bool live[kGU], ok[kGU];
+#pragma unroll
+    for (int u = 0; u < kGU; ++u) {
+      const int64_t j = j0 + u * stride;
+      live[u] = j < n;
+      v[u] = live[u] ? (int64_t)idx[j] : 0;
+      s[u] = live[u] ? w[j] : 0.f;
+      ok[u] = live[u] && v[u] >= 0 && v[u] < V;
+      if (live[u] && !ok[u] && hl == 0) ++bad;
+    }
     for (int c = 4 * hl; c < R; c += 128) {
-      f32x4 t = ok ? *reinterpret_cast<const f32x4*>(T + v * R + c) : f32x4{0.f, 0.f, 0.f, 0.f};
-      const f32x4 o = t * s;
-      __builtin_nontemporal_store(o, reinterpret_cast<f32x4*>(out + j * R + c));
+      f32x4 t[kGU];
+#pragma unroll
+      for (int u = 0; u < kGU; ++u)
+        t[u] = ok[u] ? *reinterpret_cast<const f32x4*>(T + v[u] * R + c) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int u = 0; u < kGU; ++u)
+        if (live[u])
+          __builtin_nontemporal_store(t[u] * s[u],
+                                      reinterpret_cast<f32x4*>(out + (j0 + u * stride) * R + c));
     }
   }
   if (oob) count_oob(bad, oob);
@@ -332,8 +351,8 @@ __global__ void __launch_bounds__(256) gather_scale_kernel(const float* __restri
 // Forward mode of the gather (the linear map of its linearization, Sec. 5.1;
 // idx is an integer, so it carries no tangent):
 //   tout[j, :] = tw[j] * T[idx[j], :] + w[j] * tT[idx[j], :]
-// Same layout as the gather: half a wave per row, 4 floats per lane; rows with
-// an index outside [0, V) give zeros.
+// Same layout as the gather: half a wave per row, 4 floats per lane, kGU rows
+// in flight; rows with an index outside [0, V) give zeros.
 __global__ void __launch_bounds__(256) gather_jvp_kernel(const float* __restrict__ T,
                                                          const float* __restrict__ tT,
                                                          const int32_t* __restrict__ idx,
@@ -342,20 +361,37 @@ __global__ void __launch_bounds__(256) gather_jvp_kernel(const float* __restrict
                                                          int R, int64_t n,
                                                          float* __restrict__ tout) {
   const int half = threadIdx.x >> 5, hl = threadIdx.x & 31;
-  const int64_t rows_per_iter = (int64_t)gridDim.x * 8;
-  for (int64_t j = (int64_t)blockIdx.x * 8 + half; j < n; j += rows_per_iter) {
-    const int64_t v = idx[j];
-    const bool ok = v >= 0 && v < V;
-    const float a = tw[j], b = w[j];
-    for (int c = 4 * hl; c < R; c += 128) {
-      f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (ok) {
-        const f32x4 x = *reinterpret_cast<const f32x4*>(T + v * R + c);
-        const f32x4 y = *reinterpret_cast<const f32x4*>(tT + v * R + c);
+  const int64_t stride = (int64_t)gridDim.x * 8;
+  for (int64_t j0 = (int64_t)blockIdx.x * 8 + half; j0 < n; j0 += stride * kGU) {
+    int64_t v[kGU];
+    float a[kGU], b[kGU];
+    bool live[kGU], ok[kGU];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) o[e] = fmaf(b, y[e], a * x[e]);
+    for (int u = 0; u < kGU; ++u) {
+      const int64_t j = j0 + u * stride;
+      live[u] = j < n;
+      v[u] = live[u] ? (int64_t)idx[j] : 0;
+      a[u] = live[u] ? tw[j] : 0.f;
+      b[u] = live[u] ? w[j] : 0.f;
+      ok[u] = live[u] && v[u] >= 0 && v[u] < V;
+    }
+    for (int c = 4 * hl; c < R; c += 128) {
+      f32x4 x[kGU], y[kGU];
+#pragma unroll
+      for (int u = 0; u < kGU; ++u) {
+        x[u] = ok[u] ? *reinterpret_cast<const f32x4*>(T + v[u] * R + c) : f32x4{0.f, 0.f, 0.f, 0.f};
+        y[u] = ok[u] ? *reinterpret_cast<const f32x4*>(tT + v[u] * R + c) : f32x4{0.f, 0.f, 0.f, 0.f};
       }
-      __builtin_nontemporal_store(o, reinterpret_cast<f32x4*>(tout + j * R + c));
+#pragma unroll
+      for (int u = 0; u < kGU; ++u) {
+        if (!live[u]) continue;
+        f32x4 o = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (ok[u]) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) o[e] = fmaf(b[u], y[u][e], a[u] * x[u][e]);
+        }
+        __builtin_nontemporal_store(o, reinterpret_cast<f32x4*>(tout + (j0 + u * stride) * R + c));
+      }
     }
   }
 }
