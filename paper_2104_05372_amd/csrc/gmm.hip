@@ -218,26 +218,26 @@ __global__ void __launch_bounds__(256) k_mom_reduce(float* __restrict__ part, in
   const int k = (int)(i / E);
   const int64_t kg = k / gw;
   const size_t stride = (size_t)K * E;
-  // the first 4 slots of every XCD are loaded together (one round trip for
-  // the usual case), then summed in (x, rank) order; slots past 4 follow in
-  // batches of 4
+  // the first 5 slots of every XCD are loaded together (one round trip for
+  // the usual case: a group's waves on one XCD leave at most wx / groups + 2
+  // slots), then summed in (x, rank) order; slots past 5 follow in batches of 4
   int S[8];
-  float v[8][4];
+  float v[8][5];
 #pragma unroll
   for (int x = 0; x < 8; ++x) {
     S[x] = shared_counts ? Ssh[k - k0][x] : mom_slots(kg, x, nkg, nsteps, Wx);
     const float* base = part + (size_t)x * SX * stride + i;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[x][u] = u < S[x] ? base[(size_t)u * stride] : 0.f;
+    for (int u = 0; u < 5; ++u) v[x][u] = u < S[x] ? base[(size_t)u * stride] : 0.f;
   }
   float s = 0.f, err = 0.f;
 #pragma unroll
   for (int x = 0; x < 8; ++x) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 5; ++u)
       if (u < S[x]) comp_add(s, err, v[x][u]);
     const float* base = part + (size_t)x * SX * stride + i;
-    for (int sp = 4; sp < S[x]; sp += 4) {
+    for (int sp = 5; sp < S[x]; sp += 4) {
       float w[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) w[u] = sp + u < S[x] ? base[(size_t)(sp + u) * stride] : 0.f;

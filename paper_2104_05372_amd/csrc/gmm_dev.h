@@ -421,16 +421,24 @@ DEX_DEV void prep_x_tile(const float* __restrict__ x, int N, int D, int Npad, in
                          typename MomT<MomOf<PREC>::MP>::S* xhT,
                          typename MomT<MomOf<PREC>::MP>::S* xlT, float* tmax = nullptr,
                          const float* __restrict__ shift = nullptr) {
+  // (256 threads) the tile's loads are all issued before the first is used
+  constexpr int NL = 64 * DP / 256;
   __shared__ float tile[64][DP + 1];
   __shared__ float red[16];
   __syncthreads();
   float mx = 0.f;
-  for (int e = threadIdx.x; e < 64 * DP; e += blockDim.x) {
-    int pp = e / DP, b = e % DP, p = p0 + pp;
+  float v[NL];
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int e = threadIdx.x + 256 * r, pp = e / DP, b = e % DP, p = p0 + pp;
     const bool in = p < N && b < D;
-    const float v = in ? x[(size_t)p * D + b] - (shift ? shift[b] : 0.f) : 0.f;
-    tile[pp][b] = v;
-    mx = fmaxf(mx, fabsf(v));
+    v[r] = in ? x[(size_t)p * D + b] - (shift ? shift[b] : 0.f) : 0.f;
+  }
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int e = threadIdx.x + 256 * r;
+    tile[e / DP][e % DP] = v[r];
+    mx = fmaxf(mx, fabsf(v[r]));
   }
   if (tmax) {
     mx = wave_max(mx);
@@ -795,6 +803,7 @@ DEX_DEV void bwd_mom_unit_f16p(const void* xT_hi, int N, int Npad, int K, int kw
   using V8 = typename MomT<MP_F16>::V8;
   constexpr int NB = DP / 16, NBLK = NB * (NB + 1) / 2;
   constexpr int NP = (GW + 1) / 2;  // component pairs
+  constexpr int SP = 32;            // points per step
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
   const int half = lane >> 5, j = lane & 31;
   if (kw >= K) return;
@@ -815,18 +824,33 @@ DEX_DEV void bwd_mom_unit_f16p(const void* xT_hi, int N, int Npad, int K, int kw
 
   // every load is in bounds: steps past the end reload the last one, f is
   // clamped to N - 1, components past K to K - 1
+  // x~^T rows and beta by buffer loads: a wave-uniform resource and step offset
+  // (scalar registers) plus a 32-bit per-lane byte offset fixed for the whole
+  // unit, so a load needs no vector address arithmetic (the host guarantees
+  // DP * Npad * 2 < 2^32; the resources' ranges are not used for clamping)
+  const __amdgpu_buffer_rsrc_t xr_ = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<_Float16*>(xh), (short)0, -1, 0x00020000);
+  const __amdgpu_buffer_rsrc_t br_ = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(beta + (size_t)kw * Npad), (short)0, -1, 0x00020000);
+  uint32_t xoff[NB], boff[NP];
+#pragma unroll
+  for (int bb = 0; bb < NB; ++bb) xoff[bb] = (uint32_t)((16 * bb + c) * Npad + 8 * g) * 2u;
+#pragma unroll
+  for (int pp = 0; pp < NP; ++pp)
+    boff[pp] = (uint32_t)((min(kw + 2 * pp + half, K - 1) - kw) * Npad + j) * 4u;
   auto load_x = [&](int t, V8(&xt)[NB]) {
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb)
-      xt[bb] = *reinterpret_cast<const V8*>(xh + (size_t)(16 * bb + c) * Npad + t + 8 * g);
+      xt[bb] = __builtin_bit_cast(
+          V8, __builtin_amdgcn_raw_buffer_load_b128(xr_, xoff[bb], (uint32_t)t * 2u, 0));
   };
   auto load_w = [&](int t, float(&bt)[NP], float& ft) {
     const int p = t + j;
     ft = f[min(p, N - 1)];
 #pragma unroll
     for (int pp = 0; pp < NP; ++pp)
-      bt[pp] = __builtin_nontemporal_load(
-          &beta[(size_t)min(kw + 2 * pp + half, K - 1) * Npad + p]);
+      bt[pp] = __builtin_bit_cast(
+          float, __builtin_amdgcn_raw_buffer_load_b32(br_, boff[pp], (uint32_t)t * 4u, 0));
   };
   // weights of the step at t (lanes 0-31: component kw + 2pp, lanes 32-63:
   // kw + 2pp + 1, point t + j) into LDS buffer b; zero past N, K or pend
@@ -854,12 +878,12 @@ DEX_DEV void bwd_mom_unit_f16p(const void* xT_hi, int N, int Npad, int K, int kw
   };
   // step at t0 with parity b (= step index % 2): x rows xt (loaded during the
   // previous step), next step's rows into xn, beta/f slot (bs, fs) holding the
-  // step at t0 + 64, weights wc / wcc of this step, wn / wnc receive the next
+  // step at t0 + 2 SP, weights wc / wcc of this step, wn / wnc receive the next
   auto step = [&](int t0, V8(&xt)[NB], V8(&xn)[NB], float(&bs)[NP], float& fs, V8(&wq)[GW],
                   V8& wcc, V8(&wn)[GW], V8& wnc, int b) {
-    load_x(t0 + 32 < pend ? t0 + 32 : t0, xn);
-    weights(t0 + 64, bs, fs, b);
-    load_w(min(t0 + 128, pend - 32), bs, fs);
+    load_x(t0 + SP < pend ? t0 + SP : t0, xn);
+    weights(t0 + 2 * SP, bs, fs, b);
+    load_w(min(t0 + 4 * SP, pend - SP), bs, fs);
     readw(b ^ 1, wn, wnc);
 #pragma unroll
     for (int bb = 0; bb < NB; ++bb) uq[bb] = mom_mma1<MP_F16>(xt[bb], wcc, uq[bb]);
@@ -898,17 +922,17 @@ DEX_DEV void bwd_mom_unit_f16p(const void* xT_hi, int N, int Npad, int K, int kw
   // with steps 2 and 3, weights of step 0 read back
   load_x(pbeg, xA);
   load_w(pbeg, bA, fA);
-  load_w(min(pbeg + 32, pend - 32), bB, fB);
+  load_w(min(pbeg + SP, pend - SP), bB, fB);
   weights(pbeg, bA, fA, 0);
-  weights(pbeg + 32, bB, fB, 1);
-  load_w(min(pbeg + 64, pend - 32), bA, fA);
-  load_w(min(pbeg + 96, pend - 32), bB, fB);
+  weights(pbeg + SP, bB, fB, 1);
+  load_w(min(pbeg + 2 * SP, pend - SP), bA, fA);
+  load_w(min(pbeg + 3 * SP, pend - SP), bB, fB);
   wave_fence();
   readw(0, wqA, wcA);
   int t0 = pbeg;
-  for (; t0 + 32 < pend; t0 += 64) {
+  for (; t0 + SP < pend; t0 += 2 * SP) {
     step(t0, xA, xB, bA, fA, wqA, wcA, wqB, wcB, 0);
-    step(t0 + 32, xB, xA, bB, fB, wqB, wcB, wqA, wcA, 1);
+    step(t0 + SP, xB, xA, bB, fB, wqB, wcB, wqA, wcA, 1);
   }
   if (t0 < pend) step(t0, xA, xB, bA, fA, wqA, wcA, wqB, wcB, 0);
 
@@ -1205,7 +1229,9 @@ DEX_DEV void bwd_mom_unit_gen(const void* xT_hi, const void* xT_lo, int N, int N
   }
 }
 
-// The FP16 form with double-buffered rows takes the pipelined-weights unit.
+// The FP16 form with double-buffered rows takes the pipelined-weights unit
+// (whose 32-bit row offsets need DP * Npad * 2 < 2^32: the host launches the
+// form without double-buffered rows beyond that).
 template <int DP, int MP, int GW, bool DB = true>
 DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad, int K, int kw,
                           int pbeg, int pend, const float* __restrict__ beta,
@@ -1272,6 +1298,31 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
     for (int i = 0; i < 11; ++i) {
       const int e = t + 256 * i;
       pv[i] = e < NE ? part[e] : 0.f;
+    }
+  } else if (S <= 8) {
+    // up to 8 slots (the batched launch's point chunks): every load of the
+    // thread's 11 elements issued before the first sum, then the same
+    // fixed-order compensated sums
+    float v[11][8];
+#pragma unroll
+    for (int i = 0; i < 11; ++i) {
+      const int e = t + 256 * i;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[i][u] = u < S && e < NE ? part[(size_t)u * sstride + e] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < 11; ++i) {
+      float sm = 0.f, err = 0.f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (u < S) {
+          float ns, ne;
+          two_sum<float>(sm, v[i][u], ns, ne);
+          sm = ns;
+          err += ne;
+        }
+      }
+      pv[i] = sm + err;
     }
   } else {
 #pragma unroll

@@ -603,19 +603,21 @@ DEX_DEV float row_sum16(float v) {
 // half the coefficient operand.
 constexpr int kQfWaves = 8;
 
-template <int CH, int NT>
+template <int CH, int NT, bool TR>
 DEX_DEV void qf_chunk(const qf::h2 (&xr)[4][32], _Float16 one, const qf::h8 (&w)[2],
                       f32x4 (&acc)[4][2]) {
-  // coefficients as the A operand and features as B (the A and B register
+  // TR: coefficients as the A operand and features as B (the A and B register
   // layouts of this product are the same): the result is component x point, so
   // a lane holds 4 components of one point (lane (c, g): point c, components
-  // 4g .. 4g + 3 of the tile)
+  // 4g .. 4g + 3 of the tile). Otherwise point x component: lane (c, g) holds
+  // points 4g .. 4g + 3 of component c.
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) {
     const qf::h8 z = qf::features<CH>(xr[tt], one);
 #pragma unroll
     for (int n = 0; n < NT; ++n)
-      acc[tt][n] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w[n], z, acc[tt][n], 0, 0, 0);
+      acc[tt][n] = TR ? __builtin_amdgcn_mfma_f32_16x16x32_f16(w[n], z, acc[tt][n], 0, 0, 0)
+                      : __builtin_amdgcn_mfma_f32_16x16x32_f16(z, w[n], acc[tt][n], 0, 0, 0);
   }
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) {
@@ -625,7 +627,7 @@ DEX_DEV void qf_chunk(const qf::h2 (&xr)[4][32], _Float16 one, const qf::h8 (&w)
 }
 
 // chunks CH.. with the operands of chunk CH + 1 read from LDS during chunk CH
-template <int NT, int... CH>
+template <int NT, bool TR, int... CH>
 DEX_DEV void qf_chunks(const qf::h2 (&xr)[4][32], _Float16 one, const qf::h8 (*wsh)[2][64],
                        int lane, f32x4 (&acc)[4][2], std::integer_sequence<int, CH...>) {
   qf::h8 w[2][2];
@@ -637,7 +639,7 @@ DEX_DEV void qf_chunks(const qf::h2 (&xr)[4][32], _Float16 one, const qf::h8 (*w
 #pragma unroll
           for (int n = 0; n < NT; ++n) w[(CH + 1) & 1][n] = wsh[CH + 1][n][lane];
         }
-        qf_chunk<CH, NT>(xr, one, w[CH & 1], acc);
+        qf_chunk<CH, NT, TR>(xr, one, w[CH & 1], acc);
         __builtin_amdgcn_sched_barrier(0);
       }(),
       ...);
@@ -711,13 +713,15 @@ __global__ void __launch_bounds__(64 * kQfWaves) k_gmm_fwd_qf(
       __syncthreads();  // (waits for the loads: vmcnt(0))
       // the pass's kappa' and rescale factors of the lane's components
       // (16 n + 4 g + i), loaded once per pass (not after every unit's products)
+      // (forward: components 16 n + 4 g + i; forward mode: component 16 n + c)
       float kqv[NT][4], iscv[NT][4];
 #pragma unroll
       for (int n = 0; n < NT; ++n)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          kqv[n][i] = kq[pass * qf::kPass + 16 * n + 4 * g + i];
-          iscv[n][i] = isc[pass * qf::kPass + 16 * n + 4 * g + i];
+          const int kc = pass * qf::kPass + 16 * n + (TAN ? c : 4 * g + i);
+          kqv[n][i] = kq[kc];
+          iscv[n][i] = isc[kc];
         }
       for (int64_t u = cur + wv; u < seg; u += kQfWaves) {
         const int pb = (int)(t0 + (u - (int64_t)pass * ntx)) * 64;  // the tile's first point
@@ -733,32 +737,38 @@ __global__ void __launch_bounds__(64 * kQfWaves) k_gmm_fwd_qf(
         // so the two waves of a SIMD drift apart and one's epilogue overlaps
         // the other's products
         __builtin_amdgcn_s_setprio(2);
-        qf_chunks<NT>(xr, one, wsh, lane, acc, std::make_integer_sequence<int, qf::kChunks>{});
+        qf_chunks<NT, !TAN>(xr, one, wsh, lane, acc,
+                            std::make_integer_sequence<int, qf::kChunks>{});
         __builtin_amdgcn_s_setprio(0);
-        // lane (c, g) holds, for point pb + 16 tt + c, acc[tt][n][i] of
-        // component pass * 32 + 16 n + 4 g + i
         if constexpr (TAN) {
-          // dbeta = dkq' - disc 2^(2 ex) / 2 * product, weighted by exp(beta - f)
+          // lane (c, g) holds acc[tt][n][i] of point pb + 16 tt + 4 g + i and
+          // component pass * 32 + 16 n + c: dbeta = dkq' - disc 2^(2 ex) / 2 *
+          // product, weighted by exp(beta - f) (beta read 4 points at a time)
           float lsum = 0.f;
 #pragma unroll
-          for (int tt = 0; tt < 4; ++tt) {
-            const int p = pb + 16 * tt + c;
-            const float fv = fres[min(p, N - 1)];
+          for (int n = 0; n < NT; ++n) {
+            const int k = pass * qf::kPass + 16 * n + c;  // < Kp: beta has the row
+            const bool vk = k < K;
+            const float kk = kqv[n][0], is = ldexpf(iscv[n][0], 2 * ex);
 #pragma unroll
-            for (int n = 0; n < NT; ++n)
+            for (int tt = 0; tt < 4; ++tt) {
+              const int p0 = pb + 16 * tt + 4 * g;
+              const f32x4 bv = *reinterpret_cast<const f32x4*>(beta + (size_t)k * Npad + p0);
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
-                const int k = pass * qf::kPass + 16 * n + 4 * g + i;  // < Kp: beta has the row
-                const float bv = beta[(size_t)k * Npad + p];
-                const float w = k < K && p < N ? __expf(bv - fv) : 0.f;
-                const float is = ldexpf(iscv[n][i], 2 * ex);
-                lsum = fmaf(w, kqv[n][i] - 0.5f * is * acc[tt][n][i], lsum);
+                const int p = p0 + i;
+                const float fv = fres[min(p, N - 1)];
+                const float w = vk && p < N ? __expf(bv[i] - fv) : 0.f;
+                lsum = fmaf(w, kk - 0.5f * is * acc[tt][n][i], lsum);
               }
+            }
           }
           const double ds = wave_sum((double)lsum);
           if (lane == 0) part[(size_t)pass * ntiles + (pb >> 6)] = ds;
           continue;
         }
+        // lane (c, g) holds, for point pb + 16 tt + c, acc[tt][n][i] of
+        // component pass * 32 + 16 n + 4 g + i.
         // epilogue: beta = kappa' - isc 2^(2 ex) / 2 * product, stored per
         // component row; the pass's log-sum-exp of each point: the lane's 4 NT
         // components, then the 4 lanes of the point (lanes c, c + 16, c + 32,
@@ -924,7 +934,11 @@ static FlatSplit bwd_launch(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o,
 template <int DP>
 static FlatSplit bwd_dp(const GmmGeom& g, const BwdCfg& c, const MfmaOps& o, const float* beta,
                         const float* f, const float* ct, float* part, hipStream_t st) {
+  // the FP16 form with double-buffered rows addresses x~^T rows by 32-bit byte
+  // offsets (DP * Npad * 2 < 2^32); beyond that the form without runs
+  const bool wide = P == PREC_BF16 && (uint64_t)DP * (uint64_t)g.Npad * 2u >= (1ull << 32);
   if (c.gw == 4 && !c.db) return bwd_launch<DP, 4, false>(g, c, o, beta, f, ct, part, st);
+  if (wide) return bwd_launch<DP, 4, false>(g, BwdCfg{4, c.wps, 0}, o, beta, f, ct, part, st);
   if (c.gw == 4) return bwd_launch<DP, 4, true>(g, c, o, beta, f, ct, part, st);
   if (c.gw == 3) return bwd_launch<DP, 3, true>(g, c, o, beta, f, ct, part, st);
   if (c.gw == 2) return bwd_launch<DP, 2, true>(g, c, o, beta, f, ct, part, st);
