@@ -76,40 +76,135 @@ __device__ inline MfmaOps bops(const BInst& I, const char* cache) {
 
 // ---------------------------------------------------------------------------
 // D <= 8: the 16x16 matrix-core tiles would be mostly padding, so these
-// instances run on the vector units, one lane per point. Q~, -c~ and kappa are
-// read from the same operand cache (DP = 16, row-major, zero padded).
+// instances run on the vector units. Q~, -c~ and kappa come from the same
+// operand cache (DP = 16, row-major, zero padded).
+//
+// Forward. The block's npts points are split in two halves and its 256 lanes
+// in G = 512 / npts component groups: a lane takes points pi and pi + npts/2
+// for the components of its group (one group per wave). Each component's
+// triangular factor, offset and constant are staged in LDS, 64 components at a
+// time, and read back as wave-wide broadcasts; the groups' running
+// log-sum-exps are merged through LDS at the end. All 256 lanes must call it.
 template <int DV>
 DEX_DEV void fwd_unit_valu(const MfmaOps& o, int N, int Npad, int p0blk, int npts, int K,
                            float* __restrict__ beta, float2* __restrict__ ml) {
-  const int p = p0blk + (int)threadIdx.x;
-  if ((int)threadIdx.x >= npts) return;
+  constexpr int NQ = DV * (DV + 1) / 2;  // lower-triangular entries of Q~
+  constexpr int CW = 64;                 // floats per staged component
+  constexpr int KS = 64;                 // components staged at a time
+  constexpr int NT = (NQ + DV + 1 + 3) / 4;  // float4 reads per component
+  static_assert(NQ + DV + 1 <= CW, "staged component does not fit");
+  __shared__ __attribute__((aligned(16))) float tab[KS * CW];
+  __shared__ float2 mls[512];
+  (void)N;
   const float* xh = (const float*)o.xh;
   const float* Q = (const float*)o.Qh;
-  float x[DV];
+  const int tid = (int)threadIdx.x;
+  const int half = npts >> 1, G = 256 / half, JC = KS / G;
+  const int pi = tid % half, g = tid / half;
+  const int Kg = (K + G - 1) / G;
+  const int pa = p0blk + pi, pb = pa + half;
+  float xa[DV], xb[DV];
 #pragma unroll
-  for (int b = 0; b < DV; ++b) x[b] = xh[(size_t)p * 16 + b];
-  float m = -INFINITY, lsum = 0.f;
-  for (int k = 0; k < K; ++k) {
-    const float* Qk = Q + (size_t)k * 256;
-    float s = 0.f;
-#pragma unroll
-    for (int a = 0; a < DV; ++a) {
-      float y = o.negc[(size_t)k * 16 + a];
-#pragma unroll
-      for (int b = 0; b <= a; ++b) y = fmaf(Qk[a * 16 + b], x[b], y);
-      s = fmaf(y, y, s);
+  for (int b = 0; b < DV; ++b) {
+    xa[b] = xh[(size_t)pa * 16 + b];
+    xb[b] = xh[(size_t)pb * 16 + b];
+  }
+  // this lane stages entry r of components tid / CW + 4 i: its source is
+  // base[k * stride] (Q~ row entry, -c~ entry or kappa), or zero padding
+  const int r = tid % CW;
+  const float* base = nullptr;
+  int stride = 0;
+  if (r < NQ) {
+    int a = 0, e = r;
+    while (e > a) {
+      e -= a + 1;
+      ++a;
     }
-    const float bv = o.kappa[k] - 0.5f * s;
-    if (p < N) beta[(size_t)k * Npad + p] = bv;
+    base = Q + a * 16 + e;
+    stride = 256;
+  } else if (r < NQ + DV) {
+    base = o.negc + (r - NQ);
+    stride = 16;
+  } else if (r == NQ + DV) {
+    base = o.kappa;
+    stride = 1;
+  }
+  constexpr int SV = KS * CW / 256;  // staged values per lane
+  float sv[SV];
+  // the global loads of a stage are issued one stage ahead of its use
+  auto stage_load = [&](int j0) {
+#pragma unroll
+    for (int i = 0; i < SV; ++i) {
+      const int slot = tid / CW + (256 / CW) * i;
+      const int j = j0 + slot % JC, k = (slot / JC) * Kg + j;
+      sv[i] = (base && j < Kg && k < K) ? base[(size_t)k * stride] : 0.f;
+    }
+  };
+  stage_load(0);
+  float ma = -INFINITY, la = 0.f, mb = -INFINITY, lb = 0.f;
+  // running log-sum-exp: one exponential of -|bv - m| serves both cases
+  auto lse = [](float& m, float& l, float bv) {
     const float d = bv - m;
-    if (d > 0.f) {
-      lsum = lsum * __expf(-d) + 1.f;
-      m = bv;
-    } else {
-      lsum += __expf(d);
+    const float ex = __expf(-fabsf(d));
+    l = d > 0.f ? fmaf(l, ex, 1.f) : l + ex;
+    m = fmaxf(m, bv);
+  };
+  for (int j0 = 0; j0 < Kg; j0 += JC) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SV; ++i) tab[(tid / CW + (256 / CW) * i) * CW + r] = sv[i];
+    __syncthreads();
+    if (j0 + JC < Kg) stage_load(j0 + JC);
+    const int jn = std::min(JC, Kg - j0);
+    for (int jj = 0; jj < jn; ++jj) {
+      const int k = g * Kg + j0 + jj;
+      if (k >= K) break;  // the same for the whole wave
+      const float4* T4 = (const float4*)(tab + (g * JC + jj) * CW);
+      float t[4 * NT];
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        const float4 v = T4[i];
+        t[4 * i] = v.x;
+        t[4 * i + 1] = v.y;
+        t[4 * i + 2] = v.z;
+        t[4 * i + 3] = v.w;
+      }
+      float sa = 0.f, sb = 0.f;
+      int e = 0;
+#pragma unroll
+      for (int a = 0; a < DV; ++a) {
+        float ya = t[NQ + a], yb = t[NQ + a];
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+          ya = fmaf(t[e], xa[b], ya);
+          yb = fmaf(t[e], xb[b], yb);
+          ++e;
+        }
+        sa = fmaf(ya, ya, sa);
+        sb = fmaf(yb, yb, sb);
+      }
+      const float kap = t[NQ + DV];
+      const float ba = kap - 0.5f * sa, bb = kap - 0.5f * sb;
+      // padded points (N <= p < Npad) get a value too; nothing reads it
+      beta[(size_t)k * Npad + pa] = ba;
+      beta[(size_t)k * Npad + pb] = bb;
+      lse(ma, la, ba);
+      lse(mb, lb, bb);
     }
   }
-  ml[p] = make_float2(m, lsum);
+  mls[g * npts + pi] = make_float2(ma, la);
+  mls[g * npts + pi + half] = make_float2(mb, lb);
+  __syncthreads();
+  if (tid < npts) {
+    float m = -INFINITY;
+    for (int gg = 0; gg < G; ++gg) m = fmaxf(m, mls[gg * npts + tid].x);
+    float l = 0.f;
+    for (int gg = 0; gg < G; ++gg) {
+      const float2 v = mls[gg * npts + tid];
+      l += v.y * __expf(v.x - m);
+    }
+    ml[p0blk + tid] = make_float2(m, l);
+  }
 }
 
 // Reverse for D <= 8: wave wv accumulates, per component, the lane-private sums
@@ -134,18 +229,35 @@ DEX_DEV void bwd_unit_valu(const float* __restrict__ xh, int N, int Npad, int K,
     for (int a = 0; a < DV; ++a) uacc[gk][a] = 0.f;
     aacc[gk] = 0.f;
   }
-  for (int t0 = pbeg; t0 < pend; t0 += 64) {
+  // The next tile's point, log-density and weights are loaded before the
+  // current tile's products, to cover the load latency.
+  float xn[DV], fn = 0.f, bn[GW];
+  auto load = [&](int t0) {
     const int p = t0 + lane;
-    const bool valid = p < N;
-    float x[DV];
+    const bool valid = t0 < pend && p < N;
+    const int pc = valid ? p : 0;
 #pragma unroll
-    for (int b = 0; b < DV; ++b) x[b] = xh[(size_t)p * 16 + b];
-    const float fp = valid ? f[p] : 0.f;
+    for (int b = 0; b < DV; ++b) xn[b] = xh[(size_t)pc * 16 + b];
+    fn = valid ? f[pc] : 0.f;
+#pragma unroll
+    for (int gk = 0; gk < GW; ++gk)
+      bn[gk] = valid ? beta[(size_t)std::min(kw + gk, K - 1) * Npad + pc] : -INFINITY;
+  };
+  load(pbeg);
+  for (int t0 = pbeg; t0 < pend; t0 += 64) {
+    float x[DV], bt[GW];
+#pragma unroll
+    for (int b = 0; b < DV; ++b) x[b] = xn[b];
+#pragma unroll
+    for (int gk = 0; gk < GW; ++gk) bt[gk] = bn[gk];
+    const float fp = fn;
+    load(t0 + 64);
 #pragma unroll
     for (int gk = 0; gk < GW; ++gk) {
       const int k = kw + gk;
       if (k >= K) break;
-      const float w = valid ? __expf(beta[(size_t)k * Npad + p] - fp) * ctv : 0.f;
+      // beta is -inf past the last point, so w = 0 there
+      const float w = __expf(bt[gk] - fp) * ctv;
       aacc[gk] += w;
       float wx[DV];
 #pragma unroll
@@ -227,7 +339,7 @@ DEX_DEV int next_item(int* counter) {
   __syncthreads();
   if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
   __syncthreads();
-  return cur;
+  return __builtin_amdgcn_readfirstlane(cur);
 }
 
 template <int CB>
@@ -554,7 +666,9 @@ int gmm_batched_num_configs(const dex_desc& d, int role) {
   return role == DEX_WS_VJP ? kBBwdCfgs : kBFwdCfgs;
 }
 
-static int persistent_blocks() { return num_cus() * 2; }
+// Blocks of the persistent launches, per CU: the reverse kernels hide their
+// load latency with more resident blocks; the forward ones do best with two.
+static int persistent_blocks(bool reverse) { return num_cus() * (reverse ? 4 : 2); }
 
 dex_status gmm_batched_fwd(const dex_desc& d, int cfg, const void* plan, const GmmPtrs& in,
                            void* F, void* f, void* cache, void* ws, hipStream_t st) {
@@ -570,10 +684,10 @@ dex_status gmm_batched_fwd(const dex_desc& d, int cfg, const void* plan, const G
   hipLaunchKernelGGL(fill_counters, dim3(1), dim3(64), 0, st, (int*)w, 64);
   ProfRange pr(DEX_PROF_BGMM_FWD, st);
   if (bfwd_cb(cfg) == 4)
-    hipLaunchKernelGGL((k_bgmm_fwd<4>), dim3(persistent_blocks()), dim3(256), 0, st, pl, cfg,
+    hipLaunchKernelGGL((k_bgmm_fwd<4>), dim3(persistent_blocks(false)), dim3(256), 0, st, pl, cfg,
                        (const char*)cc, w);
   else
-    hipLaunchKernelGGL((k_bgmm_fwd<2>), dim3(persistent_blocks()), dim3(256), 0, st, pl, cfg,
+    hipLaunchKernelGGL((k_bgmm_fwd<2>), dim3(persistent_blocks(false)), dim3(256), 0, st, pl, cfg,
                        (const char*)cc, w);
   pr.end(1);
   hipLaunchKernelGGL(k_bmerge, dim3((unsigned)n_merge), dim3(256), 0, st, pl, (float*)f, w);
@@ -592,7 +706,7 @@ dex_status gmm_batched_vjp(const dex_desc& d, int cfg, const void* plan, const G
   const BBwd bc = bbwd_cfg(cfg);
   hipLaunchKernelGGL(fill_counters, dim3(1), dim3(64), 0, st, (int*)w, 64);
 #define DEX_BB(GW_)                                                                     \
-  hipLaunchKernelGGL((k_bgmm_bwd<GW_>), dim3(persistent_blocks()), dim3(256), 0, st, pl, \
+  hipLaunchKernelGGL((k_bgmm_bwd<GW_>), dim3(persistent_blocks(true)), dim3(256), 0, st, pl, \
                      cfg, (const char*)cache, (const float*)f, (const float*)ct, w)
   ProfRange pr(DEX_PROF_BGMM_VJP, st);
   if (bc.gw == 1)

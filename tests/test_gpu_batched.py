@@ -67,7 +67,7 @@ def check_instances(shapes, insts, got, which, ct=None):
 
 def small_batch():
     shapes = np.array([[1000, 8, 10], [1537, 16, 3], [2049, 32, 7], [256, 8, 1],
-                       [3001, 32, 12], [999, 16, 25], [4100, 8, 2]], np.int64)
+                       [3001, 32, 12], [999, 16, 25], [4100, 8, 2], [600, 8, 77]], np.int64)
     return shapes, workloads.batched_inputs(shapes, seed=30)
 
 
