@@ -332,7 +332,8 @@ dex_status dex_accum_scatter_workspace_bytes(int32_t acc_dtype, int64_t n_rows,
 
 /*
  * Host-side plan for DEX_GMM_BATCHED. `shapes` is host memory, B rows of
- * (N, D, K) int64 with D in {8, 16, 32}, N >= 1, K >= 1. Fills *desc_out and
+ * (N, D, K) int64 with 1 <= D <= 32, N >= 1, K >= 1 (D <= 8 runs on the vector
+ * units, 9..16 and 17..32 on matrix-core tiles padded to 16 and 32). Fills *desc_out and
  * writes the plan (instance table and work lists, longest work first) into
  * host memory `plan` of *plan_bytes bytes. Call with plan == NULL to query
  * *plan_bytes. The caller copies the plan to the device and passes it as in[0].

@@ -689,8 +689,8 @@ dex_status dex_gmm_batched_plan(const int64_t* shapes, int64_t B, int32_t varian
   if (variant != DEX_GMM_PLAIN) return fail(DEX_ERR_UNSUPPORTED, "batched GMM is FP32 PLAIN");
   for (int64_t b = 0; b < B; ++b) {
     const int64_t N = shapes[3 * b], D = shapes[3 * b + 1], K = shapes[3 * b + 2];
-    if (N < 1 || K < 1 || (D != 8 && D != 16 && D != 32))
-      return fail(DEX_ERR_UNSUPPORTED, "instance %lld: N>=1, K>=1, D in {8,16,32}", (long long)b);
+    if (N < 1 || K < 1 || D < 1 || D > 32)
+      return fail(DEX_ERR_UNSUPPORTED, "instance %lld: N>=1, K>=1, 1<=D<=32", (long long)b);
     if (N > (int64_t(1) << 26) || K > 4096) return fail(DEX_ERR_UNSUPPORTED, "instance too large");
   }
   const size_t need = gmm_batched_plan_bytes(B, shapes);

@@ -6,7 +6,8 @@
 // ordered longest first; the forward and reverse phases each run as one
 // persistent launch whose blocks take items from an atomic counter until the
 // list is exhausted, so the smallest instances do not pay a launch each.
-// Tiles: 16-deep contraction chunks (D in {8, 16} padded to 16, D = 32 as is).
+// Tiles: 16-deep contraction chunks (D = 9..16 padded to 16, 17..32 to 32);
+// D <= 8 runs on the vector units.
 #include <string.h>
 
 #include <algorithm>

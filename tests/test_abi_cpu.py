@@ -152,7 +152,7 @@ def test_batched_plan(dex):
 
 
 def test_batched_plan_rejects_bad_shapes(dex):
-    for bad in ([[100, 12, 5]], [[0, 8, 5]], [[100, 8, 0]]):
+    for bad in ([[100, 33, 5]], [[100, 0, 5]], [[0, 8, 5]], [[100, 8, 0]]):
         with pytest.raises(dex_error()):
             dex.dex_gmm_batched_plan(np.array(bad))
 

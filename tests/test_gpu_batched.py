@@ -78,6 +78,17 @@ def test_small_batch_all_configs(dev, fcfg, bcfg):
     check_instances(shapes, insts, got, range(len(insts)))
 
 
+@pytest.mark.parametrize("fcfg,bcfg", [(0, 0), (2, 4)])
+def test_any_dimension(dev, fcfg, bcfg):
+    """Dimensions other than 8, 16 and 32: D <= 8 on the vector units (D = 1
+    has no off-diagonal factor entries), 9..16 and 17..32 on padded tiles."""
+    shapes = np.array([[700, 1, 9], [513, 3, 20], [900, 5, 70], [1100, 7, 33], [300, 2, 1],
+                       [600, 12, 15], [800, 20, 11], [1000, 31, 6], [450, 9, 40]], np.int64)
+    insts = workloads.batched_inputs(shapes, seed=41)
+    got = run_batched(shapes, insts, fcfg, bcfg)
+    check_instances(shapes, insts, got, range(len(insts)))
+
+
 def test_per_instance_cotangents(dev):
     shapes, insts = small_batch()
     ct = np.linspace(-2, 2, len(insts)).astype(np.float32)
