@@ -365,74 +365,95 @@ def row_batched(torch, dex, workloads, dev, steps):
     import numpy as np
     shapes = workloads.batched_shapes()
     insts = workloads.batched_inputs(shapes)
-    d, plan = dex.dex_gmm_batched_plan(shapes)
     packed = [torch.tensor(a, device=dev) for a in workloads.pack_batched(insts)]
     del insts
-    tplan = torch.tensor(plan, device=dev)
     B = shapes.shape[0]
-    F = torch.empty(B, device=dev)
-    f = torch.empty(int(d.dims[1]), device=dev)
-    cache = torch.empty(int(d.dims[7]), dtype=torch.uint8, device=dev)
-    ws = dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_FWD), dev)
-    ct = torch.ones(B, device=dev)
-    grads = [torch.empty_like(p) for p in packed[:4]]
-    ins = [tplan, *packed]
-    bf = dex.dex_autotune(d, dex.DEX_WS_FWD, ins, [F], [f, cache], [], [], ws)
-    dex.dex_fwd(d, ins, [F], [f, cache], ws)
-    bb = dex.dex_autotune(d, dex.DEX_WS_VJP, ins, [], [f, cache], [ct], grads, ws)
-
-    def fwd():
-        dex.dex_fwd(d, ins, [F], [f, cache], ws)
-
-    def vjp():
-        dex.dex_vjp(d, ins, [f, cache], [ct], grads, 0, ws)
-
-    fwd()
-    vjp()
-    dex.dex_profile_reset()
-    dex.dex_profile_enable(True)
-    f_ms = timed(fwd, steps, torch.cuda.synchronize) * 1e3
-    b_ms = timed(vjp, steps, torch.cuda.synchronize) * 1e3
-    dex.dex_profile_enable(False)
     N, D, K = shapes[:, 0], shapes[:, 1], shapes[:, 2]
     tri = float(np.sum(D * (D + 1) * N * K))
     mom = float(np.sum(D * (D + 3) * N * K))
+
+    def measure(variant):
+        """Autotuned forward and reverse of the whole batch in one variant: the
+        timings, the kernel figures and the outputs of one more evaluation."""
+        d, plan = dex.dex_gmm_batched_plan(shapes, variant)
+        tplan = torch.tensor(plan, device=dev)
+        F = torch.empty(B, device=dev)
+        f = torch.empty(int(d.dims[1]), device=dev)
+        cache = torch.empty(int(d.dims[7]), dtype=torch.uint8, device=dev)
+        ws = dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_FWD), dev)
+        ct = torch.ones(B, device=dev)
+        grads = [torch.empty_like(p) for p in packed[:4]]
+        ins = [tplan, *packed]
+        bf = dex.dex_autotune(d, dex.DEX_WS_FWD, ins, [F], [f, cache], [], [], ws)
+        dex.dex_fwd(d, ins, [F], [f, cache], ws)
+        bb = dex.dex_autotune(d, dex.DEX_WS_VJP, ins, [], [f, cache], [ct], grads, ws)
+
+        def fwd():
+            dex.dex_fwd(d, ins, [F], [f, cache], ws)
+
+        def vjp():
+            dex.dex_vjp(d, ins, [f, cache], [ct], grads, 0, ws)
+
+        fwd()
+        vjp()
+        dex.dex_profile_reset()
+        dex.dex_profile_enable(True)
+        f_ms = timed(fwd, steps, torch.cuda.synchronize) * 1e3
+        b_ms = timed(vjp, steps, torch.cuda.synchronize) * 1e3
+        dex.dex_profile_enable(False)
+        r = {"fwd_ms": round(f_ms, 4), "vjp_ms": round(b_ms, 4), "bwd_fwd_ratio": round(b_ms / f_ms, 3),
+             "grad_evals_per_s": round(1e3 / (f_ms + b_ms), 2), "config": [bf, bb]}
+        for k, fl in (("BGMM_FWD", tri), ("BGMM_VJP", mom)):
+            ms, cnt = dex.dex_profile_read(k)
+            a = fl / (ms / max(cnt, 1) * 1e-3) / 1e12
+            r[k.lower()] = {"avg_ms": round(ms / max(cnt, 1), 4), "tflops": round(a, 2),
+                            "frac_fp32": round(a / PEAK["fp32"], 4)}
+        out = None
+        if CHECK["on"]:
+            fwd()
+            vjp()
+            torch.cuda.synchronize()
+            out = (F.cpu().numpy(), f.cpu().numpy(), [x.cpu().numpy() for x in grads])
+        del cache, ws, grads, tplan
+        torch.cuda.empty_cache()
+        return r, out
+
+    res, out = measure(dex.DEX_GMM_PLAIN)
     res = {"workload": "512 GMM instances, N~U[1000,50000], D in {8,16,32}, K~U[10,100], FP32",
-           "fwd_ms": round(f_ms, 4), "vjp_ms": round(b_ms, 4), "bwd_fwd_ratio": round(b_ms / f_ms, 3),
-           "grad_evals_per_s": round(1e3 / (f_ms + b_ms), 2), "config": [bf, bb],
-           "algorithmic_tflop": round((tri + mom) / 1e12, 4)}
-    for k, fl in (("BGMM_FWD", tri), ("BGMM_VJP", mom)):
-        ms, cnt = dex.dex_profile_read(k)
-        a = fl / (ms / max(cnt, 1) * 1e-3) / 1e12
-        res[k.lower()] = {"avg_ms": round(ms / max(cnt, 1), 4), "tflops": round(a, 2),
-                          "frac_fp32": round(a / PEAK["fp32"], 4)}
+           **res, "algorithmic_tflop": round((tri + mom) / 1e12, 4)}
+    # the split-FP16 form of the same batch (instances with D > 8 take hi + lo
+    # FP16 operands, scaled into range; FP32-class results)
+    res_s, out_s = measure(dex.DEX_GMM_F16X3)
+    for k in ("bgmm_fwd", "bgmm_vjp"):
+        a = res_s[k]["tflops"]
+        res_s[k]["frac_fp16_over_3"] = round(a / (PEAK["bf16"] / 3), 4)
+    res["split_fp16"] = res_s
     if not CHECK["on"]:
         return res
     # a sample of instances against the FP64 oracle (the largest, the smallest
     # and two others), and the oracle's time on them scaled by algorithmic cost
     from oracle import gmm as ogmm
-    fwd()
-    vjp()
-    torch.cuda.synchronize()
-    Fg, fg, gg = F.cpu().numpy(), f.cpu().numpy(), [x.cpu().numpy() for x in grads]
     cost = N * K * D * D
     pick = sorted({int(np.argmax(cost)), int(np.argmin(cost)), 0, B // 2})
     offs = {name: np.concatenate([[0], np.cumsum(v)]) for name, v in
             (("N", N), ("K", K), ("KD", K * D), ("KL", K * D * (D - 1) // 2))}
-    errs, t_cpu = [], 0.0
+    errs, errs_s, t_cpu = [], [], 0.0
+    sl = lambda key, i: slice(offs[key][i], offs[key][i + 1])
     for b in pick:
         gi = workloads.gmm_inputs(int(N[b]), int(D[b]), int(K[b]), workloads.BATCHED["seed"] + 1 + b,
                                   np.float32)
         (Fo, fo), t1 = cpu_timed(lambda: ogmm.objective(*gi.params(), gi.x))
         go, t2 = cpu_timed(lambda: ogmm.vjp(*gi.params(), gi.x, fo))
         t_cpu += t1 + t2
-        sl = lambda key, i: slice(offs[key][i], offs[key][i + 1])
-        blk = [gg[0][sl("K", b)], gg[1][sl("KD", b)], gg[2][sl("KD", b)], gg[3][sl("KL", b)]]
-        errs.append(max([abs(Fg[b] - Fo) / abs(Fo), rel_l2(fg[sl("N", b)], fo)] +
-                        [rel_l2(a, o) for a, o in zip(blk, go) if o.size]))
+        for (Fg, fg, gg), e in ((out, errs), (out_s, errs_s)):
+            blk = [gg[0][sl("K", b)], gg[1][sl("KD", b)], gg[2][sl("KD", b)], gg[3][sl("KL", b)]]
+            e.append(max([abs(Fg[b] - Fo) / abs(Fo), rel_l2(fg[sl("N", b)], fo)] +
+                         [rel_l2(a, o) for a, o in zip(blk, go) if o.size]))
     scale = float(cost.sum() / cost[pick].sum())
     res["rel_l2_vs_fp64_oracle"] = {"max_over_sampled_instances": float(f"{max(errs):.3e}"),
                                     "instances": pick}
+    res["split_fp16"]["rel_l2_vs_fp64_oracle"] = {
+        "max_over_sampled_instances": float(f"{max(errs_s):.3e}"), "instances": pick}
     res["cpu_oracle"] = {"ms_per_grad_eval": round(t_cpu * scale * 1e3, 1), "cores": blas_threads(),
                          "sample": f"FP64 oracle on instances {pick} ({t_cpu:.2f} s), scaled by "
                                    f"the batch's N K D^2 over theirs ({scale:.1f}x)"}

@@ -77,6 +77,14 @@ typedef int32_t dex_status;
                             enters) but keeps the 16-bit values small for data far
                             from the origin.                                      */
 #define DEX_GMM_BF16X3 2 /* split-BF16 operands, hi*hi + hi*lo + lo*hi per product   */
+#define DEX_GMM_F16X3  3 /* DEX_GMM_BATCHED only: the forward of instances with D > 8
+                            takes split-FP16 operands (hi + lo, 22 significant bits;
+                            hi*hi + hi*lo + lo*hi per product, FP32 accumulation) of
+                            x - c and Q_k, c the mean of the instance's first
+                            min(K, 16) means, each scaled by a power of two so its
+                            largest entry lies in [2^13, 2^14); the reverse keeps
+                            FP32 moments. FP32-class results (about 1e-6 relative).
+                            D <= 8 instances run as in PLAIN.                     */
 
 /* stencil variants */
 #define DEX_STENCIL_RECOMPUTE 0 /* reverse pass recomputes each checkpoint segment */
@@ -149,7 +157,7 @@ typedef struct dex_buf {
  *   (Sec. 6.1.3), done as per-block partial sums and a fixed-order compensated
  *   final sum (so the result does not depend on scheduling).
  *
- * DEX_GMM_BATCHED (dims from dex_gmm_batched_plan; FP32, variant PLAIN):
+ * DEX_GMM_BATCHED (dims from dex_gmm_batched_plan; FP32, variant PLAIN or F16X3):
  *   in     = plan[bytes, DEX_U8, device copy of the plan], alphas, means, qd, l, x
  *            (instances concatenated in order; instance b's arrays have the
  *            DEX_GMM sizes of its (N_b, D_b, K_b))
@@ -333,7 +341,9 @@ dex_status dex_accum_scatter_workspace_bytes(int32_t acc_dtype, int64_t n_rows,
 /*
  * Host-side plan for DEX_GMM_BATCHED. `shapes` is host memory, B rows of
  * (N, D, K) int64 with 1 <= D <= 32, N >= 1, K >= 1 (D <= 8 runs on the vector
- * units, 9..16 and 17..32 on matrix-core tiles padded to 16 and 32). Fills *desc_out and
+ * units, 9..16 and 17..32 on matrix-core tiles padded to 16 and 32); variant
+ * DEX_GMM_PLAIN or DEX_GMM_F16X3 (fixed in the plan and the descriptor; the
+ * operand cache of F16X3 holds the split parts). Fills *desc_out and
  * writes the plan (instance table and work lists, longest work first) into
  * host memory `plan` of *plan_bytes bytes. Call with plan == NULL to query
  * *plan_bytes. The caller copies the plan to the device and passes it as in[0].

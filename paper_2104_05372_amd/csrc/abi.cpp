@@ -686,14 +686,15 @@ dex_status dex_gmm_batched_plan(const int64_t* shapes, int64_t B, int32_t varian
                                 dex_desc* desc_out, void* plan, size_t* plan_bytes) {
   if (!shapes || B < 1 || !plan_bytes || !desc_out)
     return fail(DEX_ERR_INVALID_ARG, "batched plan: null argument or B < 1");
-  if (variant != DEX_GMM_PLAIN) return fail(DEX_ERR_UNSUPPORTED, "batched GMM is FP32 PLAIN");
+  if (variant != DEX_GMM_PLAIN && variant != DEX_GMM_F16X3)
+    return fail(DEX_ERR_UNSUPPORTED, "batched GMM: variant PLAIN or F16X3");
   for (int64_t b = 0; b < B; ++b) {
     const int64_t N = shapes[3 * b], D = shapes[3 * b + 1], K = shapes[3 * b + 2];
     if (N < 1 || K < 1 || D < 1 || D > 32)
       return fail(DEX_ERR_UNSUPPORTED, "instance %lld: N>=1, K>=1, 1<=D<=32", (long long)b);
     if (N > (int64_t(1) << 26) || K > 4096) return fail(DEX_ERR_UNSUPPORTED, "instance too large");
   }
-  const size_t need = gmm_batched_plan_bytes(B, shapes);
+  const size_t need = gmm_batched_plan_bytes(B, shapes, variant);
   if (!plan) {
     *plan_bytes = need;
     return gmm_batched_plan(shapes, B, variant, desc_out, nullptr, need);

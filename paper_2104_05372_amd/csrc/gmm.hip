@@ -564,6 +564,7 @@ bool valid_shape(const Shape& s) {
   if (g.N < 1 || g.D < 1 || g.K < 1 || g.D > 64) return false;
   if (s.dtype != DEX_F32 && s.dtype != DEX_F64) return false;
   if (s.variant != DEX_GMM_PLAIN && s.dtype != DEX_F32) return false;
+  if (s.variant > DEX_GMM_BF16X3) return false;  // the split-FP16 form is batched only
   return true;
 }
 

@@ -28,7 +28,9 @@ struct BInst {
   int64_t fpart_off;  // ws float pairs
   int64_t part_off;   // ws floats
   int32_t nblk;       // Npad / 256
-  int32_t pad0;
+  int32_t split;      // forward operands in split FP16 (variant DEX_GMM_F16X3, D > 8)
+  int64_t xl_off, xlT_off, Ql_off;  // cache (bytes): the split form's low parts (xlT unused)
+  int64_t sh_off;     // cache (bytes): origin shift[DP], then x and Q scales
 };
 
 struct BItem {
@@ -65,11 +67,11 @@ __device__ inline const PlanHeader* hdr(const char* plan) { return (const PlanHe
 __device__ inline MfmaOps bops(const BInst& I, const char* cache) {
   MfmaOps o;
   o.xh = cache + I.xh_off;
-  o.xl = nullptr;
+  o.xl = I.split ? cache + I.xl_off : nullptr;
   o.xhT = cache + I.xhT_off;
   o.xlT = nullptr;
   o.Qh = cache + I.Q_off;
-  o.Ql = nullptr;
+  o.Ql = I.split ? cache + I.Ql_off : nullptr;
   o.negc = (const float*)(cache + I.negc_off);
   o.kappa = (const float*)(cache + I.kappa_off);
   return o;
@@ -298,17 +300,90 @@ DEX_DEV void bwd_unit_valu(const float* __restrict__ xh, int N, int Npad, int K,
   }
 }
 
+// One block per instance: the origin shift, the mean of the first min(K, 16)
+// means (every operand is taken about it, so data far from the origin loses
+// nothing to cancellation: only x - mu enters). Split instances also get the
+// powers of two that bring max |x - shift| and the largest factor entry to
+// [2^13, 2^14), so hi and lo parts stay normal FP16 numbers for all but the
+// smallest entries (whose absolute error is then below 2^-24 of the largest);
+// the other instances get scales of 1.
+__global__ void __launch_bounds__(256) k_bscale(const char* __restrict__ plan,
+                                                const float* __restrict__ x,
+                                                const float* __restrict__ means,
+                                                const float* __restrict__ qd,
+                                                const float* __restrict__ l, char* cache) {
+  const PlanHeader* h = hdr(plan);
+  const BInst I = ((const BInst*)(plan + h->inst_off))[blockIdx.x];
+  __shared__ float csh[64];
+  __shared__ float red[2][4];
+  block_shift(means + I.m_off, I.K, I.D, csh);
+  const int t = threadIdx.x;
+  float* sh = (float*)(cache + I.sh_off);
+  if (t < I.DP) sh[t] = csh[t];
+  if (!I.split) {
+    if (t == 0) sh[I.DP] = sh[I.DP + 1] = 1.f;
+    return;
+  }
+  // max |x - shift| over the instance, one point (row of D) per thread at a time
+  const float* xi = x + I.x_off;
+  float mx = 0.f;
+  for (int p = t; p < I.N; p += 256) {
+    const float* row = xi + (size_t)p * I.D;
+#pragma unroll 4
+    for (int b = 0; b < I.D; ++b) mx = fmaxf(mx, fabsf(row[b] - csh[b]));
+  }
+  // the largest factor entry: exp(qd) on the diagonal, |l| below it
+  float mq = 0.f;
+  const int64_t nd = (int64_t)I.K * I.D, nl = (int64_t)I.K * I.D * (I.D - 1) / 2;
+  for (int64_t e = t; e < nd; e += 256) mq = fmaxf(mq, expf(qd[I.m_off + e]));
+  for (int64_t e = t; e < nl; e += 256) mq = fmaxf(mq, fabsf(l[I.l_off + e]));
+  mx = wave_max(mx);
+  mq = wave_max(mq);
+  if ((t & 63) == 0) {
+    red[0][t >> 6] = mx;
+    red[1][t >> 6] = mq;
+  }
+  __syncthreads();
+  if (t == 0) {
+    mx = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
+    mq = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
+    int ex = 0, eq = 0;
+    if (mx > 0.f && mx <= 3.0e38f) (void)frexpf(mx, &ex);
+    if (mq > 0.f && mq <= 3.0e38f) (void)frexpf(mq, &eq);
+    sh[I.DP] = ldexpf(1.f, 14 - ex);      // x scale: max |x - shift| * scale in [2^13, 2^14)
+    sh[I.DP + 1] = ldexpf(1.f, 14 - eq);  // factor scale
+  }
+}
+
 __global__ void __launch_bounds__(256) k_bprep_x(const char* __restrict__ plan,
                                                  const float* __restrict__ x, char* cache) {
   const PlanHeader* h = hdr(plan);
   const BItem w = ((const BItem*)(plan + h->prepx_off))[blockIdx.x];
   const BInst I = ((const BInst*)(plan + h->inst_off))[w.inst];
+  if (I.split) {
+    // forward rows in split FP16, the reverse's x~^T in FP32 (same scaled values)
+    using H = Store<PREC_F16X3>::S;
+    const float* sh = (const float*)(cache + I.sh_off);
+    H* xh = (H*)(cache + I.xh_off);
+    H* xl = (H*)(cache + I.xl_off);
+    float* xhT = (float*)(cache + I.xhT_off);
+    if (I.DP == 16)
+      prep_x_tile<PREC_F16X3, 16>(x + I.x_off, I.N, I.D, (int)I.Npad, w.a * 64, xh, xl, xhT, nullptr,
+                                  nullptr, sh, sh[I.DP]);
+    else
+      prep_x_tile<PREC_F16X3, 32>(x + I.x_off, I.N, I.D, (int)I.Npad, w.a * 64, xh, xl, xhT, nullptr,
+                                  nullptr, sh, sh[I.DP]);
+    return;
+  }
+  const float* sh = (const float*)(cache + I.sh_off);
   float* xh = (float*)(cache + I.xh_off);
   float* xhT = (float*)(cache + I.xhT_off);
   if (I.DP == 16)
-    prep_x_tile<PREC_F32, 16>(x + I.x_off, I.N, I.D, (int)I.Npad, w.a * 64, xh, nullptr, xhT, nullptr);
+    prep_x_tile<PREC_F32, 16>(x + I.x_off, I.N, I.D, (int)I.Npad, w.a * 64, xh, nullptr, xhT, nullptr,
+                              nullptr, sh);
   else
-    prep_x_tile<PREC_F32, 32>(x + I.x_off, I.N, I.D, (int)I.Npad, w.a * 64, xh, nullptr, xhT, nullptr);
+    prep_x_tile<PREC_F32, 32>(x + I.x_off, I.N, I.D, (int)I.Npad, w.a * 64, xh, nullptr, xhT, nullptr,
+                              nullptr, sh);
 }
 
 __global__ void __launch_bounds__(256) k_bprep_q(const char* __restrict__ plan,
@@ -319,15 +394,29 @@ __global__ void __launch_bounds__(256) k_bprep_q(const char* __restrict__ plan,
   const PlanHeader* h = hdr(plan);
   const BItem w = ((const BItem*)(plan + h->prepq_off))[blockIdx.x];
   const BInst I = ((const BInst*)(plan + h->inst_off))[w.inst];
-  float* Q = (float*)(cache + I.Q_off);
   float* negc = (float*)(cache + I.negc_off);
   float* kappa = (float*)(cache + I.kappa_off);
+  if (I.split) {
+    using H = Store<PREC_F16X3>::S;
+    const float* sh = (const float*)(cache + I.sh_off);
+    H* Qh = (H*)(cache + I.Q_off);
+    H* Ql = (H*)(cache + I.Ql_off);
+    if (I.DP == 16)
+      prep_q_comp<PREC_F16X3, 16>(alphas + I.a_off, means + I.m_off, qd + I.m_off, l + I.l_off, I.D,
+                                  w.a, Qh, Ql, negc, kappa, sh, sh[I.DP + 1], sh[I.DP]);
+    else
+      prep_q_comp<PREC_F16X3, 32>(alphas + I.a_off, means + I.m_off, qd + I.m_off, l + I.l_off, I.D,
+                                  w.a, Qh, Ql, negc, kappa, sh, sh[I.DP + 1], sh[I.DP]);
+    return;
+  }
+  float* Q = (float*)(cache + I.Q_off);
+  const float* sh = (const float*)(cache + I.sh_off);
   if (I.DP == 16)
     prep_q_comp<PREC_F32, 16>(alphas + I.a_off, means + I.m_off, qd + I.m_off, l + I.l_off, I.D, w.a,
-                              Q, nullptr, negc, kappa);
+                              Q, nullptr, negc, kappa, sh);
   else
     prep_q_comp<PREC_F32, 32>(alphas + I.a_off, means + I.m_off, qd + I.m_off, l + I.l_off, I.D, w.a,
-                              Q, nullptr, negc, kappa);
+                              Q, nullptr, negc, kappa, sh);
 }
 
 __global__ void fill_counters(int* c, int n) {
@@ -343,7 +432,8 @@ DEX_DEV int next_item(int* counter) {
   return __builtin_amdgcn_readfirstlane(cur);
 }
 
-template <int CB>
+// SPLIT: the plan's instances with D > 8 carry split FP16 operands.
+template <int CB, bool SPLIT>
 __global__ void __launch_bounds__(256) k_bgmm_fwd(const char* __restrict__ plan, int cfg,
                                                   const char* cache, char* ws) {
   const PlanHeader* h = hdr(plan);
@@ -359,9 +449,20 @@ __global__ void __launch_bounds__(256) k_bgmm_fwd(const char* __restrict__ plan,
     const BInst I = inst[w.inst];
     const MfmaOps o = bops(I, cache);
     float* beta = (float*)(cache + I.beta_off);
-    if (I.D <= 8)
+    if (I.D <= 8) {
       fwd_unit_valu<8>(o, I.N, (int)I.Npad, w.a * 64 * CB, 64 * CB, I.K, beta, ml + I.ml_off);
-    else if (I.DP == 16)
+    } else if constexpr (SPLIT) {
+      const float* sh = (const float*)(cache + I.sh_off);
+      const float sc = sh[I.DP] * sh[I.DP + 1], sfac = 1.f / (sc * sc);
+      if (I.DP == 16)
+        fwd_unit<16, PREC_F16X3, CB, 16>(o, I.N, (int)I.Npad,
+                                         w.a * 64 * CB + (threadIdx.x >> 6) * 16 * CB, 0, I.K, beta,
+                                         ml + I.ml_off, sfac);
+      else
+        fwd_unit<32, PREC_F16X3, CB, 16>(o, I.N, (int)I.Npad,
+                                         w.a * 64 * CB + (threadIdx.x >> 6) * 16 * CB, 0, I.K, beta,
+                                         ml + I.ml_off, sfac);
+    } else if (I.DP == 16)
       fwd_unit<16, PREC_F32, CB, 16>(o, I.N, (int)I.Npad, w.a * 64 * CB + (threadIdx.x >> 6) * 16 * CB,
                                      0, I.K, beta, ml + I.ml_off);
     else
@@ -394,7 +495,7 @@ __global__ void __launch_bounds__(256) k_bfinalize_F(const char* __restrict__ pl
   finalize_F_block<float>(fpart, I.nblk, alphas + I.a_off, I.K, I.N, F + blockIdx.x);
 }
 
-template <int GW>
+template <int GW, bool SPLIT>
 __global__ void __launch_bounds__(256) k_bgmm_bwd(const char* __restrict__ plan, int cfg,
                                                   const char* cache, const float* __restrict__ f,
                                                   const float* __restrict__ ct, char* ws) {
@@ -415,10 +516,21 @@ __global__ void __launch_bounds__(256) k_bgmm_bwd(const char* __restrict__ plan,
     const int pend = (int)std::min<int64_t>(I.Npad, pbeg + chunk);
     const size_t E = mom_slot(I.DP);
     float* P = part + I.part_off + (size_t)w.b * I.K * E;
-    if (I.D <= 8)
+    if (I.D <= 8) {
       bwd_unit_valu<8, GW>((const float*)(cache + I.xh_off), I.N, (int)I.Npad, I.K, w.a * 4 * GW,
                            pbeg, pend, beta, f + I.f_off, ct[w.inst], P, E);
-    else if (I.DP == 16)
+    } else if constexpr (SPLIT) {
+      // FP32 moments of the scaled x - shift; the cotangent and the scales
+      // are applied in the assembly
+      if (I.DP == 16)
+        bwd_mom_unit<16, MP_F32, GW>(cache + I.xhT_off, nullptr, I.N, (int)I.Npad, I.K,
+                                     w.a * 4 * GW + (threadIdx.x >> 6) * GW, pbeg, pend, beta,
+                                     f + I.f_off, 1.f, P, E);
+      else
+        bwd_mom_unit<32, MP_F32, GW>(cache + I.xhT_off, nullptr, I.N, (int)I.Npad, I.K,
+                                     w.a * 4 * GW + (threadIdx.x >> 6) * GW, pbeg, pend, beta,
+                                     f + I.f_off, 1.f, P, E);
+    } else if (I.DP == 16)
       bwd_mom_unit<16, MP_F32, GW>(cache + I.xhT_off, nullptr, I.N, (int)I.Npad, I.K,
                                    w.a * 4 * GW + (threadIdx.x >> 6) * GW,
                                    pbeg, pend, beta, f + I.f_off, ct[w.inst], P, E);
@@ -430,7 +542,8 @@ __global__ void __launch_bounds__(256) k_bgmm_bwd(const char* __restrict__ plan,
 }
 
 __global__ void __launch_bounds__(256) k_bbwd_finalize(const char* __restrict__ plan, int cfg,
-                                                       const char* ws, const float* __restrict__ alphas,
+                                                       const char* ws, const char* cache,
+                                                       const float* __restrict__ alphas,
                                                        const float* __restrict__ qd,
                                                        const float* __restrict__ l,
                                                        const float* __restrict__ means,
@@ -445,9 +558,20 @@ __global__ void __launch_bounds__(256) k_bbwd_finalize(const char* __restrict__ 
   const int nch = ((const int32_t*)(plan + h->nch_off))[cfg * h->B + w.inst];
   const size_t E = mom_slot(I.DP);
   const float* part = (const float*)(ws + h->ws_part) + I.part_off + (size_t)w.a * E;
+  if (I.split) {
+    // moments of x - shift scaled by xs, without the cotangent
+    const float* sh = (const float*)(cache + I.sh_off);
+    const float c = ct[w.inst], ixs = 1.f / sh[I.DP];
+    bwd_finalize_mom(part, (size_t)I.K * E, nch, w.a, I.K, I.D, I.DP, I.N, alphas + I.a_off,
+                     means + I.m_off, qd + I.m_off, l + I.l_off, c, d_alphas + I.a_off,
+                     d_means + I.m_off, d_qd + I.m_off, d_l + I.l_off, accumulate, sh,
+                     c * ixs * ixs, c * ixs, c);
+    return;
+  }
   bwd_finalize_mom(part, (size_t)I.K * E, nch, w.a, I.K, I.D, I.DP, I.N, alphas + I.a_off,
                    means + I.m_off, qd + I.m_off, l + I.l_off, ct[w.inst], d_alphas + I.a_off,
-                   d_means + I.m_off, d_qd + I.m_off, d_l + I.l_off, accumulate);
+                   d_means + I.m_off, d_qd + I.m_off, d_l + I.l_off, accumulate,
+                   (const float*)(cache + I.sh_off));
 }
 
 }  // namespace dexk
@@ -469,7 +593,7 @@ struct PlanBuild {
 
 int64_t dp_cost(int DP) { return DP == 16 ? 1 : 3; }  // 16-deep chunks per 16 points per k
 
-PlanBuild build_plan(const int64_t* shapes, int64_t B) {
+PlanBuild build_plan(const int64_t* shapes, int64_t B, int32_t variant) {
   PlanBuild p;
   p.h.B = B;
   p.inst.resize(B);
@@ -497,9 +621,16 @@ PlanBuild build_plan(const int64_t* shapes, int64_t B) {
     lo += (int64_t)I.K * I.D * (I.D - 1) / 2;
     xo += (int64_t)I.N * I.D;
     fo += I.N;
-    I.xh_off = take(I.Npad * I.DP * 4);
+    I.split = variant == DEX_GMM_F16X3 && I.D > 8;
+    const int64_t es = I.split ? 2 : 4;  // forward operand element bytes
+    I.xh_off = take(I.Npad * I.DP * es);
     I.xhT_off = take(I.Npad * I.DP * 4);
-    I.Q_off = take((int64_t)I.K * I.DP * I.DP * 4);
+    I.Q_off = take((int64_t)I.K * I.DP * I.DP * es);
+    if (I.split) {
+      I.xl_off = take(I.Npad * I.DP * es);
+      I.Ql_off = take((int64_t)I.K * I.DP * I.DP * es);
+    }
+    I.sh_off = take((int64_t)(I.DP + 2) * 4);
     I.negc_off = take((int64_t)I.K * I.DP * 4);
     I.kappa_off = take((int64_t)I.K * 4);
     I.beta_off = take((int64_t)I.K * I.Npad * 4);
@@ -602,8 +733,8 @@ struct HostPlan {
 
 }  // namespace
 
-size_t gmm_batched_plan_bytes(int64_t B, const int64_t* shapes) {
-  return build_plan(shapes, B).bytes;
+size_t gmm_batched_plan_bytes(int64_t B, const int64_t* shapes, int32_t variant) {
+  return build_plan(shapes, B, variant).bytes;
 }
 
 // Descriptor dims: {B, sum N, sum K, sum K*D, sum K*L, sum N*D, plan bytes, cache bytes}.
@@ -612,7 +743,7 @@ size_t gmm_batched_plan_bytes(int64_t B, const int64_t* shapes) {
 // fparams (exact integers below 2^53).
 dex_status gmm_batched_plan(const int64_t* shapes, int64_t B, int32_t variant, dex_desc* d,
                             void* plan, size_t plan_bytes) {
-  PlanBuild p = build_plan(shapes, B);
+  PlanBuild p = build_plan(shapes, B, variant);
   int64_t sumN = 0, sumK = 0, sumKD = 0, sumKL = 0, sumND = 0;
   for (int64_t b = 0; b < B; ++b) {
     const int64_t N = shapes[3 * b], D = shapes[3 * b + 1], K = shapes[3 * b + 2];
@@ -679,17 +810,29 @@ dex_status gmm_batched_fwd(const dex_desc& d, int cfg, const void* plan, const G
   const char* pl = (const char*)plan;
   char* cc = (char*)cache;
   char* w = (char*)ws;
+  const bool split = d.variant == DEX_GMM_F16X3;
+  hipLaunchKernelGGL(k_bscale, dim3((unsigned)B), dim3(256), 0, st, pl, (const float*)in.x,
+                     (const float*)in.means, (const float*)in.qd, (const float*)in.l, cc);
   hipLaunchKernelGGL(k_bprep_x, dim3((unsigned)n_prepx), dim3(256), 0, st, pl, (const float*)in.x, cc);
   hipLaunchKernelGGL(k_bprep_q, dim3((unsigned)sumK), dim3(256), 0, st, pl, (const float*)in.alphas,
                      (const float*)in.means, (const float*)in.qd, (const float*)in.l, cc);
   hipLaunchKernelGGL(fill_counters, dim3(1), dim3(64), 0, st, (int*)w, 64);
   ProfRange pr(DEX_PROF_BGMM_FWD, st);
-  if (bfwd_cb(cfg) == 4)
-    hipLaunchKernelGGL((k_bgmm_fwd<4>), dim3(persistent_blocks(false)), dim3(256), 0, st, pl, cfg,
-                       (const char*)cc, w);
-  else
-    hipLaunchKernelGGL((k_bgmm_fwd<2>), dim3(persistent_blocks(false)), dim3(256), 0, st, pl, cfg,
-                       (const char*)cc, w);
+#define DEX_BF(CB_, S_)                                                                    \
+  hipLaunchKernelGGL((k_bgmm_fwd<CB_, S_>), dim3(persistent_blocks(false)), dim3(256), 0, st, pl, \
+                     cfg, (const char*)cc, w)
+  if (bfwd_cb(cfg) == 4) {
+    if (split)
+      DEX_BF(4, true);
+    else
+      DEX_BF(4, false);
+  } else {
+    if (split)
+      DEX_BF(2, true);
+    else
+      DEX_BF(2, false);
+  }
+#undef DEX_BF
   pr.end(1);
   hipLaunchKernelGGL(k_bmerge, dim3((unsigned)n_merge), dim3(256), 0, st, pl, (float*)f, w);
   hipLaunchKernelGGL(k_bfinalize_F, dim3((unsigned)B), dim3(256), 0, st, pl, (const float*)in.alphas,
@@ -706,9 +849,16 @@ dex_status gmm_batched_vjp(const dex_desc& d, int cfg, const void* plan, const G
   char* w = (char*)ws;
   const BBwd bc = bbwd_cfg(cfg);
   hipLaunchKernelGGL(fill_counters, dim3(1), dim3(64), 0, st, (int*)w, 64);
-#define DEX_BB(GW_)                                                                     \
-  hipLaunchKernelGGL((k_bgmm_bwd<GW_>), dim3(persistent_blocks(true)), dim3(256), 0, st, pl, \
-                     cfg, (const char*)cache, (const float*)f, (const float*)ct, w)
+  const bool split = d.variant == DEX_GMM_F16X3;
+#define DEX_BB(GW_)                                                                          \
+  do {                                                                                       \
+    if (split)                                                                               \
+      hipLaunchKernelGGL((k_bgmm_bwd<GW_, true>), dim3(persistent_blocks(true)), dim3(256), 0, \
+                         st, pl, cfg, (const char*)cache, (const float*)f, (const float*)ct, w); \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_bgmm_bwd<GW_, false>), dim3(persistent_blocks(true)), dim3(256), 0, \
+                         st, pl, cfg, (const char*)cache, (const float*)f, (const float*)ct, w); \
+  } while (0)
   ProfRange pr(DEX_PROF_BGMM_VJP, st);
   if (bc.gw == 1)
     DEX_BB(1);
@@ -719,7 +869,7 @@ dex_status gmm_batched_vjp(const dex_desc& d, int cfg, const void* plan, const G
 #undef DEX_BB
   pr.end(1);
   hipLaunchKernelGGL(k_bbwd_finalize, dim3((unsigned)sumK), dim3(256), 0, st, pl, cfg,
-                     (const char*)w, (const float*)in.alphas, (const float*)in.qd,
+                     (const char*)w, (const char*)cache, (const float*)in.alphas, (const float*)in.qd,
                      (const float*)in.l, (const float*)in.means, (const float*)ct,
                      (float*)out.d_alphas,
                      (float*)out.d_means, (float*)out.d_qd, (float*)out.d_l, accumulate ? 1 : 0);

@@ -37,7 +37,10 @@
 
 namespace dexk {
 
-enum { PREC_F32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2 };
+// PREC_F16X3: split FP16 operands (hi + lo, 22 significant bits) of values
+// the caller has brought into the FP16 range by powers of two.
+enum { PREC_F32 = 0, PREC_BF16 = 1, PREC_BF16X3 = 2, PREC_F16X3 = 3 };
+constexpr bool prec_split(int PREC) { return PREC == PREC_BF16X3 || PREC == PREC_F16X3; }
 
 template <int PREC>
 struct Store {
@@ -46,6 +49,10 @@ struct Store {
 template <>
 struct Store<PREC_F32> {
   using S = float;
+};
+template <>
+struct Store<PREC_F16X3> {
+  using S = _Float16;
 };
 
 template <int PREC, int NV>
@@ -62,11 +69,15 @@ template <int NV>
 struct VecT<PREC_BF16X3, NV> {
   typedef __attribute__((__vector_size__(NV * sizeof(__bf16)))) __bf16 V;
 };
+template <int NV>
+struct VecT<PREC_F16X3, NV> {
+  typedef __attribute__((__vector_size__(NV * sizeof(_Float16)))) _Float16 V;
+};
 
 // One lane's NV contraction values (hi [, lo]).
 template <int PREC, int NV>
 struct Op {
-  static constexpr int NS = PREC == PREC_BF16X3 ? 2 : 1;
+  static constexpr int NS = prec_split(PREC) ? 2 : 1;
   typename VecT<PREC, NV>::V v[NS];
 };
 
@@ -77,6 +88,12 @@ DEX_DEV f32x4 mma_chunk(const typename VecT<PREC, NV>::V& a, const typename VecT
     // NV steps of 16x16x4; step j takes element j of every lane
 #pragma unroll
     for (int j = 0; j < NV; ++j) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], c, 0, 0, 0);
+  } else if constexpr (PREC == PREC_F16X3) {
+    static_assert(NV == 4 || NV == 8, "FP16 operands hold 4 or 8 values per lane");
+    if constexpr (NV == 8)
+      c = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    else
+      c = __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
   } else if constexpr (NV == 8) {
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   } else {
@@ -90,7 +107,7 @@ DEX_DEV f32x4 mma_chunk(const typename VecT<PREC, NV>::V& a, const typename VecT
 
 template <int PREC, int NV>
 DEX_DEV f32x4 mma(const Op<PREC, NV>& a, const Op<PREC, NV>& b, f32x4 c) {
-  if constexpr (PREC == PREC_BF16X3) {
+  if constexpr (prec_split(PREC)) {
     c = mma_chunk<PREC, NV>(a.v[1], b.v[0], c);  // small cross terms first
     c = mma_chunk<PREC, NV>(a.v[0], b.v[1], c);
     c = mma_chunk<PREC, NV>(a.v[0], b.v[0], c);
@@ -139,9 +156,10 @@ DEX_DEV Op<PREC, 8> to_op(const float (&v)[8]) {
     if constexpr (PREC == PREC_F32) {
       o.v[0][e] = v[e];
     } else {
-      __bf16 h = (__bf16)v[e];
+      using H = typename Store<PREC>::S;
+      H h = (H)v[e];
       o.v[0][e] = h;
-      if constexpr (PREC == PREC_BF16X3) o.v[1][e] = (__bf16)(v[e] - (float)h);
+      if constexpr (prec_split(PREC)) o.v[1][e] = (H)(v[e] - (float)h);
     }
   }
   return o;
@@ -153,9 +171,10 @@ DEX_DEV void store_split(typename Store<PREC>::S* hi, typename Store<PREC>::S* l
   if constexpr (PREC == PREC_F32) {
     hi[off] = v;
   } else {
-    __bf16 h = (__bf16)v;
+    using H = typename Store<PREC>::S;
+    H h = (H)v;
     hi[off] = h;
-    if constexpr (PREC == PREC_BF16X3) lo[off] = (__bf16)(v - (float)h);
+    if constexpr (prec_split(PREC)) lo[off] = (H)(v - (float)h);
   }
 }
 
@@ -165,9 +184,10 @@ DEX_DEV float rounded(float v) {
   if constexpr (PREC == PREC_F32) {
     return v;
   } else {
-    __bf16 h = (__bf16)v;
+    using H = typename Store<PREC>::S;
+    H h = (H)v;
     float r = (float)h;
-    if constexpr (PREC == PREC_BF16X3) r += (float)(__bf16)(v - r);
+    if constexpr (prec_split(PREC)) r += (float)(H)(v - r);
     return r;
   }
 }
@@ -181,14 +201,16 @@ DEX_DEV void store8_split(typename Store<PREC>::S* hi, typename Store<PREC>::S* 
     *reinterpret_cast<f32x4*>(hi + off) = f32x4{v[0], v[1], v[2], v[3]};
     *reinterpret_cast<f32x4*>(hi + off + 4) = f32x4{v[4], v[5], v[6], v[7]};
   } else {
-    bf16x8 h, l;
+    using H = typename Store<PREC>::S;
+    typedef __attribute__((__vector_size__(8 * sizeof(H)))) H H8;
+    H8 h, l;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      h[i] = (__bf16)v[i];
-      if constexpr (PREC == PREC_BF16X3) l[i] = (__bf16)(v[i] - (float)h[i]);
+      h[i] = (H)v[i];
+      if constexpr (prec_split(PREC)) l[i] = (H)(v[i] - (float)h[i]);
     }
-    *reinterpret_cast<bf16x8*>(hi + off) = h;
-    if constexpr (PREC == PREC_BF16X3) *reinterpret_cast<bf16x8*>(lo + off) = l;
+    *reinterpret_cast<H8*>(hi + off) = h;
+    if constexpr (prec_split(PREC)) *reinterpret_cast<H8*>(lo + off) = l;
   }
 }
 
@@ -279,7 +301,9 @@ DEX_DEV void treduce_groups(float (&v)[NV]) {
 enum { MP_F32 = 0, MP_F16 = 1, MP_F16X3 = 2 };
 template <int PREC>
 struct MomOf {
-  static constexpr int MP = PREC == PREC_F32 ? MP_F32 : PREC == PREC_BF16 ? MP_F16 : MP_F16X3;
+  // (the split-FP16 forward form keeps FP32 moments in the reverse)
+  static constexpr int MP =
+      PREC == PREC_F32 || PREC == PREC_F16X3 ? MP_F32 : PREC == PREC_BF16 ? MP_F16 : MP_F16X3;
 };
 template <int MP>
 struct MomT {
@@ -414,13 +438,14 @@ DEX_DEV void block_shift(const float* __restrict__ means, int K, int D, float* c
 // largest |x| of the tile (for the scaling of the feature-product forward).
 // shift != nullptr: every coordinate of a real point has shift[b] subtracted
 // (the origin moved among the means, so 16-bit operands carry
-// x - c, not x; every quadratic form in x - mu is unchanged).
+// x - c, not x; every quadratic form in x - mu is unchanged). The result is
+// then multiplied by `scale` (a power of two for the split-FP16 form).
 template <int PREC, int DP>
 DEX_DEV void prep_x_tile(const float* __restrict__ x, int N, int D, int Npad, int p0,
                          typename Store<PREC>::S* xh, typename Store<PREC>::S* xl,
                          typename MomT<MomOf<PREC>::MP>::S* xhT,
                          typename MomT<MomOf<PREC>::MP>::S* xlT, float* tmax = nullptr,
-                         const float* __restrict__ shift = nullptr) {
+                         const float* __restrict__ shift = nullptr, float scale = 1.f) {
   // (256 threads) the tile's loads are all issued before the first is used
   constexpr int NL = 64 * DP / 256;
   __shared__ float tile[64][DP + 1];
@@ -432,7 +457,7 @@ DEX_DEV void prep_x_tile(const float* __restrict__ x, int N, int D, int Npad, in
   for (int r = 0; r < NL; ++r) {
     const int e = threadIdx.x + 256 * r, pp = e / DP, b = e % DP, p = p0 + pp;
     const bool in = p < N && b < D;
-    v[r] = in ? x[(size_t)p * D + b] - (shift ? shift[b] : 0.f) : 0.f;
+    v[r] = in ? (x[(size_t)p * D + b] - (shift ? shift[b] : 0.f)) * scale : 0.f;
   }
 #pragma unroll
   for (int r = 0; r < NL; ++r) {
@@ -474,19 +499,22 @@ DEX_DEV void prep_x_tile(const float* __restrict__ x, int N, int D, int Npad, in
 
 // Q~_k (dense DP x DP, zero above the diagonal and in the padding), -c~_k and
 // kappa_k for one component k (means shifted by shift[] when it is given, as
-// the points are in prep_x_tile).
+// the points are in prep_x_tile). Scaled form: Q~ is multiplied by qscale and
+// the shifted mean by xscale, so -c~ carries qscale * xscale; kappa is not
+// scaled.
 template <int PREC, int DP>
 DEX_DEV void prep_q_comp(const float* __restrict__ alphas, const float* __restrict__ means,
                          const float* __restrict__ qd, const float* __restrict__ l, int D, int k,
                          typename Store<PREC>::S* Qh, typename Store<PREC>::S* Ql, float* negc,
-                         float* kappa, const float* __restrict__ shift = nullptr) {
+                         float* kappa, const float* __restrict__ shift = nullptr,
+                         float qscale = 1.f, float xscale = 1.f) {
   __shared__ float qs[DP][DP + 1];
   __shared__ float mus[DP], qds[DP];
   const int L = D * (D - 1) / 2;
   __syncthreads();
   if (threadIdx.x < DP) {
     const int a = threadIdx.x;
-    mus[a] = a < D ? means[(size_t)k * D + a] - (shift ? shift[a] : 0.f) : 0.f;
+    mus[a] = a < D ? (means[(size_t)k * D + a] - (shift ? shift[a] : 0.f)) * xscale : 0.f;
     qds[a] = a < D ? qd[(size_t)k * D + a] : 0.f;
   }
   __syncthreads();
@@ -499,7 +527,7 @@ DEX_DEV void prep_q_comp(const float* __restrict__ alphas, const float* __restri
       else if (a > b)
         q = l[(size_t)k * L + a * (a - 1) / 2 + b];
     }
-    qs[a][b] = q;
+    qs[a][b] = q * qscale;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < DP * DP / 8; e += blockDim.x) {
@@ -529,10 +557,11 @@ DEX_DEV void prep_q_comp(const float* __restrict__ alphas, const float* __restri
 // The wave builds Y^T (DP x 16*CB) = Q~_k X~^T - c~ from 16x16 tiles (row
 // block rb of Q, column block cb of points). A point's squared norm reduces
 // across the 4 lane groups, after which each lane owns one point and keeps its
-// running log-sum-exp over the k-range.
+// running log-sum-exp over the k-range. With scaled operands the squared norm
+// is multiplied by sfac (the inverse square of the operands' scale product).
 template <int DP, int PREC, int CB, int CK>
 DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0, int k0, int k1,
-                      float* __restrict__ beta, float2* __restrict__ ml) {
+                      float* __restrict__ beta, float2* __restrict__ ml, float sfac = 1.f) {
   using S = typename Store<PREC>::S;
   constexpr int NV = CK / 4;
   constexpr int NRB = DP / 16, NCH = DP / CK;
@@ -616,7 +645,7 @@ DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0, int k0, int k
       s[cb] = t;
     }
     treduce_groups<CB>(s);
-    const float b = kp - 0.5f * s[0];
+    const float b = kp - 0.5f * (s[0] * sfac);
     // every lane stores: lanes that share a point hold bit-identical totals,
     // and the padded points (p < Npad) have finite residuals nobody reads.
     // No branch here keeps the operand prefetch of the next component alive.
@@ -1247,14 +1276,18 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
 // Final step of the moment form for component k: fixed-order compensated sums
 // over the S partial slots, C_k, then M_k = Q_k C_k and the gradient assembly
 // (FP32 Q_k from qd and l). shift: the origin the moments were taken about
-// (nullptr: zero), subtracted from the means here as from the points.
+// (nullptr: zero), subtracted from the means here as from the points. The
+// summed second moments, first moments and weight sum are multiplied by m2, m1
+// and m0 (the undoing of a scaled form's operand scales and a cotangent left
+// out of its weights).
 DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, int S, int k, int K,
                               int D, int DP, int64_t N, const float* __restrict__ alphas,
                               const float* __restrict__ means, const float* __restrict__ qd,
                               const float* __restrict__ l, float ctv, float* __restrict__ d_alphas,
                               float* __restrict__ d_means, float* __restrict__ d_qd,
                               float* __restrict__ d_l, int accumulate,
-                              const float* __restrict__ shift = nullptr) {
+                              const float* __restrict__ shift = nullptr, float m2 = 1.f,
+                              float m1 = 1.f, float m0 = 1.f) {
   // Called with 256 threads. C is symmetric; QT holds Q transposed (row
   // stride 68 floats keeps 16-byte rows aligned for vector reads).
   __shared__ __attribute__((aligned(16))) float C[64][65];
@@ -1376,6 +1409,7 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
 #pragma unroll
   for (int i = 0; i < 11; ++i) {
     const int e = t + 256 * i;
+    pv[i] *= e < NBLK * 256 ? m2 : e < NBLK * 256 + DP ? m1 : m0;
     if (e < NE) Ps[e] = pv[i];
   }
   // QT and C: rows and columns past D stay zero

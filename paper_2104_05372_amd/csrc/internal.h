@@ -53,7 +53,7 @@ dex_status gmm_vjp(const dex_desc& d, int cfg, const GmmPtrs& in, const void* f,
                    void* ws, hipStream_t s);
 
 // ------------------------------------------------------- batched GMM -----
-size_t gmm_batched_plan_bytes(int64_t B, const int64_t* shapes);
+size_t gmm_batched_plan_bytes(int64_t B, const int64_t* shapes, int32_t variant);
 dex_status gmm_batched_plan(const int64_t* shapes, int64_t B, int32_t variant, dex_desc* d,
                             void* plan, size_t plan_bytes);
 size_t gmm_batched_ws_bytes(const dex_desc& d, int role);

@@ -28,7 +28,7 @@ DEX_F64, DEX_F32, DEX_I32, DEX_U32, DEX_I64, DEX_U8 = 1, 2, 3, 4, 5, 6
 # kinds
 DEX_GMM, DEX_GMM_BATCHED, DEX_GATHER_SCALE, DEX_STENCIL5 = 1, 2, 3, 4
 # variants
-DEX_GMM_PLAIN, DEX_GMM_BF16, DEX_GMM_BF16X3 = 0, 1, 2
+DEX_GMM_PLAIN, DEX_GMM_BF16, DEX_GMM_BF16X3, DEX_GMM_F16X3 = 0, 1, 2, 3
 DEX_STENCIL_RECOMPUTE, DEX_STENCIL_LINEAR = 0, 1
 # flags
 DEX_ACCUMULATE, DEX_CHECK_BOUNDS, DEX_SYNC_CHECK, DEX_NO_DW, DEX_DETERMINISTIC = 1, 2, 4, 8, 16

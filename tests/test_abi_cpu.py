@@ -140,21 +140,34 @@ def test_batched_plan(dex):
     assert hdr[0] == B
     inst_off = hdr[1]
     rec = np.dtype([("N", "<i4"), ("D", "<i4"), ("K", "<i4"), ("DP", "<i4"), ("Npad", "<i8"),
-                    ("offs", "<i8", (14,)), ("nblk", "<i4"), ("pad", "<i4")])
+                    ("offs", "<i8", (14,)), ("nblk", "<i4"), ("split", "<i4"),
+                    ("offs2", "<i8", (4,))])
     inst = plan[inst_off: inst_off + B * rec.itemsize].view(rec)
     assert np.array_equal(inst["N"], N) and np.array_equal(inst["D"], D) and np.array_equal(inst["K"], K)
     assert np.all(inst["Npad"] % 256 == 0) and np.all(inst["Npad"] >= N)
     # packed input offsets are prefix sums in instance order
     assert np.array_equal(inst["offs"][:, 0], np.concatenate([[0], np.cumsum(K)[:-1]]))
     assert np.array_equal(inst["offs"][:, 3], np.concatenate([[0], np.cumsum(N * D)[:-1]]))
+    assert np.all(inst["split"] == 0)
     ws = dex.dex_workspace_bytes(d, dex.DEX_WS_FWD)
     assert ws > 0 and dex.dex_workspace_bytes(d, dex.DEX_WS_RESID) == d.dims[7]
+    # the split-FP16 variant: D > 8 instances flagged, their operands in 2-byte
+    # hi and lo parts (plus the shift and scales)
+    d2, plan2 = dex.dex_gmm_batched_plan(shapes, dex.DEX_GMM_F16X3)
+    assert d2.variant == dex.DEX_GMM_F16X3 and list(d2.dims[:6]) == list(d.dims[:6])
+    inst2 = plan2[inst_off: inst_off + B * rec.itemsize].view(rec)
+    assert np.array_equal(inst2["split"], (D > 8).astype(np.int32))
+    lows = inst2["offs2"][:, [0, 2]]  # xl, Ql; the shift block (offs2[3]) is everyone's
+    assert np.all(lows[D > 8] > 0) and np.all(lows[D <= 8] == 0) and np.all(inst2["offs2"][:, 3] > 0)
 
 
 def test_batched_plan_rejects_bad_shapes(dex):
     for bad in ([[100, 33, 5]], [[100, 0, 5]], [[0, 8, 5]], [[100, 8, 0]]):
         with pytest.raises(dex_error()):
             dex.dex_gmm_batched_plan(np.array(bad))
+    for variant in (dex.DEX_GMM_BF16, dex.DEX_GMM_BF16X3, 7):
+        with pytest.raises(dex_error()):
+            dex.dex_gmm_batched_plan(np.array([[100, 16, 5]]), variant)
 
 
 def test_package_has_no_oracle_dependency():
