@@ -29,8 +29,8 @@ struct BInst {
   int64_t part_off;   // ws floats
   int32_t nblk;       // Npad / 256
   int32_t split;      // forward operands in split FP16 (variant DEX_GMM_F16X3, D > 8)
-  int64_t xl_off, xlT_off, Ql_off;  // cache (bytes): the split form's low parts (xlT unused)
-  int64_t sh_off;     // cache (bytes): origin shift[DP], then x and Q scales
+  int64_t xl_off, ts_off, Ql_off;  // cache (bytes): split form: low parts, per-tile x scales
+  int64_t sh_off;     // cache (bytes): origin shift[DP], then the factor scale
 };
 
 struct BItem {
@@ -303,55 +303,89 @@ DEX_DEV void bwd_unit_valu(const float* __restrict__ xh, int N, int Npad, int K,
 // One block per instance: the origin shift, the mean of the first min(K, 16)
 // means (every operand is taken about it, so data far from the origin loses
 // nothing to cancellation: only x - mu enters). Split instances also get the
-// powers of two that bring max |x - shift| and the largest factor entry to
-// [2^13, 2^14), so hi and lo parts stay normal FP16 numbers for all but the
-// smallest entries (whose absolute error is then below 2^-24 of the largest);
-// the other instances get scales of 1.
+// power of two that brings the largest factor entry (exp(qd) or |l|) to
+// [2^13, 2^14); the points are scaled per 64-point tile in the preparation.
 __global__ void __launch_bounds__(256) k_bscale(const char* __restrict__ plan,
-                                                const float* __restrict__ x,
                                                 const float* __restrict__ means,
                                                 const float* __restrict__ qd,
                                                 const float* __restrict__ l, char* cache) {
   const PlanHeader* h = hdr(plan);
   const BInst I = ((const BInst*)(plan + h->inst_off))[blockIdx.x];
   __shared__ float csh[64];
-  __shared__ float red[2][4];
+  __shared__ float red[4];
   block_shift(means + I.m_off, I.K, I.D, csh);
   const int t = threadIdx.x;
   float* sh = (float*)(cache + I.sh_off);
   if (t < I.DP) sh[t] = csh[t];
   if (!I.split) {
-    if (t == 0) sh[I.DP] = sh[I.DP + 1] = 1.f;
+    if (t == 0) sh[I.DP] = 1.f;
     return;
   }
-  // max |x - shift| over the instance, one point (row of D) per thread at a time
-  const float* xi = x + I.x_off;
-  float mx = 0.f;
-  for (int p = t; p < I.N; p += 256) {
-    const float* row = xi + (size_t)p * I.D;
-#pragma unroll 4
-    for (int b = 0; b < I.D; ++b) mx = fmaxf(mx, fabsf(row[b] - csh[b]));
-  }
-  // the largest factor entry: exp(qd) on the diagonal, |l| below it
   float mq = 0.f;
   const int64_t nd = (int64_t)I.K * I.D, nl = (int64_t)I.K * I.D * (I.D - 1) / 2;
   for (int64_t e = t; e < nd; e += 256) mq = fmaxf(mq, expf(qd[I.m_off + e]));
   for (int64_t e = t; e < nl; e += 256) mq = fmaxf(mq, fabsf(l[I.l_off + e]));
-  mx = wave_max(mx);
   mq = wave_max(mq);
-  if ((t & 63) == 0) {
-    red[0][t >> 6] = mx;
-    red[1][t >> 6] = mq;
-  }
+  if ((t & 63) == 0) red[t >> 6] = mq;
   __syncthreads();
   if (t == 0) {
-    mx = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
-    mq = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
-    int ex = 0, eq = 0;
-    if (mx > 0.f && mx <= 3.0e38f) (void)frexpf(mx, &ex);
+    mq = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    int eq = 0;
     if (mq > 0.f && mq <= 3.0e38f) (void)frexpf(mq, &eq);
-    sh[I.DP] = ldexpf(1.f, 14 - ex);      // x scale: max |x - shift| * scale in [2^13, 2^14)
-    sh[I.DP + 1] = ldexpf(1.f, 14 - eq);  // factor scale
+    sh[I.DP] = ldexpf(1.f, 14 - eq);
+  }
+}
+
+// Split form, one 64-point tile: x - shift in FP32 for the reverse (x~^T, as in
+// the FP32 form) and, scaled by the power of two that brings the tile's largest
+// |x - shift| to [2^13, 2^14), in split FP16 for the forward (row layout); the
+// tile's scale goes to ts[p0 / 64]. (256 threads; the loads are all issued
+// before the first is used.)
+template <int DP>
+DEX_DEV void prep_x_tile_split(const float* __restrict__ x, int N, int D, int Npad, int p0,
+                               const float* __restrict__ shift, _Float16* xh, _Float16* xl,
+                               float* xhT, float* ts) {
+  constexpr int NL = 64 * DP / 256;
+  __shared__ float tile[64][DP + 1];
+  __shared__ float red[4];
+  __syncthreads();
+  float v[NL], mx = 0.f;
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int e = threadIdx.x + 256 * r, pp = e / DP, b = e % DP, p = p0 + pp;
+    v[r] = p < N && b < D ? x[(size_t)p * D + b] - shift[b] : 0.f;
+  }
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int e = threadIdx.x + 256 * r;
+    tile[e / DP][e % DP] = v[r];
+    mx = fmaxf(mx, fabsf(v[r]));
+  }
+  mx = wave_max(mx);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  int ex = 0;
+  if (mx > 0.f && mx <= 3.0e38f) (void)frexpf(mx, &ex);
+  const float sc = ldexpf(1.f, 14 - ex);
+  if (threadIdx.x == 0) ts[p0 / 64] = sc;
+  for (int e = threadIdx.x; e < 8 * DP; e += blockDim.x) {
+    const int pp = e / (DP / 8), b0 = 8 * (e % (DP / 8));
+    float w[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[i] = tile[pp][b0 + i] * sc;
+    store8_split<PREC_F16X3>(xh, xl, (size_t)(p0 + pp) * DP + b0, w);
+  }
+  // x~^T in the matrix-core step order of the moment products (as prep_x_tile)
+  for (int e = threadIdx.x; e < 8 * DP; e += blockDim.x) {
+    const int b = e / 8, s0 = 8 * (e % 8);
+    float w[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int sp = s0 + i, st = sp & 32, q = sp & 31;
+      w[i] = tile[st + 4 * (q >> 3) + (q & 3) + 16 * ((q >> 2) & 1)][b];
+    }
+    mom_store8<MP_F32>(xhT, nullptr, (size_t)b * Npad + p0 + s0, w);
   }
 }
 
@@ -361,18 +395,15 @@ __global__ void __launch_bounds__(256) k_bprep_x(const char* __restrict__ plan,
   const BItem w = ((const BItem*)(plan + h->prepx_off))[blockIdx.x];
   const BInst I = ((const BInst*)(plan + h->inst_off))[w.inst];
   if (I.split) {
-    // forward rows in split FP16, the reverse's x~^T in FP32 (same scaled values)
-    using H = Store<PREC_F16X3>::S;
     const float* sh = (const float*)(cache + I.sh_off);
-    H* xh = (H*)(cache + I.xh_off);
-    H* xl = (H*)(cache + I.xl_off);
+    _Float16* xh = (_Float16*)(cache + I.xh_off);
+    _Float16* xl = (_Float16*)(cache + I.xl_off);
     float* xhT = (float*)(cache + I.xhT_off);
+    float* ts = (float*)(cache + I.ts_off);
     if (I.DP == 16)
-      prep_x_tile<PREC_F16X3, 16>(x + I.x_off, I.N, I.D, (int)I.Npad, w.a * 64, xh, xl, xhT, nullptr,
-                                  nullptr, sh, sh[I.DP]);
+      prep_x_tile_split<16>(x + I.x_off, I.N, I.D, (int)I.Npad, w.a * 64, sh, xh, xl, xhT, ts);
     else
-      prep_x_tile<PREC_F16X3, 32>(x + I.x_off, I.N, I.D, (int)I.Npad, w.a * 64, xh, xl, xhT, nullptr,
-                                  nullptr, sh, sh[I.DP]);
+      prep_x_tile_split<32>(x + I.x_off, I.N, I.D, (int)I.Npad, w.a * 64, sh, xh, xl, xhT, ts);
     return;
   }
   const float* sh = (const float*)(cache + I.sh_off);
@@ -403,10 +434,10 @@ __global__ void __launch_bounds__(256) k_bprep_q(const char* __restrict__ plan,
     H* Ql = (H*)(cache + I.Ql_off);
     if (I.DP == 16)
       prep_q_comp<PREC_F16X3, 16>(alphas + I.a_off, means + I.m_off, qd + I.m_off, l + I.l_off, I.D,
-                                  w.a, Qh, Ql, negc, kappa, sh, sh[I.DP + 1], sh[I.DP]);
+                                  w.a, Qh, Ql, negc, kappa, sh, sh[I.DP]);
     else
       prep_q_comp<PREC_F16X3, 32>(alphas + I.a_off, means + I.m_off, qd + I.m_off, l + I.l_off, I.D,
-                                  w.a, Qh, Ql, negc, kappa, sh, sh[I.DP + 1], sh[I.DP]);
+                                  w.a, Qh, Ql, negc, kappa, sh, sh[I.DP]);
     return;
   }
   float* Q = (float*)(cache + I.Q_off);
@@ -452,16 +483,16 @@ __global__ void __launch_bounds__(256) k_bgmm_fwd(const char* __restrict__ plan,
     if (I.D <= 8) {
       fwd_unit_valu<8>(o, I.N, (int)I.Npad, w.a * 64 * CB, 64 * CB, I.K, beta, ml + I.ml_off);
     } else if constexpr (SPLIT) {
-      const float* sh = (const float*)(cache + I.sh_off);
-      const float sc = sh[I.DP] * sh[I.DP + 1], sfac = 1.f / (sc * sc);
+      // the wave's points lie in one 64-point tile, whose x scale applies
+      const int p0 = w.a * 64 * CB + (threadIdx.x >> 6) * 16 * CB;
+      const float xs = ((const float*)(cache + I.ts_off))[p0 / 64];
+      const float sc = xs * ((const float*)(cache + I.sh_off))[I.DP], sfac = 1.f / (sc * sc);
       if (I.DP == 16)
-        fwd_unit<16, PREC_F16X3, CB, 16>(o, I.N, (int)I.Npad,
-                                         w.a * 64 * CB + (threadIdx.x >> 6) * 16 * CB, 0, I.K, beta,
-                                         ml + I.ml_off, sfac);
+        fwd_unit<16, PREC_F16X3, CB, 16>(o, I.N, (int)I.Npad, p0, 0, I.K, beta, ml + I.ml_off, sfac,
+                                         xs);
       else
-        fwd_unit<32, PREC_F16X3, CB, 16>(o, I.N, (int)I.Npad,
-                                         w.a * 64 * CB + (threadIdx.x >> 6) * 16 * CB, 0, I.K, beta,
-                                         ml + I.ml_off, sfac);
+        fwd_unit<32, PREC_F16X3, CB, 16>(o, I.N, (int)I.Npad, p0, 0, I.K, beta, ml + I.ml_off, sfac,
+                                         xs);
     } else if (I.DP == 16)
       fwd_unit<16, PREC_F32, CB, 16>(o, I.N, (int)I.Npad, w.a * 64 * CB + (threadIdx.x >> 6) * 16 * CB,
                                      0, I.K, beta, ml + I.ml_off);
@@ -520,8 +551,7 @@ __global__ void __launch_bounds__(256) k_bgmm_bwd(const char* __restrict__ plan,
       bwd_unit_valu<8, GW>((const float*)(cache + I.xh_off), I.N, (int)I.Npad, I.K, w.a * 4 * GW,
                            pbeg, pend, beta, f + I.f_off, ct[w.inst], P, E);
     } else if constexpr (SPLIT) {
-      // FP32 moments of the scaled x - shift; the cotangent and the scales
-      // are applied in the assembly
+      // FP32 moments of x - shift; the cotangent is applied in the assembly
       if (I.DP == 16)
         bwd_mom_unit<16, MP_F32, GW>(cache + I.xhT_off, nullptr, I.N, (int)I.Npad, I.K,
                                      w.a * 4 * GW + (threadIdx.x >> 6) * GW, pbeg, pend, beta,
@@ -559,13 +589,12 @@ __global__ void __launch_bounds__(256) k_bbwd_finalize(const char* __restrict__ 
   const size_t E = mom_slot(I.DP);
   const float* part = (const float*)(ws + h->ws_part) + I.part_off + (size_t)w.a * E;
   if (I.split) {
-    // moments of x - shift scaled by xs, without the cotangent
+    // moments of x - shift without the cotangent
     const float* sh = (const float*)(cache + I.sh_off);
-    const float c = ct[w.inst], ixs = 1.f / sh[I.DP];
+    const float c = ct[w.inst];
     bwd_finalize_mom(part, (size_t)I.K * E, nch, w.a, I.K, I.D, I.DP, I.N, alphas + I.a_off,
                      means + I.m_off, qd + I.m_off, l + I.l_off, c, d_alphas + I.a_off,
-                     d_means + I.m_off, d_qd + I.m_off, d_l + I.l_off, accumulate, sh,
-                     c * ixs * ixs, c * ixs, c);
+                     d_means + I.m_off, d_qd + I.m_off, d_l + I.l_off, accumulate, sh, c, c, c);
     return;
   }
   bwd_finalize_mom(part, (size_t)I.K * E, nch, w.a, I.K, I.D, I.DP, I.N, alphas + I.a_off,
@@ -629,8 +658,9 @@ PlanBuild build_plan(const int64_t* shapes, int64_t B, int32_t variant) {
     if (I.split) {
       I.xl_off = take(I.Npad * I.DP * es);
       I.Ql_off = take((int64_t)I.K * I.DP * I.DP * es);
+      I.ts_off = take(I.Npad / 64 * 4);
     }
-    I.sh_off = take((int64_t)(I.DP + 2) * 4);
+    I.sh_off = take((int64_t)(I.DP + 1) * 4);
     I.negc_off = take((int64_t)I.K * I.DP * 4);
     I.kappa_off = take((int64_t)I.K * 4);
     I.beta_off = take((int64_t)I.K * I.Npad * 4);
@@ -811,8 +841,8 @@ dex_status gmm_batched_fwd(const dex_desc& d, int cfg, const void* plan, const G
   char* cc = (char*)cache;
   char* w = (char*)ws;
   const bool split = d.variant == DEX_GMM_F16X3;
-  hipLaunchKernelGGL(k_bscale, dim3((unsigned)B), dim3(256), 0, st, pl, (const float*)in.x,
-                     (const float*)in.means, (const float*)in.qd, (const float*)in.l, cc);
+  hipLaunchKernelGGL(k_bscale, dim3((unsigned)B), dim3(256), 0, st, pl, (const float*)in.means,
+                     (const float*)in.qd, (const float*)in.l, cc);
   hipLaunchKernelGGL(k_bprep_x, dim3((unsigned)n_prepx), dim3(256), 0, st, pl, (const float*)in.x, cc);
   hipLaunchKernelGGL(k_bprep_q, dim3((unsigned)sumK), dim3(256), 0, st, pl, (const float*)in.alphas,
                      (const float*)in.means, (const float*)in.qd, (const float*)in.l, cc);

@@ -557,11 +557,13 @@ DEX_DEV void prep_q_comp(const float* __restrict__ alphas, const float* __restri
 // The wave builds Y^T (DP x 16*CB) = Q~_k X~^T - c~ from 16x16 tiles (row
 // block rb of Q, column block cb of points). A point's squared norm reduces
 // across the 4 lane groups, after which each lane owns one point and keeps its
-// running log-sum-exp over the k-range. With scaled operands the squared norm
-// is multiplied by sfac (the inverse square of the operands' scale product).
+// running log-sum-exp over the k-range. With scaled operands -c~ is multiplied
+// by cscale (the points' scale where it differs from the means') and the
+// squared norm by sfac (the inverse square of the operands' scale product).
 template <int DP, int PREC, int CB, int CK>
 DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0, int k0, int k1,
-                      float* __restrict__ beta, float2* __restrict__ ml, float sfac = 1.f) {
+                      float* __restrict__ beta, float2* __restrict__ ml, float sfac = 1.f,
+                      float cscale = 1.f) {
   using S = typename Store<PREC>::S;
   constexpr int NV = CK / 4;
   constexpr int NRB = DP / 16, NCH = DP / CK;
@@ -622,7 +624,7 @@ DEX_DEV void fwd_unit(const MfmaOps& ops, int N, int Npad, int p0, int k0, int k
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) acc[cb][rb] = cc[rb];
+      for (int cb = 0; cb < CB; ++cb) acc[cb][rb] = cc[rb] * cscale;
     int n = 0;
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb) {
