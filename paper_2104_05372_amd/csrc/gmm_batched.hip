@@ -350,10 +350,18 @@ DEX_DEV void prep_x_tile_split(const float* __restrict__ x, int N, int D, int Np
   __shared__ float red[4];
   __syncthreads();
   float v[NL], mx = 0.f;
+  // branch-free loads at clamped addresses, selected afterwards
+  float sv[NL];  // (the shift has DP entries, zero past D)
 #pragma unroll
   for (int r = 0; r < NL; ++r) {
     const int e = threadIdx.x + 256 * r, pp = e / DP, b = e % DP, p = p0 + pp;
-    v[r] = p < N && b < D ? x[(size_t)p * D + b] - shift[b] : 0.f;
+    v[r] = x[(size_t)min(p, N - 1) * D + min(b, D - 1)];
+    sv[r] = shift[b];
+  }
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int e = threadIdx.x + 256 * r, pp = e / DP, b = e % DP, p = p0 + pp;
+    v[r] = p < N && b < D ? v[r] - sv[r] : 0.f;
   }
 #pragma unroll
   for (int r = 0; r < NL; ++r) {

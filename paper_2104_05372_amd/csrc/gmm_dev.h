@@ -453,11 +453,21 @@ DEX_DEV void prep_x_tile(const float* __restrict__ x, int N, int D, int Npad, in
   __syncthreads();
   float mx = 0.f;
   float v[NL];
+  // branch-free: every load at a clamped, valid address, selected afterwards
+  // (a load under a branch would be waited for before the next is issued)
+  // (the shift has DP entries, zero past D)
+  float sv[NL];
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int e = threadIdx.x + 256 * r, pp = e / DP, b = e % DP, p = p0 + pp;
+    v[r] = x[(size_t)min(p, N - 1) * D + min(b, D - 1)];
+    sv[r] = shift ? shift[b] : 0.f;
+  }
 #pragma unroll
   for (int r = 0; r < NL; ++r) {
     const int e = threadIdx.x + 256 * r, pp = e / DP, b = e % DP, p = p0 + pp;
     const bool in = p < N && b < D;
-    v[r] = in ? (x[(size_t)p * D + b] - (shift ? shift[b] : 0.f)) * scale : 0.f;
+    v[r] = in ? (v[r] - sv[r]) * scale : 0.f;
   }
 #pragma unroll
   for (int r = 0; r < NL; ++r) {
