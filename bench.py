@@ -668,8 +668,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
     CHECK["on"] = not args.no_check
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path has no "
-              f"multi-GPU component in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library has "
+              f"no multi-GPU path", file=sys.stderr)
         return 2
     import torch
 
