@@ -30,7 +30,7 @@ struct BInst {
   int32_t nblk;       // Npad / 256
   int32_t split;      // forward operands in split FP16 (variant DEX_GMM_F16X3, D > 8)
   int64_t xl_off, ts_off, Ql_off;  // cache (bytes): split form: low parts, per-tile x scales
-  int64_t sh_off;     // cache (bytes): origin shift[DP], then the factor scale
+  int64_t sh_off;     // cache (bytes): origin shift[DP], the factor scale, max |mu - shift|
 };
 
 struct BItem {
@@ -304,7 +304,9 @@ DEX_DEV void bwd_unit_valu(const float* __restrict__ xh, int N, int Npad, int K,
 // means (every operand is taken about it, so data far from the origin loses
 // nothing to cancellation: only x - mu enters). Split instances also get the
 // power of two that brings the largest factor entry (exp(qd) or |l|) to
-// [2^13, 2^14); the points are scaled per 64-point tile in the preparation.
+// [2^13, 2^14), and the largest |mu_k - shift|, which bounds every tile's
+// point scale (the points are scaled per 64-point tile in the preparation):
+// scaled means then stay inside the FP16 range in every tile.
 __global__ void __launch_bounds__(256) k_bscale(const char* __restrict__ plan,
                                                 const float* __restrict__ means,
                                                 const float* __restrict__ qd,
@@ -312,35 +314,44 @@ __global__ void __launch_bounds__(256) k_bscale(const char* __restrict__ plan,
   const PlanHeader* h = hdr(plan);
   const BInst I = ((const BInst*)(plan + h->inst_off))[blockIdx.x];
   __shared__ float csh[64];
-  __shared__ float red[4];
+  __shared__ float red[8];
   block_shift(means + I.m_off, I.K, I.D, csh);
   const int t = threadIdx.x;
   float* sh = (float*)(cache + I.sh_off);
   if (t < I.DP) sh[t] = csh[t];
   if (!I.split) {
-    if (t == 0) sh[I.DP] = 1.f;
+    if (t == 0) sh[I.DP] = sh[I.DP + 1] = 1.f;
     return;
   }
-  float mq = 0.f;
+  float mq = 0.f, mm = 0.f;
   const int64_t nd = (int64_t)I.K * I.D, nl = (int64_t)I.K * I.D * (I.D - 1) / 2;
-  for (int64_t e = t; e < nd; e += 256) mq = fmaxf(mq, expf(qd[I.m_off + e]));
+  for (int64_t e = t; e < nd; e += 256) {
+    mq = fmaxf(mq, expf(qd[I.m_off + e]));
+    mm = fmaxf(mm, fabsf(means[I.m_off + e] - csh[(int)(e % I.D)]));
+  }
   for (int64_t e = t; e < nl; e += 256) mq = fmaxf(mq, fabsf(l[I.l_off + e]));
   mq = wave_max(mq);
-  if ((t & 63) == 0) red[t >> 6] = mq;
+  mm = wave_max(mm);
+  if ((t & 63) == 0) {
+    red[t >> 6] = mq;
+    red[4 + (t >> 6)] = mm;
+  }
   __syncthreads();
   if (t == 0) {
     mq = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
     int eq = 0;
     if (mq > 0.f && mq <= 3.0e38f) (void)frexpf(mq, &eq);
     sh[I.DP] = ldexpf(1.f, 14 - eq);
+    sh[I.DP + 1] = fmaxf(fmaxf(red[4], red[5]), fmaxf(red[6], red[7]));
   }
 }
 
 // Split form, one 64-point tile: x - shift in FP32 for the reverse (x~^T, as in
-// the FP32 form) and, scaled by the power of two that brings the tile's largest
-// |x - shift| to [2^13, 2^14), in split FP16 for the forward (row layout); the
-// tile's scale goes to ts[p0 / 64]. (256 threads; the loads are all issued
-// before the first is used.)
+// the FP32 form) and, scaled by the power of two that brings the larger of the
+// tile's largest |x - shift| and the instance's largest |mu - shift| (shift[DP
+// + 1]) to [2^13, 2^14), in split FP16 for the forward (row layout); the tile's
+// scale goes to ts[p0 / 64]. (256 threads; the loads are all issued before the
+// first is used.)
 template <int DP>
 DEX_DEV void prep_x_tile_split(const float* __restrict__ x, int N, int D, int Npad, int p0,
                                const float* __restrict__ shift, _Float16* xh, _Float16* xl,
@@ -372,7 +383,7 @@ DEX_DEV void prep_x_tile_split(const float* __restrict__ x, int N, int D, int Np
   mx = wave_max(mx);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
-  mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  mx = fmaxf(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])), shift[DP + 1]);
   int ex = 0;
   if (mx > 0.f && mx <= 3.0e38f) (void)frexpf(mx, &ex);
   const float sc = ldexpf(1.f, 14 - ex);
@@ -668,7 +679,7 @@ PlanBuild build_plan(const int64_t* shapes, int64_t B, int32_t variant) {
       I.Ql_off = take((int64_t)I.K * I.DP * I.DP * es);
       I.ts_off = take(I.Npad / 64 * 4);
     }
-    I.sh_off = take((int64_t)(I.DP + 1) * 4);
+    I.sh_off = take((int64_t)(I.DP + 2) * 4);
     I.negc_off = take((int64_t)I.K * I.DP * 4);
     I.kappa_off = take((int64_t)I.K * 4);
     I.beta_off = take((int64_t)I.K * I.Npad * 4);

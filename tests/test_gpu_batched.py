@@ -132,6 +132,22 @@ def test_shifted_and_rescaled_data(dev, offset, scale, variant):
     check_instances(shapes, insts, got, range(len(insts)))
 
 
+def test_split_fp16_points_at_the_origin_shift(dev):
+    """A tile whose points sit (almost) on the origin shift while the means are
+    spread: a tile scale taken from the points alone would blow the scaled
+    offsets -c~ out of range. The scale is bounded by the means' spread."""
+    from paper_2104_05372_amd import dex
+    shapes = np.array([[600, 16, 12], [700, 24, 9]], np.int64)
+    insts = []
+    for g, (N, D, K) in zip(workloads.batched_inputs(shapes, seed=61), shapes):
+        c = np.mean(g.means[:min(K, 16)].astype(np.float32), axis=0, dtype=np.float32)
+        x = g.x.copy()
+        x[:128] = c + np.float32(1e-12) * g.x[:128]
+        insts.append(workloads.GMMInputs(g.alphas, g.means, g.qd, g.l, x).astype(np.float32))
+    got = run_batched(shapes, insts, variant=dex.DEX_GMM_F16X3)
+    check_instances(shapes, insts, got, range(len(insts)))
+
+
 def test_per_instance_cotangents(dev):
     shapes, insts = small_batch()
     ct = np.linspace(-2, 2, len(insts)).astype(np.float32)
