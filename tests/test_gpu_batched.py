@@ -148,6 +148,31 @@ def test_split_fp16_points_at_the_origin_shift(dev):
     check_instances(shapes, insts, got, range(len(insts)))
 
 
+@pytest.mark.parametrize("variant", [0, 3])
+def test_accumulate_into_gradients(dev, variant):
+    """DEX_ACCUMULATE adds the batch's gradients to what the buffers hold: a
+    second reverse call into the first call's output gives twice the gradient."""
+    from paper_2104_05372_amd import dex
+    shapes, insts = small_batch()
+    d, plan = dex.dex_gmm_batched_plan(shapes, variant)
+    packed = [torch.tensor(a, device=dev) for a in workloads.pack_batched(insts)]
+    ins = [torch.tensor(plan, device=dev), *packed]
+    B = shapes.shape[0]
+    F = torch.empty(B, device=dev)
+    f = torch.empty(int(d.dims[1]), device=dev)
+    cache = torch.empty(int(d.dims[7]), dtype=torch.uint8, device=dev)
+    ws = dex.workspace(dex.dex_workspace_bytes(d, dex.DEX_WS_FWD), dev)
+    ct = torch.ones(B, device=dev)
+    dex.dex_fwd(d, ins, [F], [f, cache], ws)
+    once = [torch.empty_like(p) for p in packed[:4]]
+    dex.dex_vjp(d, ins, [f, cache], [ct], once, 0, ws)
+    twice = [g.clone() for g in once]
+    dex.dex_vjp(d, ins, [f, cache], [ct], twice, dex.DEX_ACCUMULATE, ws)
+    torch.cuda.synchronize()
+    for a, b in zip(once, twice):
+        assert torch.allclose(2 * a, b, rtol=1e-6, atol=0), variant
+
+
 def test_per_instance_cotangents(dev):
     shapes, insts = small_batch()
     ct = np.linspace(-2, 2, len(insts)).astype(np.float32)
