@@ -427,6 +427,8 @@ def row_batched(torch, dex, workloads, dev, steps):
     for k in ("bgmm_fwd", "bgmm_vjp"):
         a = res_s[k]["tflops"]
         res_s[k]["frac_fp16_over_3"] = round(a / (PEAK["bf16"] / 3), 4)
+    res_s["products"] = ("D > 8: forward on split FP16 operands (hi*hi + hi*lo + lo*hi, FP32 "
+                         "accumulation, power-of-two scaled), reverse FP32 moments; D <= 8 as FP32")
     res["split_fp16"] = res_s
     if not CHECK["on"]:
         return res
