@@ -611,12 +611,12 @@ __global__ void __launch_bounds__(256) k_bbwd_finalize(const char* __restrict__ 
     // moments of x - shift without the cotangent
     const float* sh = (const float*)(cache + I.sh_off);
     const float c = ct[w.inst];
-    bwd_finalize_mom(part, (size_t)I.K * E, nch, w.a, I.K, I.D, I.DP, I.N, alphas + I.a_off,
+    bwd_finalize_mom<32>(part, (size_t)I.K * E, nch, w.a, I.K, I.D, I.DP, I.N, alphas + I.a_off,
                      means + I.m_off, qd + I.m_off, l + I.l_off, c, d_alphas + I.a_off,
                      d_means + I.m_off, d_qd + I.m_off, d_l + I.l_off, accumulate, sh, c, c, c);
     return;
   }
-  bwd_finalize_mom(part, (size_t)I.K * E, nch, w.a, I.K, I.D, I.DP, I.N, alphas + I.a_off,
+  bwd_finalize_mom<32>(part, (size_t)I.K * E, nch, w.a, I.K, I.D, I.DP, I.N, alphas + I.a_off,
                    means + I.m_off, qd + I.m_off, l + I.l_off, ct[w.inst], d_alphas + I.a_off,
                    d_means + I.m_off, d_qd + I.m_off, d_l + I.l_off, accumulate,
                    (const float*)(cache + I.sh_off));

@@ -1292,6 +1292,7 @@ DEX_DEV void bwd_mom_unit(const void* xT_hi, const void* xT_lo, int N, int Npad,
 // summed second moments, first moments and weight sum are multiplied by m2, m1
 // and m0 (the undoing of a scaled form's operand scales and a cotangent left
 // out of its weights).
+template <int DPM = 64>
 DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, int S, int k, int K,
                               int D, int DP, int64_t N, const float* __restrict__ alphas,
                               const float* __restrict__ means, const float* __restrict__ qd,
@@ -1302,9 +1303,14 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
                               float m1 = 1.f, float m0 = 1.f) {
   // Called with 256 threads. C is symmetric; QT holds Q transposed (row
   // stride 68 floats keeps 16-byte rows aligned for vector reads).
-  __shared__ __attribute__((aligned(16))) float C[64][65];
-  __shared__ __attribute__((aligned(16))) float QT[64][68];
-  __shared__ float us[64], mus[64], vq[64], bq[64], Ash;
+  // DPM: the largest DP the caller passes (LDS and registers are sized for it)
+  static_assert(DPM == 32 || DPM == 64, "assembly sized for DP <= 32 or <= 64");
+  constexpr int NBM = DPM / 16, NBLKM = NBM * (NBM + 1) / 2;
+  constexpr int NPV = (NBLKM * 256 + DPM + 1 + 255) / 256;  // slot elements per thread
+  constexpr int NQV = DPM * DPM / 256;                       // Q elements per thread
+  __shared__ __attribute__((aligned(16))) float C[DPM][DPM + 1];
+  __shared__ __attribute__((aligned(16))) float QT[DPM][DPM + 4];
+  __shared__ float us[DPM], mus[DPM], vq[DPM], bq[DPM], Ash;
   const int NB = DP / 16, NBLK = NB * (NB + 1) / 2;
   const int L = D * (D - 1) / 2;
   const int t = threadIdx.x;
@@ -1333,30 +1339,30 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
     return s + err;
   };
   __shared__ float red[8];
-  __shared__ float Ps[10 * 256 + 64 + 4];  // summed slot: S blocks, u, A
+  __shared__ float Ps[NBLKM * 256 + DPM + 4];  // summed slot: S blocks, u, A
   // Every global input is loaded first, each thread's loads issued together,
   // so the block waits for memory once instead of once per phase.
   const int NE = NBLK * 256 + DP + 1;
-  float pv[11], qv[16], av[4];
+  float pv[NPV], qv[NQV], av[4];
   if (S == 1) {  // one slot (already reduced): plain loads, issued together
 #pragma unroll
-    for (int i = 0; i < 11; ++i) {
+    for (int i = 0; i < NPV; ++i) {
       const int e = t + 256 * i;
       pv[i] = e < NE ? part[e] : 0.f;
     }
   } else if (S <= 8) {
     // up to 8 slots (the batched launch's point chunks): every load of the
-    // thread's 11 elements issued before the first sum, then the same
+    // thread's NPV elements issued before the first sum, then the same
     // fixed-order compensated sums
-    float v[11][8];
+    float v[NPV][8];
 #pragma unroll
-    for (int i = 0; i < 11; ++i) {
+    for (int i = 0; i < NPV; ++i) {
       const int e = t + 256 * i;
 #pragma unroll
       for (int u = 0; u < 8; ++u) v[i][u] = u < S && e < NE ? part[(size_t)u * sstride + e] : 0.f;
     }
 #pragma unroll
-    for (int i = 0; i < 11; ++i) {
+    for (int i = 0; i < NPV; ++i) {
       float sm = 0.f, err = 0.f;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -1371,7 +1377,7 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < 11; ++i) {
+    for (int i = 0; i < NPV; ++i) {
       const int e = t + 256 * i;
       pv[i] = e < NE ? comp_sum((size_t)e) : 0.f;
     }
@@ -1386,10 +1392,10 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
     // with D = 1 there is no strict lower part (L = 0, l may be empty): the
     // unused load then reads qd instead
     const float* lsrc = L > 0 ? l + (size_t)k * L : qd + (size_t)k * D;
-    float dv[16], lv[16];
-    int sel[16];  // 0: zero, 1: diagonal, 2: strict lower
+    float dv[NQV], lv[NQV];
+    int sel[NQV];  // 0: zero, 1: diagonal, 2: strict lower
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < NQV; ++i) {
       const int e = t + 256 * i;
       const bool in = e < D * D;
       sel[i] = !in ? 0 : a == b ? 1 : a > b ? 2 : 0;
@@ -1403,7 +1409,7 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
       }
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < NQV; ++i) {
       const float ev = expf(dv[i]);
       qv[i] = sel[i] == 1 ? ev : sel[i] == 2 ? lv[i] : 0.f;
     }
@@ -1419,19 +1425,19 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
   for (int j = t + 1024; j < K; j += 256) am = fmaxf(am, alphas[j]);
   am = wave_max(am);
 #pragma unroll
-  for (int i = 0; i < 11; ++i) {
+  for (int i = 0; i < NPV; ++i) {
     const int e = t + 256 * i;
     pv[i] *= e < NBLK * 256 ? m2 : e < NBLK * 256 + DP ? m1 : m0;
     if (e < NE) Ps[e] = pv[i];
   }
   // QT and C: rows and columns past D stay zero
-  for (int e = t; e < 64 * 68; e += 256) (&QT[0][0])[e] = 0.f;
-  for (int e = t; e < 64 * 65; e += 256) (&C[0][0])[e] = 0.f;
+  for (int e = t; e < DPM * (DPM + 4); e += 256) (&QT[0][0])[e] = 0.f;
+  for (int e = t; e < DPM * (DPM + 1); e += 256) (&C[0][0])[e] = 0.f;
   if ((t & 63) == 0) red[t >> 6] = am;
   if (t < D) mus[t] = mu_t;
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
+  for (int i = 0; i < NQV; ++i) {
     const int e = t + 256 * i;
     if (e < D * D) QT[e % D][e / D] = qv[i];
   }
@@ -1452,16 +1458,16 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
     // thread's entry of block q = (ab, bb) is pv[q] (element t of the block),
     // at row r = 16 bb + (t/4 % 16) and column s = 16 ab + 4 (t/64) + t % 4
     const int rl = (t >> 2) & 15, sl = 4 * (t >> 6) + (t & 3);
-    float ur[4], mr[4], usv[4], msv[4];
+    float ur[NBM], mr[NBM], usv[NBM], msv[NBM];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < NBM; ++j) {
       ur[j] = us[16 * j + rl];
       mr[j] = mus[16 * j + rl];
       usv[j] = us[16 * j + sl];
       msv[j] = mus[16 * j + sl];
     }
 #pragma unroll
-    for (int q = 0; q < 10; ++q) {
+    for (int q = 0; q < NBLKM; ++q) {
       const int ab = q < 1 ? 0 : q < 3 ? 1 : q < 6 ? 2 : 3;
       const int bb = q - ab * (ab + 1) / 2;
       const int r = 16 * bb + rl, s2 = 16 * ab + sl;
@@ -1478,21 +1484,21 @@ DEX_DEV void bwd_finalize_mom(const float* __restrict__ part, size_t sstride, in
   // the contraction runs over cc < 16w + 16, four at a time. Lane 16g + c
   // supplies A = Q[16w + c][cc + g] and B = C[cc + g][16n + c], and holds
   // M[16w + 4g + i][16n + c]. Entries past D are zero in QT and C.
-  {
+  if (DPM == 64 || 16 * (t >> 6) < DPM) {  // (256 threads: waves past DPM / 16 have no rows)
     const int w = t >> 6, lane = t & 63, c = lane & 15, g = lane >> 4;
     const int ce = min(DP, 16 * w + 16);
-    f32x4 mt[4];
+    f32x4 mt[NBM];
 #pragma unroll
-    for (int n = 0; n < 4; ++n) mt[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int n = 0; n < NBM; ++n) mt[n] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
     for (int cc = 0; cc < ce; cc += 4) {
       const float qa = QT[cc + g][16 * w + c];
 #pragma unroll
-      for (int n = 0; n < 4; ++n)
+      for (int n = 0; n < NBM; ++n)
         mt[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa, C[cc + g][16 * n + c], mt[n], 0, 0, 0);
     }
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {
+    for (int n = 0; n < NBM; ++n) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int a = 16 * w + 4 * g + i, b = 16 * n + c;
